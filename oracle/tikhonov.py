@@ -1,0 +1,95 @@
+"""Tikhonov regularisation of the circulant-embedded operator.
+
+Oracle (test infrastructure only).
+
+The regularising algorithm R_alpha of Sec. 3 (family of Eq. (11)) is Tikhonov's
+method, named in Sec. 4 as admissible for Algorithm 1.  Here it is applied to
+the circulant embedding C of the discretised operator on the zero-padded P^3
+box (the three-axis analogue of the paper's per-frequency systems, Eq. (14)):
+
+    zeta_pad(alpha) = argmin_u ||C u - E_Y F||^2 + alpha_abs ||u||^2,
+    zeta(alpha)     = zeta_pad restricted to R's index block [0,n)^3,
+    r(alpha)        = (C zeta_pad - E_Y F) restricted to Y's index block,
+
+with alpha_abs = alpha * max |k^|^2 (alpha is relative to the squared operator
+norm of C, so one alpha range serves every grid and kernel).
+
+``dense_tikhonov`` solves the normal equations (C^T C + alpha_abs I) u = C^T E_Y F
+with C assembled as a matrix and a Cholesky factorisation -- no transform.
+``solve_spectral`` is the same minimiser through the DFT, where C is diagonal:
+u^ = conj(k^) f^ / (|k^|^2 + alpha_abs).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from .geometry import Geom
+from .operator import pad
+
+
+def kernel_spectrum(k):
+    """k^ = DFT3(k) (FP64), s = |k^|^2 and s_max."""
+    khat = np.fft.fftn(k)
+    s = (khat * khat.conj()).real
+    return khat, s, float(s.max())
+
+
+def spectral_filter(khat, fhat, alpha_abs: float):
+    """Minimiser and residual spectra on the whole box for box data with spectrum f^:
+    u^ = conj(k^) f^ / (s + a) and (C u - f)^ = k^ u^ - f^ = -a f^ / (s + a)."""
+    s = (khat * khat.conj()).real
+    return khat.conj() * fhat / (s + alpha_abs), -alpha_abs * fhat / (s + alpha_abs)
+
+
+def solve_box(khat, f_box, alpha_rel: float):
+    """Tikhonov minimiser for data given on the whole P^3 box (no restriction)."""
+    a = float(alpha_rel) * float((khat * khat.conj()).real.max())
+    uhat, rhat = spectral_filter(khat, np.fft.fftn(f_box), a)
+    return np.fft.ifftn(uhat), np.fft.ifftn(rhat)
+
+
+def solve_spectral(g: Geom, khat, F, alpha_rel: float):
+    """Tikhonov estimate at relative alpha; returns zeta on R, r on Y and their norms."""
+    s = (khat * khat.conj()).real
+    a = float(alpha_rel) * float(s.max())
+    fhat = np.fft.fftn(pad(g, np.asarray(F, dtype=np.float64)))
+    uhat, rhat = spectral_filter(khat, fhat, a)
+    zpad = np.fft.ifftn(uhat)
+    rpad = np.fft.ifftn(rhat)
+    n = g.shape
+    zeta = zpad.real[: n[0], : n[1], : n[2]]
+    r = rpad.real[: n[0], : n[1], : n[2]]
+    return dict(
+        zeta=zeta, r=r, alpha_abs=a,
+        zeta_norm=float(np.sqrt(np.sum(zeta * zeta))),
+        r_norm=float(np.sqrt(np.sum(r * r))),
+        r_full=float(np.sqrt(np.sum(rpad.real ** 2))),
+        imag_max=float(max(np.abs(zpad.imag).max(), np.abs(rpad.imag).max())),
+    )
+
+
+def circulant_matrix(k):
+    """C[p, q] = k[(p - q) mod P] over the flattened P^3 box (x fastest)."""
+    P = k.shape
+    n = k.size
+    C = np.empty((n, n))
+    col = 0
+    for qz in range(P[0]):
+        for qy in range(P[1]):
+            for qx in range(P[2]):
+                C[:, col] = np.roll(k, (qz, qy, qx), axis=(0, 1, 2)).ravel()
+                col += 1
+    return C
+
+
+def dense_tikhonov(g: Geom, k, F, alpha_abs: float):
+    """Normal-equation solve with an explicit matrix (P^3 <= ~4096 unknowns)."""
+    C = circulant_matrix(k)
+    f = pad(g, np.asarray(F, dtype=np.float64)).ravel()
+    A = C.T @ C + alpha_abs * np.eye(C.shape[0])
+    u = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), C.T @ f)
+    res = (C @ u - f).reshape(k.shape)
+    u = u.reshape(k.shape)
+    n = g.shape
+    return dict(zeta_pad=u, zeta=u[: n[0], : n[1], : n[2]], r=res[: n[0], : n[1], : n[2]], r_full=res)

@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a closed
+form, a textbook identity, a direct sum, a dense solve, or a value the
+paper's model example fixes.  None of these tests touches the GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dft, discrepancy, features, mlp, recovery, synth, tikhonov
+from oracle.geometry import Geom, kernel_dz, kernel_inv, sample_kernel, sources, v0
+from oracle.operator import circulant_apply, forward_circulant, forward_direct, offset_table, pad
+from paper_1703_01216_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- DFT (definition)
+
+@pytest.mark.parametrize("p", [2, 3, 4, 6, 8, 12, 16])
+def test_dft_matrix_on_pure_tones(p):
+    # The DFT of exp(+2 pi i m j / P) is P at k = m and 0 elsewhere (orthogonality).
+    j = np.arange(p)
+    for m in range(p):
+        x = np.exp(2j * np.pi * m * j / p)
+        X = dft.dft_matrix(p) @ x
+        ref = np.zeros(p, complex)
+        ref[m] = p
+        assert np.max(np.abs(X - ref)) < 1e-12 * p
+
+
+def test_dft_delta_and_constant():
+    p = 12
+    d = np.zeros(p)
+    d[0] = 1.0
+    assert np.allclose(dft.dft_matrix(p) @ d, np.ones(p), atol=1e-15)
+    assert np.allclose(dft.dft_matrix(p) @ np.ones(p), np.eye(p)[0] * p, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (6, 4, 8), (3, 6, 2)])
+def test_dft3_full_separable_numpy_agree(shape):
+    x = inputs.rng(1).standard_normal(shape) + 1j * inputs.rng(2).standard_normal(shape)
+    full = dft.dft3_full(x)
+    sep = dft.dft3(x)
+    ref = np.fft.fftn(x)
+    scale = np.abs(full).max()
+    assert np.max(np.abs(full - sep)) < 1e-13 * scale
+    assert np.max(np.abs(full - ref)) < 1e-13 * scale
+    back = dft.dft3_full(full, inverse=True)
+    assert np.max(np.abs(back - x)) < 1e-13 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 24, 8), (6, 18, 32)])
+def test_numpy_fft_against_separable_sums(shape):
+    # numpy.fft serves the oracle only after this check against the sums (radices 2 and 3).
+    x = inputs.rng(3).standard_normal(shape)
+    sep = dft.dft3(x)
+    ref = np.fft.fftn(x)
+    assert np.max(np.abs(sep - ref)) < 1e-13 * np.abs(ref).max()
+    inv = dft.dft3(ref, inverse=True)
+    assert np.max(np.abs(inv - x)) < 1e-13 * np.abs(x).max()
+
+
+def test_parseval():
+    # Plancherel (Sec. 4, Lemma 1), discrete form: sum |x|^2 = P^-3 sum |X|^2.
+    x = inputs.rng(4).standard_normal((8, 12, 6))
+    X = dft.dft3(x)
+    assert abs(np.sum(x * x) - np.sum(np.abs(X) ** 2) / x.size) < 1e-12 * np.sum(x * x)
+
+
+# ---------------------------------------------------------------- kernel (Sec. 3, Eq. (8))
+
+def test_kernel_closed_values():
+    # On the axis K(0,0,z) = -1/z^2; K is odd in z; even in x and y.
+    for z in (0.5, 1.0, 3.0, 40.0):
+        assert kernel_dz(0.0, 0.0, z) == pytest.approx(-1.0 / z ** 2, rel=1e-15)
+        assert kernel_inv(0.0, 0.0, z) == pytest.approx(1.0 / z, rel=1e-15)
+    # 3-4-12 triangle: |x| = 13, K = -12 / 13^3.
+    assert kernel_dz(3.0, 4.0, 12.0) == pytest.approx(-12.0 / 2197.0, rel=1e-15)
+    assert kernel_dz(-3.0, 4.0, 12.0) == kernel_dz(3.0, -4.0, 12.0) == kernel_dz(3.0, 4.0, 12.0)
+    assert kernel_dz(3.0, 4.0, -12.0) == -kernel_dz(3.0, 4.0, 12.0)
+
+
+def test_kernel_is_z_derivative_of_inverse_distance():
+    # K = d/dz (1/|x|) (Sec. 2, Eq. (6) kernel) -- central difference check.
+    x, y, z, e = 1.3, -0.7, 5.1, 1e-5
+    fd = (kernel_inv(x, y, z + e) - kernel_inv(x, y, z - e)) / (2 * e)
+    assert kernel_dz(x, y, z) == pytest.approx(fd, rel=1e-8)
+
+
+@pytest.mark.parametrize("n,nz,D,h", [(8, 4, 6, 1.0), (6, 5, 7.5, 0.5)])
+def test_sampled_table_values_and_symmetry(n, nz, D, h):
+    g = Geom(n, n + 2, nz, h=h, D=D)
+    k = sample_kernel(g)
+    pz, py, px = g.pshape
+    # slot a = n (P = 2n) is zero on every axis
+    assert np.all(k[nz, :, :] == 0) and np.all(k[:, n + 2, :] == 0) and np.all(k[:, :, n] == 0)
+    # value at (a, b, c) = (2, P-3, P-1): offsets (2, -3, -1)
+    zz = (D - 1) * h
+    ref = h ** 3 * (-zz) / ((2 * h) ** 2 + (3 * h) ** 2 + zz ** 2) ** 1.5
+    assert k[pz - 1, py - 3, 2] == pytest.approx(ref, rel=1e-14)
+    # even in the lateral offsets: k[c, b, a] = k[c, P-b, P-a]
+    assert np.array_equal(k[:, :, 1:], k[:, :, 1:][:, :, ::-1])
+    assert np.array_equal(k[:, 1:, :], k[:, 1:, :][:, ::-1, :])
+
+
+@pytest.mark.parametrize("n,nz,D", [(16, 4, 8), (32, 4, 10)])
+def test_lateral_sum_is_minus_solid_angle(n, nz, D):
+    # The lateral integral of K at height z over [-a,a]x[-b,b] is minus the solid
+    # angle of that rectangle seen from height z, 4 atan(ab / (z sqrt(a^2+b^2+z^2))).
+    # The table's lateral midpoint sum covers a = b = (n - 1/2) h.
+    g = Geom(n, n, nz, D=D)
+    k = sample_kernel(g)
+    for c in range(g.pshape[0]):
+        if c == nz:
+            continue
+        z = g.d + (c if c < nz else c - g.pshape[0])
+        a = n - 0.5
+        om = 4 * math.atan(a * a / (z * math.sqrt(2 * a * a + z * z)))
+        assert k[c].sum() == pytest.approx(-om, rel=1e-3)
+
+
+def test_lateral_transform_closed_form():
+    # 2D Fourier transform in (x,y) of K (Sec. 3, step to Eq. (9)) with kernel
+    # e^{-i w.x}: K~(w, z) = -2 pi exp(-|w| z) for z > 0.  Truncation to the
+    # lateral box of half-width L costs O(z/L).
+    g = Geom(64, 64, 2, D=3)
+    k = sample_kernel(g)
+    P = g.pshape
+    k2 = np.fft.fft2(k, axes=(1, 2))
+    for c in (0, 1, 3):
+        z = g.d + (c if c < g.nz else c - P[0])
+        for (my, mx) in ((0, 1), (1, 1), (0, 4), (3, 4), (5, 12)):
+            w = 2 * math.pi * math.hypot(mx / P[2], my / P[1])
+            ref = -2 * math.pi * math.exp(-w * z)
+            assert abs(k2[c, my, mx] - ref) < 1e-2 * abs(ref)
+
+
+def test_kernel_spectrum_symmetry():
+    # k even in x, y and real: s = |k^|^2 is even in every frequency; k^(kx,ky,-kz) = conj k^.
+    g = Geom(6, 8, 4)
+    khat, s, smax = tikhonov.kernel_spectrum(sample_kernel(g))
+    rz = (-np.arange(g.pshape[0])) % g.pshape[0]
+    ry = (-np.arange(g.pshape[1])) % g.pshape[1]
+    rx = (-np.arange(g.pshape[2])) % g.pshape[2]
+    assert np.allclose(khat, khat[:, ry, :], atol=1e-13 * np.sqrt(smax))
+    assert np.allclose(khat, khat[:, :, rx], atol=1e-13 * np.sqrt(smax))
+    assert np.allclose(khat[rz, :, :], khat.conj(), atol=1e-13 * np.sqrt(smax))
+    assert smax == s.max()
+
+
+# ---------------------------------------------------------------- forward operator (Eq. (8))
+
+@pytest.mark.parametrize("shape,D,kind", [((6, 6, 6), None, 0), ((4, 5, 7), 6.5, 0), ((5, 5, 4), None, 1)])
+def test_forward_direct_equals_circulant(shape, D, kind):
+    # Convolution theorem on the zero-padded box vs the direct quadrature sum,
+    # which evaluates K at cell-centre differences with no table and no wrap.
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz, D=D, kind=kind)
+    zeta = inputs.rng(5).standard_normal(shape)
+    a = forward_direct(g, zeta)
+    b = forward_circulant(g, zeta)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.abs(a).max()
+
+
+@pytest.mark.slow
+def test_forward_direct_equals_circulant_n32():
+    g = Geom(32, 32, 32)
+    inst = inputs.workload_instance(1, 0)
+    zeta = inst["xi"] * v0(g)
+    a = forward_direct(g, zeta)
+    b = forward_circulant(g, zeta)
+    assert np.linalg.norm(a - b) < 1e-13 * np.linalg.norm(a)
+
+
+def test_offset_table_matches_wrapped_table():
+    g = Geom(5, 4, 3, D=4.25)
+    T = offset_table(g)
+    k = sample_kernel(g)
+    for dz in range(-2, 3):
+        for dy in range(-3, 4):
+            for dx in range(-4, 5):
+                assert T[dz + 2, dy + 3, dx + 4] == k[dz % 6, dy % 8, dx % 10]
+
+
+def test_circulant_direct_vs_fft():
+    rg = inputs.rng(6)
+    k = rg.standard_normal((4, 6, 4))
+    u = rg.standard_normal((4, 6, 4))
+    a = circulant_apply(k, u)
+    b = np.fft.ifftn(np.fft.fftn(k) * np.fft.fftn(u)).real
+    assert np.max(np.abs(a - b)) < 1e-13 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------- Tikhonov (Sec. 3-4)
+
+@pytest.mark.parametrize("shape,alpha", [((4, 4, 4), 1e-3), ((3, 4, 6), 1e-5), ((6, 6, 6), 1e-2)])
+def test_dense_normal_equations_equal_spectral(shape, alpha):
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz)
+    k = sample_kernel(g)
+    khat, s, smax = tikhonov.kernel_spectrum(k)
+    F = inputs.rng(7).standard_normal(shape)
+    sp = tikhonov.solve_spectral(g, khat, F, alpha)
+    de = tikhonov.dense_tikhonov(g, k, F, alpha * smax)
+    assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-10 * np.linalg.norm(de["zeta"])
+    assert np.linalg.norm(sp["r"] - de["r"]) < 1e-10 * np.linalg.norm(de["r"])
+    assert sp["r_full"] == pytest.approx(np.linalg.norm(de["r_full"]), rel=1e-10)
+    assert sp["imag_max"] < 1e-12 * np.abs(sp["zeta"]).max()
+
+
+@pytest.mark.parametrize("alpha", [1e-10, 1e-7, 1e-4])
+def test_near_exact_recovery_of_band_limited_zeta(alpha):
+    # Circulant model, full-box data f = C zeta with zeta^ supported where
+    # s >= 1e-3 s_max: the estimate's error spectrum is exactly
+    # -a/(s+a) zeta^, so ||err|| / ||zeta|| <= alpha / (1e-3 + alpha).
+    g = Geom(8, 8, 8)
+    k = sample_kernel(g)
+    khat, s, smax = tikhonov.kernel_spectrum(k)
+    z = inputs.rng(8).standard_normal(g.pshape)
+    zh = np.fft.fftn(z) * (s >= 1e-3 * smax)
+    zeta = np.fft.ifftn(zh).real
+    f = np.fft.ifftn(khat * np.fft.fftn(zeta)).real
+    est, _ = tikhonov.solve_box(khat, f, alpha)
+    err = np.linalg.norm(est.real - zeta) / np.linalg.norm(zeta)
+    assert err <= alpha / (1e-3 + alpha) * (1 + 1e-6) + 1e-13
+
+
+def test_theorem1_error_decreases_with_noise():
+    # Circulant model: with alpha chosen by the discrepancy principle the error
+    # decreases as delta decreases (Theorem 1, qualitative).
+    g = Geom(8, 8, 8)
+    k = sample_kernel(g)
+    khat, s, smax = tikhonov.kernel_spectrum(k)
+    zeta = np.fft.ifftn(np.fft.fftn(inputs.rng(9).standard_normal(g.pshape)) * (s >= 1e-4 * smax)).real
+    f0 = np.fft.ifftn(khat * np.fft.fftn(zeta)).real
+    e = inputs.rng(10).standard_normal(g.pshape)
+    errs = []
+    for rel in (1e-1, 1e-2, 1e-3, 1e-4):
+        ee = e * rel * np.linalg.norm(f0) / np.linalg.norm(e)
+        f = f0 + ee
+        delta = np.linalg.norm(ee)
+
+        def ev(a):
+            u, r = tikhonov.solve_box(khat, f, a)
+            return np.linalg.norm(r.real), np.linalg.norm(u.real)
+        res = discrepancy.bisection(ev, delta, lo=-14)
+        u, _ = tikhonov.solve_box(khat, f, res["alpha"])
+        errs.append(np.linalg.norm(u.real - zeta) / np.linalg.norm(zeta))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+
+
+def test_full_box_residual_and_norm_monotone():
+    g = Geom(6, 6, 6)
+    khat, s, smax = tikhonov.kernel_spectrum(sample_kernel(g))
+    F = inputs.rng(11).standard_normal(g.shape)
+    ts = np.linspace(-8, 0, 33)
+    rf = [tikhonov.solve_spectral(g, khat, F, 10 ** t)["r_full"] for t in ts]
+    zn = []
+    for t in ts:
+        u, _ = tikhonov.solve_box(khat, pad(g, F), 10 ** t)
+        zn.append(np.linalg.norm(u.real))
+    assert all(rf[i + 1] > rf[i] for i in range(len(rf) - 1))
+    assert all(zn[i + 1] < zn[i] for i in range(len(zn) - 1))
+
+
+# ---------------------------------------------------------------- discrepancy rule
+
+def _identity_problem(delta_frac, n=4):
+    # k = delta_0: k^ = 1, s = 1, alpha_abs = alpha; zeta = F/(1+alpha),
+    # r = -alpha F/(1+alpha), so ||r|| = delta at alpha* = delta / (||F|| - delta).
+    g = Geom(n, n, n)
+    k = np.zeros(g.pshape)
+    k[0, 0, 0] = 1.0
+    khat = np.fft.fftn(k)
+    F = inputs.rng(12).standard_normal(g.shape)
+    Fn = np.linalg.norm(F)
+    delta = delta_frac * Fn
+
+    def ev(a):
+        out = tikhonov.solve_spectral(g, khat, F, a)
+        return out["r_norm"], out["zeta_norm"]
+    return ev, delta, Fn
+
+
+@pytest.mark.parametrize("frac", [0.01, 0.05, 0.3])
+def test_bisection_reaches_closed_form_root(frac):
+    ev, delta, Fn = _identity_problem(frac)
+    a_star = delta / (Fn - delta)
+    res = discrepancy.bisection(ev, delta, tol=1e-6)
+    assert res["flags"] == 0
+    assert res["alpha"] == pytest.approx(a_star, rel=1e-5)
+    assert res["n_evals"] == len(res["trace"]) and res["n_evals"] >= 3
+    # the first two points are the range ends, hi first
+    assert res["trace"][0][0] == 0.0 and res["trace"][1][0] == -8.0
+
+
+def test_bisection_flags():
+    ev, delta, Fn = _identity_problem(0.6)
+    # at alpha = 1 the identity residual is ||F||/2 < delta: no root below hi
+    res = discrepancy.bisection(ev, delta)
+    assert res["flags"] == discrepancy.NOROOT_HIGH and res["n_evals"] == 1 and res["alpha"] == 1.0
+    ev, delta, Fn = _identity_problem(1e-12)
+    res = discrepancy.bisection(ev, delta)
+    assert res["flags"] == discrepancy.NOROOT_LOW and res["n_evals"] == 2 and res["alpha"] == 1e-8
+    ev, delta, Fn = _identity_problem(0.05)
+    res = discrepancy.bisection(ev, delta, tol=0.0, max_steps=5)
+    assert res["flags"] == discrepancy.MAXITER
+    assert res["trace"][-1][0] == res["t"]
+
+
+def test_seeded_search():
+    ev, delta, Fn = _identity_problem(0.03)
+    t_star = math.log10(delta / (Fn - delta))
+    res = discrepancy.seeded(ev, delta, t_star + 0.01)
+    assert res["flags"] == 0 and res["n_evals"] == 1
+    for off in (-3.3, 2.7):
+        res = discrepancy.seeded(ev, delta, t_star + off, tol=1e-6)
+        assert res["flags"] == discrepancy.PRED_FALLBACK
+        assert res["alpha"] == pytest.approx(10 ** t_star, rel=1e-5)
+        assert res["n_evals"] < 45
+    # bracket walk uses one-decade steps from the seed
+    res = discrepancy.seeded(ev, delta, t_star - 3.3, tol=1e-6)
+    assert [round(t - res["trace"][0][0], 9) for t, *_ in res["trace"][:4]] == [0.0, 1.0, 2.0, 3.0]
+
+
+# ---------------------------------------------------------------- recovery and V0 (Sec. 2, Sec. 6)
+
+def test_model_example_v0_closed_form():
+    # Sec. 6 model example: ten sources (0,0,z0), (+-8,0,z0), (0,+-8,z0), z0 = 3, 5;
+    # g = exp(-t) so A0 = 1, A2 = 2.  At (0,0,1.5):
+    # V0 = -(1/4pi)(1/1.5 + 4/sqrt(64+1.5^2) + 1/3.5 + 4/sqrt(64+3.5^2)).
+    with open(os.path.join(GOLDEN, "model_example.json")) as fh:
+        ex = json.load(fh)
+    assert ex["A0"] == pytest.approx(math.gamma(1)) and ex["A2"] == pytest.approx(math.gamma(3))
+    x = np.array([0.0, 0.0, 1.5])
+    v = sum(1.0 / np.linalg.norm(x - np.array(s)) for s in ex["sources"])
+    ref = -(1 / (4 * math.pi)) * (1 / 1.5 + 4 / math.sqrt(64 + 2.25) + 1 / 3.5 + 4 / math.sqrt(64 + 12.25))
+    assert -ex["A0"] / (4 * math.pi) * v == pytest.approx(ref, rel=1e-15)
+
+
+def test_v0_negative_and_harmonic_in_R():
+    # V0 = -(A0/4pi) sum 1/|x - x_l| < 0 (Sec. 2) and harmonic away from the sources.
+    g = Geom(12, 12, 8)
+    V = v0(g)
+    assert np.all(V < 0)
+    lap = (V[2:, 1:-1, 1:-1] + V[:-2, 1:-1, 1:-1] + V[1:-1, 2:, 1:-1] + V[1:-1, :-2, 1:-1]
+           + V[1:-1, 1:-1, 2:] + V[1:-1, 1:-1, :-2] - 6 * V[1:-1, 1:-1, 1:-1])
+    assert np.abs(lap).max() < 0.05 * np.abs(V).max()
+    s = sources(g)
+    assert s.shape == (10, 3) and np.all((s[:, 2] > g.nz) & (s[:, 2] < g.d))
+
+
+def test_recovery_formula():
+    V0 = np.full((2, 2, 2), -0.5)
+    c0 = 0.5
+    xi_true = np.array([0.0, 1 / c0 ** 2 - 0.25, 1 / c0 ** 2 - 1 / 9, 1 / c0 ** 2 + 1.0, 1 / c0 ** 2,
+                        -1.0, 0.1, 2.0]).reshape(2, 2, 2)
+    xi, c, ncl = recovery.recover(xi_true * V0, V0, c0)
+    assert np.allclose(xi, xi_true, rtol=0, atol=1e-15)
+    assert c.ravel()[0] == pytest.approx(c0) and c.ravel()[1] == pytest.approx(2.0) \
+        and c.ravel()[2] == pytest.approx(3.0)
+    assert ncl == 2 and c.ravel()[3] == pytest.approx(1 / math.sqrt(1e-6 / c0 ** 2))
+
+
+# ---------------------------------------------------------------- synthesis
+
+def test_synth_noise_level_exact():
+    g = Geom(8, 8, 8)
+    inst = inputs.workload_instance(1, 3, n=8)
+    d = synth.make_data(g, inst["xi"], inst["noise"], 0.03)
+    assert np.linalg.norm(d["F"] - d["AF"]) == pytest.approx(0.03 * np.linalg.norm(d["AF"]), rel=1e-12)
+    assert d["delta"] == pytest.approx(0.03 * np.linalg.norm(d["AF"]), rel=1e-12)
+
+
+# ---------------------------------------------------------------- features
+
+def test_bin_index_exact_against_integer_sqrt():
+    for pshape in ((16, 16, 16), (12, 8, 24)):
+        b = features.bin_index(pshape)
+        lc = math.lcm(*pshape)
+        L = lc * lc
+        for kz in range(pshape[0]):
+            for ky in range(pshape[1]):
+                for kx in range(pshape[2]):
+                    m = [k if k <= p // 2 else k - p for k, p in zip((kz, ky, kx), pshape)]
+                    U = sum(4 * mi * mi * (lc // p) ** 2 for mi, p in zip(m, pshape))
+                    # largest bb with 3 bb^2 L <= 4096 U  <=>  bb = isqrt(4096 U / (3 L))
+                    bb = math.isqrt((4096 * U) // (3 * L))
+                    assert b[kz, ky, kx] == min(bb, 63)
+    # the corner (P/2, P/2, P/2) has rho = 1 and goes to the last bin
+    assert features.bin_index((16, 16, 16))[8, 8, 8] == 63
+
+
+def test_radial_energy_parseval():
+    g = Geom(8, 6, 4)
+    F = inputs.rng(13).standard_normal(g.shape)
+    fh = np.fft.fftn(pad(g, F))
+    E = features.radial_energy(fh)
+    assert E.sum() == pytest.approx(np.prod(g.pshape) * np.sum(F * F), rel=1e-12)
+
+
+# ---------------------------------------------------------------- MLP reference
+
+def test_bf16_rounding_known_values():
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7, -2.5, 1 + 2 ** -8 + 2 ** -20])
+    out = mlp.bf16_round(vals)
+    assert list(out) == [1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -2.5, 1 + 2 ** -7]
+
+
+def test_gelu_known_values():
+    # GELU(x) = x Phi(x); Phi(1) = 0.8413447460685429 (standard normal CDF).
+    assert mlp.gelu(np.array(0.0)) == 0.0
+    assert mlp.gelu(np.array(1.0)) == pytest.approx(0.8413447460685429, rel=1e-15)
+    assert mlp.gelu(np.array(-1.0)) == pytest.approx(-0.15865525393145707, rel=1e-14)
+
+
+def test_mlp_gradients_against_central_differences():
+    p = mlp.init_params(3)
+    X = inputs.rng(14).standard_normal((6, mlp.D_IN))
+    t = inputs.rng(15).standard_normal(6)
+    y, cache = mlp.forward(p, X, bf16=False)
+    g = mlp.backward(p, cache, t, bf16=False)
+    rg = inputs.rng(16)
+    eps = 1e-6
+    for name, _ in mlp.PARAM_SHAPES:
+        idxs = [tuple(rg.integers(0, s) for s in p[name].shape) for _ in range(6)]
+        for idx in idxs:
+            pp = {k: v.copy() for k, v in p.items()}
+            pm = {k: v.copy() for k, v in p.items()}
+            pp[name][idx] += eps
+            pm[name][idx] -= eps
+            fd = (mlp.loss(mlp.forward(pp, X, False)[0], t) - mlp.loss(mlp.forward(pm, X, False)[0], t)) / (2 * eps)
+            assert g[name][idx] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_adam_first_step():
+    # After one step from zero moments the bias-corrected update is lr * g / (|g| + eps).
+    p = {"w": np.array([1.0, -2.0, 0.5])}
+    g = {"w": np.array([0.3, -1e-3, 0.0])}
+    opt = mlp.Adam(p, lr=1e-3)
+    out = opt.step({"w": p["w"].copy()}, g)
+    assert np.allclose(out["w"], p["w"] - 1e-3 * g["w"] / (np.abs(g["w"]) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_mlp_param_count():
+    p = mlp.init_params(0)
+    assert sum(v.size for v in p.values()) == 25089
