@@ -1,0 +1,178 @@
+/*
+ * fr3d -- regularised FFT solve of the layered 3D Fredholm equation of the
+ * first kind for the inverse coefficient problem of the wave equation
+ * (Leonov & Bakushinsky, arXiv 1703.01216), on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 3, Eq. (8)): find zeta on the layer R from data F on the
+ * layer Y, where
+ *     (A zeta)(y) = sum over cells r of R  h^3 K(x_y - x_r) zeta(r),
+ *     K(x,y,z) = d/dz 1/|x| = -z / (x^2+y^2+z^2)^(3/2),
+ * and F approximates A zeta with ||F - A zeta|| <= delta (Sec. 3, before
+ * Eq. (11)).  The solve follows Algorithm 1 (Sec. 4) with the transform taken
+ * over all three axes of the zero-padded P^3 = (2n)^3 box: Tikhonov's
+ * estimate of the circulant-embedded operator
+ *     zeta^ = conj(k^) f^ / (|k^|^2 + alpha |k^|max^2),
+ * the inverse transform restricted to R, alpha chosen by the discrepancy
+ * principle on Y (Sec. 4, after Algorithm 1), and step 4:
+ *     xi = zeta / V0,   c = (1/c0^2 - xi)^(-1/2)   (xi = 1/c0^2 - 1/c^2, Sec. 2).
+ *
+ * Conventions for every call:
+ *   - Arrays are C order [z][y][x] (x fastest), cell (i,j,k) of R has centre
+ *     ((i+.5)h, (j+.5)h, (k+.5)h); cell (i,j,k) of Y has centre
+ *     ((i+.5)h, (j+.5)h, (D+k+.5)h).
+ *   - Pointers with the suffix _dev are device pointers owned by the caller;
+ *     they must stay valid until the context's stream has reached the work
+ *     that uses them.  Element type is float for precision 32 and double for
+ *     precision 64 unless stated.
+ *   - All GPU work is enqueued on the stream given to fr3d_create.  Calls that
+ *     return host values (reports, deltas, counts) synchronise that stream.
+ *   - Every call returns an fr3d_status; no exception crosses the boundary.
+ *     On failure fr3d_last_error(ctx) holds a message.  One context per host
+ *     thread.
+ */
+#ifndef FR3D_H
+#define FR3D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr3d_ctx fr3d_ctx;  /* opaque, owned by the library */
+
+typedef enum {
+  FR3D_OK = 0,
+  FR3D_E_INVALID = 1, /* bad argument: null pointer, size, alpha <= 0, delta < 0, non-finite */
+  FR3D_E_STATE = 2,   /* call out of order: no kernel loaded, no data set */
+  FR3D_E_NOMEM = 3,   /* device allocation failed */
+  FR3D_E_DEVICE = 4   /* HIP runtime error, or no usable gfx950 device */
+} fr3d_status;
+
+/* Report flags (non-fatal outcomes of a solve). */
+#define FR3D_NOROOT_HIGH 1   /* residual below the target even at the largest alpha */
+#define FR3D_NOROOT_LOW 2    /* residual above the target even at the smallest alpha */
+#define FR3D_MAXITER 4       /* step limit reached; alpha is the upper bracket end */
+#define FR3D_NAN_INPUT 8     /* a norm came out non-finite */
+#define FR3D_PRED_FALLBACK 16 /* predicted alpha rejected; the search continued */
+
+/* Geometry of R and Y (Sec. 3: both are horizontal layers with the same
+ * lateral footprint; Sec. 5: uniform grids, midpoint quadrature weight h^3). */
+typedef struct {
+  int32_t nx, ny, nz; /* cells per axis of R (= of Y); each 2n must be 2^a 3^b, n >= 2 */
+  double h;           /* cell edge (> 0) */
+  double D;           /* z-offset of Y above R in cells, >= nz; <= 0 selects the default */
+  int32_t kind;       /* 0: K = dz(1/|x|) (Eq. (6), (8)); 1: K = 1/|x| (Eq. (5)) */
+  int32_t q;          /* source parameter: -1 = single-kernel default gap nz + ceil(nz/4);
+                         q >= 0: gap (q+1) ceil(nz/8) (each q gives its own kernel) */
+  int32_t precision;  /* 32: FP32 complex transforms and filtering, FP64 kernel spectrum,
+                         norms and alpha search; 64: all FP64 */
+} fr3d_geom;
+
+/* Options of the discrepancy search (Sec. 4: Tikhonov with the discrepancy
+ * principle or its generalisation).  rho(t) = r(10^t)^2 - (tau delta +
+ * h_op ||zeta||)^2 - mu^2 with r the residual on Y; t = log10 alpha. */
+typedef struct {
+  double log10_alpha_lo, log10_alpha_hi; /* search range, default -8, 0 */
+  int32_t max_steps;                     /* bisection steps, default 40 */
+  double tol;                            /* accept |r/T - 1| <= tol, default 1e-3 */
+  double accept_lo, accept_hi;           /* window for predicted points, default 0.9, 1.1 */
+  double tau, h_op, mu;                  /* generalised principle, default 1, 0, 0 */
+  int32_t use_predictor;                 /* 1: seed the search with the alpha predictor */
+} fr3d_dp_opts;
+
+typedef struct {
+  double alpha;             /* relative alpha of the returned estimate */
+  double residual;          /* ||r||_Y at alpha */
+  double zeta_norm;         /* ||zeta||_R at alpha */
+  double delta;             /* noise level used */
+  double target;            /* (tau delta + h_op ||zeta||)^2 + mu^2, square-rooted */
+  int32_t n_evals;          /* number of alpha evaluations (inverse transforms) */
+  int32_t flags;            /* FR3D_* report flags */
+} fr3d_report;
+
+/* Defaults of fr3d_dp_opts. */
+void fr3d_dp_opts_default(fr3d_dp_opts* opts);
+
+/* Create a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  FR3D_E_DEVICE if the device is not
+ * present or is not gfx950.  *out is NULL on failure. */
+fr3d_status fr3d_create(fr3d_ctx** out, int32_t device, void* hip_stream);
+/* Free every device buffer of the context (synchronises its stream). */
+fr3d_status fr3d_destroy(fr3d_ctx* ctx);
+/* Change the stream later work is enqueued on. */
+fr3d_status fr3d_set_stream(fr3d_ctx* ctx, void* hip_stream);
+
+/* Sample K at every wrapped cell offset of the P^3 box (zero in the slot no
+ * pair of cells reaches), take its FP64 3D DFT and keep the octant
+ * kx,ky,kz <= P/2 of k^ (k^ is even in kx and ky and Hermitian in kz).
+ * Algorithm 1 step 1 (Sec. 4) for the kernel, with the midpoint quadrature of
+ * Sec. 5.  Allocates the context's workspaces for this geometry; drops data
+ * set earlier. */
+fr3d_status fr3d_load_kernel(fr3d_ctx* ctx, const fr3d_geom* geom);
+
+/* Set the data F on Y (nz*ny*nx values, device) and the noise level delta >= 0
+ * (absolute, ||F - A zeta|| <= delta).  Runs the zero-padded forward
+ * transform (Algorithm 1 step 1 for the data) and its radial energy
+ * reduction.  F is not retained. */
+fr3d_status fr3d_set_data(fr3d_ctx* ctx, const void* F_dev, double delta);
+
+/* One alpha evaluation at relative alpha > 0 (alpha_abs = alpha |k^|max^2):
+ * Algorithm 1 steps 2-3 with Tikhonov's filter.  Writes zeta on R
+ * (nz*ny*nx, device) and fills *rep (synchronises). */
+fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha_rel, void* zeta_dev, fr3d_report* rep);
+
+/* Choose alpha by the discrepancy principle and write zeta at that alpha.
+ * opts NULL = defaults.  Search rule: evaluate the range ends (hi first), then
+ * bisect in log10 alpha; with use_predictor, start from the predicted alpha,
+ * walk one decade at a time to a sign change, then bisect.  Fills *rep
+ * (synchronises). */
+fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
+                                   fr3d_report* rep);
+
+/* Algorithm 1 step 4: xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2) on R; where
+ * 1/c0^2 - xi < 1e-6/c0^2 the argument is clamped and the cell counted in
+ * *n_clamped (synchronises).  c0 > 0.  zeta, V0, c: nz*ny*nx device arrays. */
+fr3d_status fr3d_recover_c(fr3d_ctx* ctx, const void* zeta_dev, const void* V0_dev, double c0,
+                           void* c_dev, int64_t* n_clamped);
+
+/* V0 on R's cell centres for the geometry's ten point sources (Sec. 6):
+ * V0(x) = -(A0/4 pi) sum_l 1/|x - x_l|.  The sources form the model example's
+ * cross (lateral centre and +-0.4 n along x and y) at heights nz + G/4 and
+ * nz + 3G/4 with G = D - nz.  Writes nz*ny*nx values. */
+fr3d_status fr3d_source_potential(fr3d_ctx* ctx, double A0, void* V0_dev);
+
+/* Apply the forward operator: F = A zeta on Y (Eq. (8) by midpoint
+ * quadrature), through the same padded transforms and the loaded kernel
+ * spectrum.  zeta on R, F on Y, both nz*ny*nx device arrays; may alias. */
+fr3d_status fr3d_apply_operator(fr3d_ctx* ctx, const void* zeta_dev, void* F_dev);
+
+/* F += e * (delta_rel ||F|| / ||e||) with FP64 norms; *delta (host) receives
+ * ||added noise|| (synchronises).  F, e: nz*ny*nx device arrays. */
+fr3d_status fr3d_add_noise(fr3d_ctx* ctx, void* F_dev, const void* e_dev, double delta_rel,
+                           double* delta);
+
+/* Inspection of the context's spectra (for checks).  Layouts:
+ *   octant: double2 [Px/2+1][Pz/2+1][Py/2+1]  (k^ at kx, kz, ky)
+ *   data spectrum: complex T [Px/2+1][Pz][Py] (f^ at kx, kz, ky; kx <= Px/2)
+ *   features: float[65] = log10(E_b/mean E + 1e-30), b < 64, then log10(delta/||F||)
+ *   energy: double[64] radial energies E_b over the full spectrum. */
+fr3d_status fr3d_get_octant(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
+fr3d_status fr3d_get_data_spectrum(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
+fr3d_status fr3d_get_features(fr3d_ctx* ctx, float* feat_dev, double* energy_dev);
+/* |k^|max^2 of the loaded kernel (host). */
+fr3d_status fr3d_get_smax(fr3d_ctx* ctx, double* smax);
+
+/* Per-pass timing with HIP events on the context's stream (for measurement).
+ * Pass ids: 0..2 forward x,y,z; 3..5 inverse z,y,x. */
+fr3d_status fr3d_set_timing(fr3d_ctx* ctx, int32_t enable);
+fr3d_status fr3d_get_timing(fr3d_ctx* ctx, int32_t pass, double* total_ms, int64_t* launches);
+
+const char* fr3d_status_string(fr3d_status s);
+const char* fr3d_last_error(const fr3d_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR3D_H */

@@ -1,0 +1,157 @@
+// Device-resident control block of the alpha search.
+//
+// The regularisation parameter is chosen by the discrepancy principle
+// (Sec. 4, after Algorithm 1: Tikhonov's method with the discrepancy
+// principle or its generalisation).  With t = log10 alpha and r the residual
+// on Y, rho(t) = r^2 - (tau delta + h_op ||zeta||)^2 - mu^2.
+//
+// The search runs on the device: the inverse transform of each evaluation
+// reads alpha from this block and the last workgroup of the final pass, once
+// the two FP64 norms are complete, advances the state machine below and
+// writes the next alpha.  Once the search is done, `active` drops to 0 and
+// every later pass kernel of that search returns at once, so the host can
+// enqueue evaluations ahead without reading anything back.
+//
+// Plain search: evaluate hi; rho < 0 -> done NOROOT_HIGH.  Evaluate lo;
+// rho > 0 -> done NOROOT_LOW.  Then bisect: m = (a+b)/2, accept when
+// |r/T - 1| <= tol, else a = m if rho < 0 else b = m; after max_steps the
+// answer is b (MAXITER), re-evaluated there if b was not the last point.
+// Seeded search: evaluate the predicted t0; accept inside [acc_lo, acc_hi];
+// else walk one decade at a time toward the sign change (accepting any point
+// inside the window), then bisect inside the bracket.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fr3d {
+
+enum : int32_t {
+  ST_IDLE = 0,
+  ST_FIXED = 1,   // one evaluation at a given alpha
+  ST_HI = 2,      // evaluating the upper range end
+  ST_LO = 3,      // evaluating the lower range end
+  ST_BISECT = 4,  // evaluating a bisection midpoint
+  ST_FINAL = 5,   // re-evaluating b after the step limit
+  ST_SEED = 6,    // evaluating the predicted point
+  ST_UP = 7,      // decade walk upward
+  ST_DOWN = 8,    // decade walk downward
+  ST_DONE = 9,
+};
+
+enum : int32_t { F_NOROOT_HIGH = 1, F_NOROOT_LOW = 2, F_MAXITER = 4, F_NAN = 8, F_PRED_FALLBACK = 16 };
+
+struct Ctrl {
+  // settings
+  double s_max, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi;
+  int32_t max_steps;
+  // state
+  int32_t state, active, n_evals, flags, steps;
+  double t;          // log10 of the relative alpha being evaluated
+  double a, b;       // bracket
+  double alpha_abs;  // 10^t * s_max, read by the filter
+  double r2, z2;     // norms of the last evaluation
+  double target;     // T of the last evaluation
+  uint32_t ticket;   // last-workgroup counter of the final pass
+  uint32_t pad_;
+};
+
+__device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {
+  c->t = t;
+  c->alpha_abs = pow(10.0, t) * c->s_max;
+}
+
+__device__ __forceinline__ void ctrl_finish(Ctrl* c, int32_t flags) {
+  c->flags |= flags;
+  c->state = ST_DONE;
+  c->active = 0;
+}
+
+// Advance after an evaluation at c->t with ||r||^2 = r2 and ||zeta||^2 = z2.
+__device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
+  c->r2 = r2;
+  c->z2 = z2;
+  c->n_evals += 1;
+  const double r = sqrt(r2), zn = sqrt(z2);
+  const double g = c->tau * c->delta + c->h_op * zn;
+  const double tgt2 = g * g + c->mu * c->mu;
+  const double rho = r2 - tgt2;
+  const double tgt = sqrt(tgt2);
+  c->target = tgt;
+  const double ratio = tgt2 > 0 ? r / tgt : INFINITY;
+  if (!isfinite(r2) || !isfinite(z2)) { ctrl_finish(c, F_NAN); return; }
+  const bool in_window = ratio >= c->acc_lo && ratio <= c->acc_hi;
+  switch (c->state) {
+    case ST_FIXED:
+      ctrl_finish(c, 0);
+      return;
+    case ST_HI:
+      if (rho < 0) { ctrl_finish(c, F_NOROOT_HIGH); return; }
+      c->state = ST_LO;
+      ctrl_set_t(c, c->lo);
+      return;
+    case ST_LO:
+      if (rho > 0) { ctrl_finish(c, F_NOROOT_LOW); return; }
+      c->a = c->lo; c->b = c->hi; c->steps = 0;
+      c->state = ST_BISECT;
+      ctrl_set_t(c, 0.5 * (c->a + c->b));
+      return;
+    case ST_BISECT:
+      if (fabs(ratio - 1.0) <= c->tol) { ctrl_finish(c, 0); return; }
+      if (rho < 0) c->a = c->t; else c->b = c->t;
+      c->steps += 1;
+      if (c->steps >= c->max_steps) {
+        if (c->t == c->b) { ctrl_finish(c, F_MAXITER); return; }
+        c->state = ST_FINAL;
+        ctrl_set_t(c, c->b);
+        return;
+      }
+      ctrl_set_t(c, 0.5 * (c->a + c->b));
+      return;
+    case ST_FINAL:
+      ctrl_finish(c, F_MAXITER);
+      return;
+    case ST_SEED:
+      if (in_window) { ctrl_finish(c, 0); return; }
+      c->flags |= F_PRED_FALLBACK;
+      if (rho < 0) {
+        c->a = c->t;
+        if (c->a >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
+        c->state = ST_UP;
+        ctrl_set_t(c, fmin(c->a + 1.0, c->hi));
+      } else {
+        c->b = c->t;
+        if (c->b <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
+        c->state = ST_DOWN;
+        ctrl_set_t(c, fmax(c->b - 1.0, c->lo));
+      }
+      return;
+    case ST_UP:
+      if (in_window) { ctrl_finish(c, 0); return; }
+      if (rho >= 0) {
+        c->b = c->t; c->steps = 0; c->state = ST_BISECT;
+        ctrl_set_t(c, 0.5 * (c->a + c->b));
+        return;
+      }
+      c->a = c->t;
+      if (c->a >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
+      ctrl_set_t(c, fmin(c->a + 1.0, c->hi));
+      return;
+    case ST_DOWN:
+      if (in_window) { ctrl_finish(c, 0); return; }
+      if (rho <= 0) {
+        c->a = c->t; c->steps = 0; c->state = ST_BISECT;
+        ctrl_set_t(c, 0.5 * (c->a + c->b));
+        return;
+      }
+      c->b = c->t;
+      if (c->b <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
+      ctrl_set_t(c, fmax(c->b - 1.0, c->lo));
+      return;
+    default:
+      ctrl_finish(c, 0);
+      return;
+  }
+}
+
+}  // namespace fr3d

@@ -1,0 +1,100 @@
+// Pencil passes of the zero-padded 3D transforms and their fused prologues and
+// epilogues (Algorithm 1, steps 1-3, Sec. 4, with the transform over all three
+// axes of the P^3 = (2n)^3 box).
+//
+// Volume layouts in device memory (T = float or double, c2 = complex T):
+//   F, zeta      real  [nz][ny][nx]                 data on Y / estimate on R
+//   A  (x done)  c2    [Kx][nz][ny]     Kx = Px/2+1 real-to-complex along x
+//   B  (y done)  c2    [Kx][nz][Py]
+//   S  (spectrum)c2    [Kx][Pz][Py]     f^ for kx <= Px/2 (f is real)
+//   O  (octant)  double2 [Kx][Pz/2+1][Py/2+1]   k^ (even in kx, ky; Hermitian in kz)
+//   W1 (z undone) c4   [Kx][nz][Py]     (u^, r^) pairs, z < nz only
+//   W2 (y undone) c4   [Kx][nz][ny]
+// The forward passes read only the n nonzero inputs of each pencil; the
+// inverse passes write only the outputs inside R / Y.  The x axis is the
+// slowest axis of every spectral volume, so the y pass reads and writes whole
+// rows and the z and x passes read rows of C consecutive pencils.
+#pragma once
+
+#include "control.hpp"
+#include "fft_core.hpp"
+
+namespace fr3d {
+
+constexpr int NT = 256;  // threads per workgroup of every pass
+
+// Pencils per workgroup: a 32 KiB tile (FP32: 4096 elements, FP64: 2048).
+template <typename T, int P> struct Tile {
+  static constexpr int pow2ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
+  static constexpr int TE = sizeof(T) == 4 ? 4096 : 2048;
+  static constexpr int C = TE / pow2ceil(P) > 0 ? TE / pow2ceil(P) : 1;
+};
+
+// Spectral-energy bin of a point (exact integer rule; see the feature oracle):
+// b = largest b <= 63 with 3 b^2 L <= 4096 U, U = sum 4 m_i^2 (l/P_i)^2, L = l^2.
+struct BinGeom {
+  int px, py, pz;
+  long long fx, fy, fz;  // (l / P_i)^2
+  long long L3;          // 3 L
+};
+
+__device__ __forceinline__ int energy_bin(const BinGeom& g, int kx, int ky, int kz) {
+  const long long mx = kx <= g.px / 2 ? kx : kx - g.px;
+  const long long my = ky <= g.py / 2 ? ky : ky - g.py;
+  const long long mz = kz <= g.pz / 2 ? kz : kz - g.pz;
+  const long long U = 4 * (mx * mx * g.fx + my * my * g.fy + mz * mz * g.fz);
+  const long long U4 = 4096 * U;
+  int b = (int)floor(64.0 * sqrt((double)U / ((double)g.L3)));
+  if ((long long)(b + 1) * (b + 1) * g.L3 <= U4) b += 1;
+  if ((long long)b * b * g.L3 > U4) b -= 1;
+  return b < 63 ? b : 63;
+}
+
+struct FwdArgs {
+  int nz_in, ny_in;   // rows of the x pass: nz_in planes of ny_in rows
+  int kx_n;           // Px/2 + 1
+  int py, pz;         // padded extents
+  // kernel sampling (x pass in generator mode)
+  double h, D;
+  int nx, ny, nz;     // cell counts
+  int kind;
+  // energy epilogue
+  BinGeom bg;
+  double* bins_part;  // [gridDim][64]
+  double* bins_out;   // [64] energies
+  float* feat_out;    // [65] features
+  uint32_t* ticket;
+  double delta;       // noise level for the last feature
+};
+
+struct InvArgs {
+  int nx, ny, nz;
+  int kx_n, py, pz;
+  double scale;             // 1/(Px Py Pz)
+  const double2* oct;
+  Ctrl* ctrl;               // null for the forward operator (no search)
+  double2* norm_part;       // [gridDim][2]
+  uint32_t* ticket;
+};
+
+// ------------------------------------------------------------------ host launchers
+// Each returns hipSuccess or the launch error; P is the transform length of
+// the pass axis and selects the compiled instance.
+template <typename T>
+hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
+// mode 0: data (pruned input, full output, energy epilogue); 1: kernel (full input, octant output)
+template <typename T>
+hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
+// mode 0: Tikhonov filter (u^, r^); 1: multiply by k^ (forward operator)
+template <typename T>
+hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+
+bool supported_length(int P);
+
+}  // namespace fr3d

@@ -1,0 +1,240 @@
+"""Python binding of libfr3d (include/fr3d.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch provides device memory and
+the stream.  Importing this module loads the in-tree libfr3d.so and fails
+loudly if it has not been built.
+
+    from paper_1703_01216_amd import fr3d
+    ctx = fr3d.Context()                       # current torch device and stream
+    ctx.load_kernel(nx=128, ny=128, nz=128, precision=32)
+    ctx.set_data(F, delta)                     # F: (nz, ny, nx) float32 cuda tensor
+    rep = ctx.solve_discrepancy(zeta)          # zeta: output tensor of the same shape
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfr3d.so")
+
+OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE = 0, 1, 2, 3, 4
+NOROOT_HIGH, NOROOT_LOW, MAXITER, NAN_INPUT, PRED_FALLBACK = 1, 2, 4, 8, 16
+
+EXPORTED = [
+    "fr3d_dp_opts_default", "fr3d_create", "fr3d_destroy", "fr3d_set_stream", "fr3d_load_kernel",
+    "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
+    "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
+    "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error",
+]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double), ("D", ctypes.c_double), ("kind", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class DpOpts(ctypes.Structure):
+    _fields_ = [("log10_alpha_lo", ctypes.c_double), ("log10_alpha_hi", ctypes.c_double),
+                ("max_steps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("accept_lo", ctypes.c_double), ("accept_hi", ctypes.c_double),
+                ("tau", ctypes.c_double), ("h_op", ctypes.c_double), ("mu", ctypes.c_double),
+                ("use_predictor", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("residual", ctypes.c_double),
+                ("zeta_norm", ctypes.c_double), ("delta", ctypes.c_double),
+                ("target", ctypes.c_double), ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Fr3dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fr3d status {status}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1703_01216_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "fr3d_dp_opts_default": (None, [ctypes.POINTER(DpOpts)]),
+        "fr3d_create": (I32, [ctypes.POINTER(P), I32, P]),
+        "fr3d_destroy": (I32, [P]),
+        "fr3d_set_stream": (I32, [P, P]),
+        "fr3d_load_kernel": (I32, [P, ctypes.POINTER(Geom)]),
+        "fr3d_set_data": (I32, [P, P, D]),
+        "fr3d_solve_alpha": (I32, [P, D, P, ctypes.POINTER(Report)]),
+        "fr3d_solve_discrepancy": (I32, [P, ctypes.POINTER(DpOpts), P, ctypes.POINTER(Report)]),
+        "fr3d_recover_c": (I32, [P, P, P, D, P, ctypes.POINTER(I64)]),
+        "fr3d_source_potential": (I32, [P, D, P]),
+        "fr3d_apply_operator": (I32, [P, P, P]),
+        "fr3d_add_noise": (I32, [P, P, P, D, ctypes.POINTER(D)]),
+        "fr3d_get_octant": (I32, [P, P, I64]),
+        "fr3d_get_data_spectrum": (I32, [P, P, I64]),
+        "fr3d_get_features": (I32, [P, P, P]),
+        "fr3d_get_smax": (I32, [P, ctypes.POINTER(D)]),
+        "fr3d_set_timing": (I32, [P, I32]),
+        "fr3d_get_timing": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)]),
+        "fr3d_status_string": (ctypes.c_char_p, [I32]),
+        "fr3d_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def default_opts(**kw) -> DpOpts:
+    o = DpOpts()
+    lib().fr3d_dp_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """One solver context on a device, enqueuing on a torch stream."""
+
+    def __init__(self, device: int | None = None, stream=None):
+        import torch
+        self.torch = torch
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        self._lib = lib()
+        self._ctx = ctypes.c_void_p()
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = st
+        s = self._lib.fr3d_create(ctypes.byref(self._ctx), int(device), ctypes.c_void_p(st.cuda_stream))
+        if s != OK:
+            raise Fr3dError(s, self._lib.fr3d_status_string(s).decode())
+        self.geom = None
+
+    # ------------------------------------------------------------ plumbing
+    def _chk(self, s):
+        if s != OK:
+            raise Fr3dError(s, self._lib.fr3d_last_error(self._ctx).decode())
+
+    def close(self):
+        if self._ctx:
+            self._lib.fr3d_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dtype(self):
+        return self.torch.float64 if self.geom.precision == 64 else self.torch.float32
+
+    @property
+    def shape(self):
+        return (self.geom.nz, self.geom.ny, self.geom.nx)
+
+    def _arr(self, t, name):
+        if t is None:
+            raise ValueError(f"{name} is None")
+        if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} cuda tensor of shape {self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_stream(self, stream):
+        self._stream = stream
+        self._chk(self._lib.fr3d_set_stream(self._ctx, ctypes.c_void_p(stream.cuda_stream)))
+
+    # ------------------------------------------------------------ calls of include/fr3d.h
+    def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32):
+        g = Geom(nx, ny, nz, h, D, kind, q, precision)
+        self._chk(self._lib.fr3d_load_kernel(self._ctx, ctypes.byref(g)))
+        self.geom = g
+
+    def set_data(self, F, delta):
+        self._chk(self._lib.fr3d_set_data(self._ctx, self._arr(F, "F"), float(delta)))
+
+    def solve_alpha(self, alpha_rel, zeta):
+        rep = Report()
+        self._chk(self._lib.fr3d_solve_alpha(self._ctx, float(alpha_rel), self._arr(zeta, "zeta"), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_discrepancy(self, zeta, opts: DpOpts | None = None, **kw):
+        o = opts if opts is not None else default_opts(**kw)
+        rep = Report()
+        self._chk(self._lib.fr3d_solve_discrepancy(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
+                                                   ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def recover_c(self, zeta, V0, c0, c_out):
+        n = ctypes.c_int64()
+        self._chk(self._lib.fr3d_recover_c(self._ctx, self._arr(zeta, "zeta"), self._arr(V0, "V0"), float(c0),
+                                           self._arr(c_out, "c"), ctypes.byref(n)))
+        return int(n.value)
+
+    def source_potential(self, V0, A0=1.0):
+        self._chk(self._lib.fr3d_source_potential(self._ctx, float(A0), self._arr(V0, "V0")))
+
+    def apply_operator(self, zeta, F_out):
+        self._chk(self._lib.fr3d_apply_operator(self._ctx, self._arr(zeta, "zeta"), self._arr(F_out, "F")))
+
+    def add_noise(self, F, e, delta_rel):
+        d = ctypes.c_double()
+        self._chk(self._lib.fr3d_add_noise(self._ctx, self._arr(F, "F"), self._arr(e, "e"), float(delta_rel),
+                                           ctypes.byref(d)))
+        return d.value
+
+    def get_octant(self):
+        g = self.geom
+        out = self.torch.empty((g.nx + 1, g.nz + 1, g.ny + 1, 2), dtype=self.torch.float64, device="cuda")
+        self._chk(self._lib.fr3d_get_octant(self._ctx, _ptr(out), out.numel() * 8))
+        return out
+
+    def get_data_spectrum(self):
+        g = self.geom
+        out = self.torch.empty((g.nx + 1, 2 * g.nz, 2 * g.ny, 2), dtype=self.dtype, device="cuda")
+        self._chk(self._lib.fr3d_get_data_spectrum(self._ctx, _ptr(out), out.numel() * out.element_size()))
+        return out
+
+    def get_features(self):
+        feat = self.torch.empty(65, dtype=self.torch.float32, device="cuda")
+        en = self.torch.empty(64, dtype=self.torch.float64, device="cuda")
+        self._chk(self._lib.fr3d_get_features(self._ctx, _ptr(feat), _ptr(en)))
+        return feat, en
+
+    def get_smax(self):
+        d = ctypes.c_double()
+        self._chk(self._lib.fr3d_get_smax(self._ctx, ctypes.byref(d)))
+        return d.value
+
+    def set_timing(self, on: bool):
+        self._chk(self._lib.fr3d_set_timing(self._ctx, 1 if on else 0))
+
+    def get_timing(self, pass_id: int):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._chk(self._lib.fr3d_get_timing(self._ctx, int(pass_id), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

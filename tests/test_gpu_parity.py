@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU FP64 oracle.
+
+Tolerances: FP64 path within 1e-11 relative (rounding of two 3D transforms);
+FP32 path within 1e-5 relative L2 on reconstructions (the precision target of
+the FP32/FP64 split) and 2e-6 on raw spectra relative to their largest entry.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import discrepancy, features, recovery, tikhonov
+from oracle.geometry import sample_kernel, v0
+from oracle.operator import forward_circulant, forward_direct, pad
+
+from gpu_helpers import geom, half_spectrum, instance, octant_from_full, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fr3d():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_01216_amd import fr3d as m
+    return m
+
+
+def ctx_for(fr3d, g, precision):
+    c = fr3d.Context()
+    c.load_kernel(g.nx, g.ny, g.nz, h=g.h, D=g.d, kind=g.kind, precision=precision)
+    return c
+
+
+def dev(a, precision):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64 if precision == 64 else torch.float32,
+                        device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+SHAPES = [(2, 2, 2), (4, 4, 4), (8, 6, 4), (6, 12, 8), (16, 16, 16), (24, 12, 32), (32, 32, 32), (48, 24, 16)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kind", [0, 1])
+def test_kernel_octant(fr3d, shape, kind):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz, kind=kind)
+    c = ctx_for(fr3d, g, 64)
+    khat = np.fft.fftn(sample_kernel(g))
+    ref = octant_from_full(khat, g)
+    got = host(c.get_octant())
+    got = got[..., 0] + 1j * got[..., 1]
+    scale = np.abs(khat).max()
+    assert np.abs(got - ref).max() < 1e-13 * scale
+    assert c.get_smax() == pytest.approx((np.abs(khat) ** 2).max(), rel=1e-13)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("precision", [64, 32])
+def test_data_spectrum(fr3d, shape, precision):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    c = ctx_for(fr3d, g, precision)
+    F = np.random.default_rng(1).standard_normal(g.shape)
+    Fd = dev(F, precision)
+    Fh = host(Fd)
+    c.set_data(Fd, 0.1)
+    ref = half_spectrum(np.fft.fftn(pad(g, Fh)), g)
+    got = host(c.get_data_spectrum())
+    got = got[..., 0] + 1j * got[..., 1]
+    tol = 1e-13 if precision == 64 else 2e-6
+    assert np.abs(got - ref).max() < tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 4), (16, 16, 16), (24, 12, 32), (32, 32, 32)])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_features(fr3d, shape, precision):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    c = ctx_for(fr3d, g, precision)
+    F = np.random.default_rng(2).standard_normal(g.shape)
+    Fd = dev(F, precision)
+    Fh = host(Fd)
+    delta = 0.03 * np.linalg.norm(Fh)
+    c.set_data(Fd, delta)
+    feat, en = c.get_features()
+    x, E = features.features(np.fft.fftn(pad(g, Fh)), delta, np.linalg.norm(Fh))
+    tol = 1e-12 if precision == 64 else 2e-6
+    assert np.abs(host(en) - E).max() < tol * E.max()
+    assert np.abs(host(feat) - x).max() < 1e-4
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 4), (16, 16, 16), (24, 12, 32), (32, 32, 32), (48, 48, 48)])
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("alpha", [1e-2, 1e-4])
+def test_solve_alpha(fr3d, shape, precision, alpha):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    d = instance(g, 11, 0.01)
+    c = ctx_for(fr3d, g, precision)
+    Fd = dev(d["F"], precision)
+    Fh = host(Fd)
+    c.set_data(Fd, d["delta"])
+    zeta = torch.empty_like(Fd)
+    rep = c.solve_alpha(alpha, zeta)
+    ref = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), Fh, alpha)
+    tol = 1e-11 if precision == 64 else 1e-5
+    assert rel_l2(host(zeta), ref["zeta"]) < tol
+    assert rep["residual"] == pytest.approx(ref["r_norm"], rel=tol * 10)
+    assert rep["zeta_norm"] == pytest.approx(ref["zeta_norm"], rel=tol * 10)
+    assert rep["n_evals"] == 1 and rep["flags"] == 0
+    assert rep["alpha"] == pytest.approx(alpha, rel=1e-14)
+
+
+@pytest.mark.parametrize("shape,D", [((8, 8, 8), None), ((16, 12, 8), 13.5), ((32, 32, 32), None)])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_apply_operator(fr3d, shape, D, precision):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz, D=D)
+    c = ctx_for(fr3d, g, precision)
+    z = np.random.default_rng(3).standard_normal(g.shape)
+    zd = dev(z, precision)
+    out = torch.empty_like(zd)
+    c.apply_operator(zd, out)
+    zh = host(zd)
+    ref = forward_direct(g, zh) if max(shape) <= 16 else forward_circulant(g, zh)
+    tol = 1e-12 if precision == 64 else 1e-5
+    assert rel_l2(host(out), ref) < tol
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (24, 12, 32)])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_source_potential_and_recovery(fr3d, shape, precision):
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    c = ctx_for(fr3d, g, precision)
+    V = torch.empty(g.shape, dtype=torch.float64 if precision == 64 else torch.float32, device="cuda")
+    c.source_potential(V, 1.0)
+    ref = v0(g)
+    tol = 1e-14 if precision == 64 else 1e-6
+    assert np.abs(host(V) - ref).max() < tol * np.abs(ref).max()
+    xi = np.random.default_rng(4).uniform(-0.5, 0.9, g.shape)
+    xi.flat[0] = 5.0  # beyond 1/c0^2: clamped
+    zeta = dev(xi * host(V), precision)
+    cc = torch.empty_like(zeta)
+    ncl = c.recover_c(zeta, V, 1.0, cc)
+    xr, cr, nr = recovery.recover(host(zeta), host(V), 1.0)
+    assert ncl == nr == 1
+    assert np.abs(host(cc) - cr).max() < (1e-12 if precision == 64 else 1e-5) * np.abs(cr).max()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_add_noise_level(fr3d, precision):
+    g = geom(8, 8, 8)
+    c = ctx_for(fr3d, g, precision)
+    rg = np.random.default_rng(5)
+    F0 = dev(rg.standard_normal(g.shape), precision)
+    e = dev(rg.standard_normal(g.shape), precision)
+    F = F0.clone()
+    delta = c.add_noise(F, e, 0.03)
+    diff = np.linalg.norm(host(F) - host(F0))
+    assert delta == pytest.approx(0.03 * np.linalg.norm(host(F0)), rel=1e-12)
+    assert diff == pytest.approx(delta, rel=1e-12 if precision == 64 else 1e-5)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 16, 16), (32, 32, 32), (24, 12, 32)])
+@pytest.mark.parametrize("delta_rel", [0.01, 0.05])
+def test_discrepancy_fp64_matches_rule(fr3d, shape, delta_rel):
+    # FP64: the device search takes the oracle's decisions step for step.
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    d = instance(g, 21, delta_rel)
+    c = ctx_for(fr3d, g, 64)
+    Fd = dev(d["F"], 64)
+    c.set_data(Fd, d["delta"])
+    zeta = torch.empty_like(Fd)
+    rep = c.solve_discrepancy(zeta)
+    khat = np.fft.fftn(sample_kernel(g))
+
+    def ev(a):
+        o = tikhonov.solve_spectral(g, khat, d["F"], a)
+        return o["r_norm"], o["zeta_norm"]
+    ref = discrepancy.bisection(ev, d["delta"])
+    assert rep["flags"] == ref["flags"]
+    assert rep["n_evals"] == ref["n_evals"]
+    assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    o = tikhonov.solve_spectral(g, khat, d["F"], rep["alpha"])
+    assert rel_l2(host(zeta), o["zeta"]) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32)])
+@pytest.mark.parametrize("delta_rel", [0.01, 0.03])
+def test_discrepancy_fp32(fr3d, shape, delta_rel):
+    # FP32: judged at the device's alpha -- the oracle's residual there meets
+    # the acceptance rule, and zeta agrees with the oracle at that alpha.
+    nx, ny, nz = shape
+    g = geom(nx, ny, nz)
+    d = instance(g, 31, delta_rel)
+    c = ctx_for(fr3d, g, 32)
+    Fd = dev(d["F"], 32)
+    Fh = host(Fd)
+    c.set_data(Fd, d["delta"])
+    zeta = torch.empty_like(Fd)
+    rep = c.solve_discrepancy(zeta)
+    assert rep["flags"] == 0
+    o = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), Fh, rep["alpha"])
+    assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + 1e-5
+    assert rel_l2(host(zeta), o["zeta"]) < 1e-5
+
+
+def test_flags_and_errors(fr3d):
+    g = geom(8, 8, 8)
+    c = ctx_for(fr3d, g, 64)
+    F = dev(instance(g, 41)["F"], 64)
+    zeta = torch.empty_like(F)
+    with pytest.raises(fr3d.Fr3dError) as ei:
+        c.solve_alpha(1e-3, zeta)
+    assert ei.value.status == fr3d.E_STATE
+    c.set_data(F, 1e30)
+    rep = c.solve_discrepancy(zeta)
+    assert rep["flags"] == fr3d.NOROOT_HIGH and rep["n_evals"] == 1
+    c.set_data(F, 0.0)
+    rep = c.solve_discrepancy(zeta)
+    assert rep["flags"] == fr3d.NOROOT_LOW and rep["n_evals"] == 2
+    for bad in (0.0, -1.0, float("nan")):
+        with pytest.raises(fr3d.Fr3dError) as ei:
+            c.solve_alpha(bad, zeta)
+        assert ei.value.status == fr3d.E_INVALID
+    with pytest.raises(fr3d.Fr3dError):
+        c.set_data(F, -1.0)
+    with pytest.raises(fr3d.Fr3dError):
+        c.load_kernel(10, 8, 8)  # 2n = 20 is not 2^a 3^b
+    with pytest.raises(fr3d.Fr3dError):
+        c.load_kernel(8, 8, 8, D=4.0)  # Y overlaps R
+
+
+def test_deterministic(fr3d):
+    g = geom(32, 32, 32)
+    d = instance(g, 51, 0.02)
+    c = ctx_for(fr3d, g, 32)
+    Fd = dev(d["F"], 32)
+    outs = []
+    for _ in range(2):
+        c.set_data(Fd, d["delta"])
+        zeta = torch.empty_like(Fd)
+        rep = c.solve_discrepancy(zeta)
+        outs.append((host(zeta), rep))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("index", [0, 1])
+def test_workload2_full_size(fr3d, index):
+    # 128^3 grids padded to 256^3, FP32 transforms, bisection to the
+    # discrepancy; oracle evaluated at the device's alpha.
+    from paper_1703_01216_amd import inputs
+    from oracle import synth
+    inst = inputs.workload_instance(2, index)
+    g = geom(128, 128, 128)
+    d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"])
+    c = ctx_for(fr3d, g, 32)
+    Fd = dev(d["F"], 32)
+    Fh = host(Fd)
+    c.set_data(Fd, d["delta"])
+    zeta = torch.empty_like(Fd)
+    rep = c.solve_discrepancy(zeta)
+    assert rep["flags"] == 0
+    o = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), Fh, rep["alpha"])
+    assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + 1e-5
+    err = rel_l2(host(zeta), o["zeta"])
+    print(f"workload 2 #{index}: alpha={rep['alpha']:.4e} evals={rep['n_evals']} rel_l2={err:.2e}")
+    assert err < 1e-5

@@ -1,0 +1,69 @@
+"""Host-side checks of the C-ABI library (no GPU compute): it loads, exports
+every function include/fr3d.h declares, and its pure-host entry points behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fr3d.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr3d_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1703_01216_amd import fr3d
+    if not os.path.exists(fr3d.LIB_PATH):
+        pytest.fail("libfr3d.so not built (run __graft_entry__.build())")
+    return fr3d.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert len(names) >= 18
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+    from paper_1703_01216_amd import fr3d
+    assert sorted(fr3d.EXPORTED) == names
+
+
+def test_defaults_and_status_strings(lib):
+    from paper_1703_01216_amd import fr3d
+    o = fr3d.default_opts()
+    assert (o.log10_alpha_lo, o.log10_alpha_hi, o.max_steps, o.tol) == (-8.0, 0.0, 40, 1e-3)
+    assert (o.accept_lo, o.accept_hi, o.tau, o.h_op, o.mu, o.use_predictor) == (0.9, 1.1, 1.0, 0.0, 0.0, 0)
+    assert lib.fr3d_status_string(0) == b"ok"
+    assert lib.fr3d_status_string(1) == b"invalid argument"
+    assert lib.fr3d_last_error(None) == b"null context"
+
+
+def test_null_arguments_rejected(lib):
+    from paper_1703_01216_amd import fr3d
+    assert lib.fr3d_create(None, 0, None) == fr3d.E_INVALID
+    assert lib.fr3d_destroy(None) == fr3d.E_INVALID
+    assert lib.fr3d_set_data(None, None, 0.0) == fr3d.E_INVALID
+    assert lib.fr3d_solve_alpha(None, 1.0, None, None) == fr3d.E_INVALID
+
+
+def test_create_without_gpu_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1703_01216_amd import fr3d
+    ctx = ctypes.c_void_p()
+    assert lib.fr3d_create(ctypes.byref(ctx), 0, None) == fr3d.E_DEVICE
+    assert not ctx.value
+
+
+def test_struct_layouts_match_header():
+    from paper_1703_01216_amd import fr3d
+    # int32 x3, (pad) double x2, int32 x3 (+pad)
+    assert ctypes.sizeof(fr3d.Geom) == 48 and fr3d.Geom.h.offset == 16 and fr3d.Geom.kind.offset == 32
+    assert ctypes.sizeof(fr3d.Report) == 48 and fr3d.Report.n_evals.offset == 40
+    assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 80
