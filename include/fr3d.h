@@ -11,7 +11,7 @@
  * Eq. (11)).  The solve follows Algorithm 1 (Sec. 4) with the transform taken
  * over all three axes of the zero-padded P^3 = (2n)^3 box: Tikhonov's
  * estimate of the circulant-embedded operator
- *     zeta^ = conj(k^) f^ / (|k^|^2 + alpha |k^|max^2),
+ *     zeta^ = conj(k^) f^ / (|k^|^2 + alpha),
  * the inverse transform restricted to R, alpha chosen by the discrepancy
  * principle on Y (Sec. 4, after Algorithm 1), and step 4:
  *     xi = zeta / V0,   c = (1/c0^2 - xi)^(-1/2)   (xi = 1/c0^2 - 1/c^2, Sec. 2).
@@ -67,6 +67,10 @@ typedef struct {
                          q >= 0: gap (q+1) ceil(nz/8) (each q gives its own kernel) */
   int32_t precision;  /* 32: FP32 complex transforms and filtering, FP64 kernel spectrum,
                          norms and alpha search; 64: all FP64 */
+  int32_t alpha_relative; /* 0: alpha is the parameter of the Tikhonov functional
+                         ||A zeta - F||^2 + alpha ||zeta||^2 in the L2 norms of Sec. 3
+                         (the h^3 weights of both terms cancel); 1: alpha is relative,
+                         alpha_abs = alpha max|k^|^2 */
 } fr3d_geom;
 
 /* Options of the discrepancy search (Sec. 4: Tikhonov with the discrepancy
@@ -82,7 +86,7 @@ typedef struct {
 } fr3d_dp_opts;
 
 typedef struct {
-  double alpha;             /* relative alpha of the returned estimate */
+  double alpha;             /* alpha of the returned estimate (geom.alpha_relative units) */
   double residual;          /* ||r||_Y at alpha */
   double zeta_norm;         /* ||zeta||_R at alpha */
   double delta;             /* noise level used */
@@ -117,10 +121,10 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* ctx, const fr3d_geom* geom);
  * reduction.  F is not retained. */
 fr3d_status fr3d_set_data(fr3d_ctx* ctx, const void* F_dev, double delta);
 
-/* One alpha evaluation at relative alpha > 0 (alpha_abs = alpha |k^|max^2):
+/* One alpha evaluation at alpha > 0 (units set by geom.alpha_relative):
  * Algorithm 1 steps 2-3 with Tikhonov's filter.  Writes zeta on R
  * (nz*ny*nx, device) and fills *rep (synchronises). */
-fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha_rel, void* zeta_dev, fr3d_report* rep);
+fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_report* rep);
 
 /* Choose alpha by the discrepancy principle and write zeta at that alpha.
  * opts NULL = defaults.  Search rule: evaluate the range ends (hi first), then

@@ -11,8 +11,10 @@ box (the three-axis analogue of the paper's per-frequency systems, Eq. (14)):
     zeta(alpha)     = zeta_pad restricted to R's index block [0,n)^3,
     r(alpha)        = (C zeta_pad - E_Y F) restricted to Y's index block,
 
-with alpha_abs = alpha * max |k^|^2 (alpha is relative to the squared operator
-norm of C, so one alpha range serves every grid and kernel).
+where alpha_abs is the Tikhonov parameter of the functional in the L2 norms of
+Sec. 3 (midpoint weights h^3 on both sides cancel, so alpha_abs = alpha for
+any h).  With ``relative=True`` the given alpha is scaled by max |k^|^2
+(relative to the squared operator norm of C) instead.
 
 ``dense_tikhonov`` solves the normal equations (C^T C + alpha_abs I) u = C^T E_Y F
 with C assembled as a matrix and a Cholesky factorisation -- no transform.
@@ -42,17 +44,20 @@ def spectral_filter(khat, fhat, alpha_abs: float):
     return khat.conj() * fhat / (s + alpha_abs), -alpha_abs * fhat / (s + alpha_abs)
 
 
-def solve_box(khat, f_box, alpha_rel: float):
+def alpha_abs(khat, alpha: float, relative: bool) -> float:
+    return float(alpha) * (float((khat * khat.conj()).real.max()) if relative else 1.0)
+
+
+def solve_box(khat, f_box, alpha: float, relative: bool = False):
     """Tikhonov minimiser for data given on the whole P^3 box (no restriction)."""
-    a = float(alpha_rel) * float((khat * khat.conj()).real.max())
+    a = alpha_abs(khat, alpha, relative)
     uhat, rhat = spectral_filter(khat, np.fft.fftn(f_box), a)
     return np.fft.ifftn(uhat), np.fft.ifftn(rhat)
 
 
-def solve_spectral(g: Geom, khat, F, alpha_rel: float):
-    """Tikhonov estimate at relative alpha; returns zeta on R, r on Y and their norms."""
-    s = (khat * khat.conj()).real
-    a = float(alpha_rel) * float(s.max())
+def solve_spectral(g: Geom, khat, F, alpha: float, relative: bool = False):
+    """Tikhonov estimate at alpha; returns zeta on R, r on Y and their norms."""
+    a = alpha_abs(khat, alpha, relative)
     fhat = np.fft.fftn(pad(g, np.asarray(F, dtype=np.float64)))
     uhat, rhat = spectral_filter(khat, fhat, a)
     zpad = np.fft.ifftn(uhat)

@@ -412,7 +412,7 @@ fr3d_status launch_ctrl(fr3d_ctx* c, const Ctrl& v) {
 
 Ctrl ctrl_base(fr3d_ctx* c) {
   Ctrl v{};
-  v.s_max = c->smax;
+  v.a_scale = c->g.alpha_relative ? c->smax : 1.0;
   v.delta = c->delta;
   v.tau = 1.0;
   v.h_op = 0.0;
@@ -555,6 +555,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   if (g->kind != 0 && g->kind != 1) return fail(c, FR3D_E_INVALID, "kind must be 0 or 1");
   if (g->precision != 32 && g->precision != 64) return fail(c, FR3D_E_INVALID, "precision must be 32 or 64");
   if (!std::isfinite(g->D)) return fail(c, FR3D_E_INVALID, "D must be finite");
+  if (g->alpha_relative != 0 && g->alpha_relative != 1) return fail(c, FR3D_E_INVALID, "alpha_relative must be 0 or 1");
   const double D = g->D > 0 ? g->D : (double)gap_default(g->nz, g->q);
   if (D < g->nz) return fail(c, FR3D_E_INVALID, "D must be >= nz (R and Y disjoint)");
   HIPCHK(c, hipSetDevice(c->device));
@@ -652,6 +653,7 @@ static fr3d_status run_search(fr3d_ctx* c, const Ctrl& init, int max_evals, void
 }
 
 fr3d_status fr3d_solve_alpha(fr3d_ctx* c, double alpha_rel, void* zeta, fr3d_report* rep) {
+  // alpha_rel is in the context's alpha units (geom.alpha_relative)
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, true)) return FR3D_E_STATE;
   if (!zeta) return fail(c, FR3D_E_INVALID, "zeta is null");
@@ -659,7 +661,7 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* c, double alpha_rel, void* zeta, fr3d_rep
   Ctrl v = ctrl_base(c);
   v.state = ST_FIXED;
   v.t = std::log10(alpha_rel);
-  v.alpha_abs = alpha_rel * c->smax;
+  v.alpha_abs = alpha_rel * v.a_scale;
   return run_search(c, v, 1, zeta, rep);
 }
 
@@ -686,7 +688,7 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
   v.mu = d.mu;
   v.state = ST_HI;
   v.t = v.hi;
-  v.alpha_abs = std::pow(10.0, v.hi) * c->smax;
+  v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
   return run_search(c, v, 2 + d.max_steps + 1, zeta, rep);
 }
 

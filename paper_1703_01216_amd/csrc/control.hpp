@@ -1,4 +1,5 @@
-// Device-resident control block of the alpha search.
+// Device-resident control block of the alpha search.  a_scale converts the
+// caller's alpha to the filter's: 1 (L2 units) or max |k^|^2 (relative).
 //
 // The regularisation parameter is chosen by the discrepancy principle
 // (Sec. 4, after Algorithm 1: Tikhonov's method with the discrepancy
@@ -43,13 +44,13 @@ enum : int32_t { F_NOROOT_HIGH = 1, F_NOROOT_LOW = 2, F_MAXITER = 4, F_NAN = 8, 
 
 struct Ctrl {
   // settings
-  double s_max, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi;
+  double a_scale, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi;
   int32_t max_steps;
   // state
   int32_t state, active, n_evals, flags, steps;
-  double t;          // log10 of the relative alpha being evaluated
+  double t;          // log10 of the alpha being evaluated (caller units)
   double a, b;       // bracket
-  double alpha_abs;  // 10^t * s_max, read by the filter
+  double alpha_abs;  // 10^t * a_scale, read by the filter
   double r2, z2;     // norms of the last evaluation
   double target;     // T of the last evaluation
   uint32_t ticket;   // last-workgroup counter of the final pass
@@ -58,7 +59,7 @@ struct Ctrl {
 
 __device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {
   c->t = t;
-  c->alpha_abs = pow(10.0, t) * c->s_max;
+  c->alpha_abs = pow(10.0, t) * c->a_scale;
 }
 
 __device__ __forceinline__ void ctrl_finish(Ctrl* c, int32_t flags) {

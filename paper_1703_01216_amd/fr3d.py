@@ -33,7 +33,7 @@ EXPORTED = [
 class Geom(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("h", ctypes.c_double), ("D", ctypes.c_double), ("kind", ctypes.c_int32),
-                ("q", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("q", ctypes.c_int32), ("precision", ctypes.c_int32), ("alpha_relative", ctypes.c_int32)]
 
 
 class DpOpts(ctypes.Structure):
@@ -169,17 +169,17 @@ class Context:
         self._chk(self._lib.fr3d_set_stream(self._ctx, ctypes.c_void_p(stream.cuda_stream)))
 
     # ------------------------------------------------------------ calls of include/fr3d.h
-    def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32):
-        g = Geom(nx, ny, nz, h, D, kind, q, precision)
+    def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0):
+        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative)
         self._chk(self._lib.fr3d_load_kernel(self._ctx, ctypes.byref(g)))
         self.geom = g
 
     def set_data(self, F, delta):
         self._chk(self._lib.fr3d_set_data(self._ctx, self._arr(F, "F"), float(delta)))
 
-    def solve_alpha(self, alpha_rel, zeta):
+    def solve_alpha(self, alpha, zeta):
         rep = Report()
-        self._chk(self._lib.fr3d_solve_alpha(self._ctx, float(alpha_rel), self._arr(zeta, "zeta"), ctypes.byref(rep)))
+        self._chk(self._lib.fr3d_solve_alpha(self._ctx, float(alpha), self._arr(zeta, "zeta"), ctypes.byref(rep)))
         return rep.as_dict()
 
     def solve_discrepancy(self, zeta, opts: DpOpts | None = None, **kw):

@@ -200,12 +200,13 @@ def test_circulant_direct_vs_fft():
 
 @pytest.mark.parametrize("shape,alpha", [((4, 4, 4), 1e-3), ((3, 4, 6), 1e-5), ((6, 6, 6), 1e-2)])
 def test_dense_normal_equations_equal_spectral(shape, alpha):
+    # relative scale: alpha_abs = alpha max|k^|^2
     nz, ny, nx = shape
     g = Geom(nx, ny, nz)
     k = sample_kernel(g)
     khat, s, smax = tikhonov.kernel_spectrum(k)
     F = inputs.rng(7).standard_normal(shape)
-    sp = tikhonov.solve_spectral(g, khat, F, alpha)
+    sp = tikhonov.solve_spectral(g, khat, F, alpha, relative=True)
     de = tikhonov.dense_tikhonov(g, k, F, alpha * smax)
     assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-10 * np.linalg.norm(de["zeta"])
     assert np.linalg.norm(sp["r"] - de["r"]) < 1e-10 * np.linalg.norm(de["r"])
@@ -225,7 +226,7 @@ def test_near_exact_recovery_of_band_limited_zeta(alpha):
     zh = np.fft.fftn(z) * (s >= 1e-3 * smax)
     zeta = np.fft.ifftn(zh).real
     f = np.fft.ifftn(khat * np.fft.fftn(zeta)).real
-    est, _ = tikhonov.solve_box(khat, f, alpha)
+    est, _ = tikhonov.solve_box(khat, f, alpha, relative=True)
     err = np.linalg.norm(est.real - zeta) / np.linalg.norm(zeta)
     assert err <= alpha / (1e-3 + alpha) * (1 + 1e-6) + 1e-13
 
@@ -246,12 +247,25 @@ def test_theorem1_error_decreases_with_noise():
         delta = np.linalg.norm(ee)
 
         def ev(a):
-            u, r = tikhonov.solve_box(khat, f, a)
+            u, r = tikhonov.solve_box(khat, f, a, relative=True)
             return np.linalg.norm(r.real), np.linalg.norm(u.real)
         res = discrepancy.bisection(ev, delta, lo=-14)
-        u, _ = tikhonov.solve_box(khat, f, res["alpha"])
+        u, _ = tikhonov.solve_box(khat, f, res["alpha"], relative=True)
         errs.append(np.linalg.norm(u.real - zeta) / np.linalg.norm(zeta))
     assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+
+
+def test_alpha_units_h_invariant():
+    # In L2 units the functional h^3 (||C u - f||^2 + alpha ||u||^2) has the
+    # same minimiser for every h once the table carries the weight h^3; the
+    # dense solve confirms the absolute scale used by default.
+    g = Geom(4, 4, 4, h=0.5, D=5)
+    k = sample_kernel(g)
+    khat, s, smax = tikhonov.kernel_spectrum(k)
+    F = inputs.rng(17).standard_normal(g.shape)
+    sp = tikhonov.solve_spectral(g, khat, F, 3e-6)
+    de = tikhonov.dense_tikhonov(g, k, F, 3e-6)
+    assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-9 * np.linalg.norm(de["zeta"])
 
 
 def test_full_box_residual_and_norm_monotone():
@@ -259,10 +273,10 @@ def test_full_box_residual_and_norm_monotone():
     khat, s, smax = tikhonov.kernel_spectrum(sample_kernel(g))
     F = inputs.rng(11).standard_normal(g.shape)
     ts = np.linspace(-8, 0, 33)
-    rf = [tikhonov.solve_spectral(g, khat, F, 10 ** t)["r_full"] for t in ts]
+    rf = [tikhonov.solve_spectral(g, khat, F, 10 ** t, relative=True)["r_full"] for t in ts]
     zn = []
     for t in ts:
-        u, _ = tikhonov.solve_box(khat, pad(g, F), 10 ** t)
+        u, _ = tikhonov.solve_box(khat, pad(g, F), 10 ** t, relative=True)
         zn.append(np.linalg.norm(u.real))
     assert all(rf[i + 1] > rf[i] for i in range(len(rf) - 1))
     assert all(zn[i + 1] < zn[i] for i in range(len(zn) - 1))
@@ -271,7 +285,7 @@ def test_full_box_residual_and_norm_monotone():
 # ---------------------------------------------------------------- discrepancy rule
 
 def _identity_problem(delta_frac, n=4):
-    # k = delta_0: k^ = 1, s = 1, alpha_abs = alpha; zeta = F/(1+alpha),
+    # k = delta_0: k^ = 1, s = 1 (both alpha scales agree); zeta = F/(1+alpha),
     # r = -alpha F/(1+alpha), so ||r|| = delta at alpha* = delta / (||F|| - delta).
     g = Geom(n, n, n)
     k = np.zeros(g.pshape)
@@ -283,6 +297,8 @@ def _identity_problem(delta_frac, n=4):
 
     def ev(a):
         out = tikhonov.solve_spectral(g, khat, F, a)
+        out2 = tikhonov.solve_spectral(g, khat, F, a, relative=True)
+        assert out["r_norm"] == out2["r_norm"]
         return out["r_norm"], out["zeta_norm"]
     return ev, delta, Fn
 
