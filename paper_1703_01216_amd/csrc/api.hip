@@ -30,16 +30,16 @@ __global__ void k_ctrl_init(Ctrl* c, Ctrl v) { *c = v; }
 template <typename T>
 __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, double inv_c02, double floor_,
                           T* __restrict__ c, long long n, unsigned long long* nclamp) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int cl = 0;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
+  __shared__ double red[NT / 64];
+  double cl = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const double xi = (double)zeta[i] / (double)V0[i];
     double arg = inv_c02 - xi;
-    if (arg < floor_) { arg = floor_; cl++; }
+    if (arg < floor_) { arg = floor_; cl += 1.0; }
     c[i] = (T)(1.0 / sqrt(arg));
   }
-  cl = (int)wave_sum<double>((double)cl);
-  if ((threadIdx.x & 63) == 0 && cl) atomicAdd(nclamp, (unsigned long long)cl);
+  cl = block_sum<NT>(cl, red);
+  if (threadIdx.x == 0 && cl > 0) atomicAdd(nclamp, (unsigned long long)cl);
 }
 
 // V0(x) = -(A0/4 pi) sum_l 1/|x - x_l| at R's cell centres (Sec. 6 point sources).
@@ -106,11 +106,13 @@ __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long lon
     F[i] = (T)((double)F[i] + f * (double)e[i]);
 }
 
-// max |k^|^2 over the octant (it covers every value of |k^| by symmetry).
-__global__ void k_smax(const double2* __restrict__ oct, long long n, double* out) {
+// max |k^|^2 over the octant (it covers every value of |k^| by symmetry):
+// per-block maxima, then the last block takes the maximum of those.
+__global__ void k_smax(const double2* __restrict__ oct, long long n, double* part, uint32_t* ticket, double* out) {
   __shared__ double red[NT];
+  __shared__ int last;
   double m = 0.0;
-  for (long long i = threadIdx.x; i < n; i += NT) {
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const double2 k = oct[i];
     m = fmax(m, k.x * k.x + k.y * k.y);
   }
@@ -120,7 +122,27 @@ __global__ void k_smax(const double2* __restrict__ oct, long long n, double* out
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0];
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  m = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += NT)
+    m = fmax(m, __hip_atomic_load(&part[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out = red[0];
+    *ticket = 0u;
+  }
 }
 
 }  // namespace
@@ -258,20 +280,20 @@ fr3d_status ensure(fr3d_ctx* c, void** p, size_t& have, size_t need) {
 }
 
 // --------------------------------------------------------------- timing
-void tbegin(fr3d_ctx* c, int pass, hipEvent_t* e1) {
-  *e1 = nullptr;
-  if (!c->timing) return;
+// With timing on, each pass kernel is launched with an event pair recorded at
+// its own start and end.
+Launch mkL(fr3d_ctx* c, int pass) {
+  Launch L{c->stream, nullptr, nullptr};
+  if (!c->timing) return L;
   std::pair<hipEvent_t, hipEvent_t> p;
   if (!c->ev_pool.empty()) { p = c->ev_pool.back(); c->ev_pool.pop_back(); }
-  else { (void)hipEventCreate(&p.first); (void)hipEventCreate(&p.second); }
-  (void)hipEventRecord(p.first, c->stream);
+  else if (hipEventCreate(&p.first) != hipSuccess || hipEventCreate(&p.second) != hipSuccess) return L;
   c->ev[pass].push_back(p);
-  *e1 = p.first;
+  L.e0 = p.first;
+  L.e1 = p.second;
+  return L;
 }
-void tend(fr3d_ctx* c, int pass) {
-  if (!c->timing) return;
-  (void)hipEventRecord(c->ev[pass].back().second, c->stream);
-}
+
 // Accumulate recorded pass times.  keep_inv >= 0 counts only the first
 // keep_inv launches of each inverse pass (the later launches of a search
 // return at once after the search has finished).
@@ -371,16 +393,9 @@ template <typename T> fr3d_status forward_data(fr3d_ctx* c, const T* F) {
     return FR3D_E_DEVICE;
   Bufs<T> b = bufs<T>(c);
   FwdArgs a = fwd_args(c, false);
-  hipEvent_t e;
-  tbegin(c, 0, &e);
-  LCHK(c, launch_fx<T>(c->px, false, F, b.A, a, (const c2<T>*)twx, c->stream));
-  tend(c, 0);
-  tbegin(c, 1, &e);
-  LCHK(c, launch_fy<T>(c->py, true, b.A, b.B, a, (const c2<T>*)twy, c->stream));
-  tend(c, 1);
-  tbegin(c, 2, &e);
-  LCHK(c, launch_fz<T>(c->pz, 0, b.B, b.S, a, (const c2<T>*)twz, c->stream));
-  tend(c, 2);
+  LCHK(c, launch_fx<T>(c->px, false, F, b.A, a, (const c2<T>*)twx, mkL(c, 0)));
+  LCHK(c, launch_fy<T>(c->py, true, b.A, b.B, a, (const c2<T>*)twy, mkL(c, 1)));
+  LCHK(c, launch_fz<T>(c->pz, 0, b.B, b.S, a, (const c2<T>*)twz, mkL(c, 2)));
   return FR3D_OK;
 }
 
@@ -391,16 +406,9 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, int mode, T* out) {
     return FR3D_E_DEVICE;
   Bufs<T> b = bufs<T>(c);
   InvArgs a = inv_args(c, mode == 0);
-  hipEvent_t e;
-  tbegin(c, 3, &e);
-  LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, c->stream));
-  tend(c, 3);
-  tbegin(c, 4, &e);
-  LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, c->stream));
-  tend(c, 4);
-  tbegin(c, 5, &e);
-  LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, c->stream));
-  tend(c, 5);
+  LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, 3)));
+  LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, 4)));
+  LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, 5)));
   return FR3D_OK;
 }
 
@@ -594,11 +602,14 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
     return st;
   }
   FwdArgs a = fwd_args(c, true);
-  hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, c->stream);
-  if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, c->stream);
-  if (le == hipSuccess) le = launch_fz<double>(c->pz, 1, Bk, c->oct, a, (const double2*)twz, c->stream);
+  const Launch L{c->stream, nullptr, nullptr};
+  hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, L);
+  if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, L);
+  if (le == hipSuccess) le = launch_fz<double>(c->pz, 1, Bk, c->oct, a, (const double2*)twz, L);
   if (le == hipSuccess) {
-    hipLaunchKernelGGL(k_smax, dim3(1), dim3(NT), 0, c->stream, c->oct, (long long)noct, c->scal);
+    const unsigned nb = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 1024);
+    hipLaunchKernelGGL(k_smax, dim3(nb), dim3(NT), 0, c->stream, c->oct, (long long)noct, (double*)Ak,
+                       c->tickets + 3, c->scal);
     le = hipGetLastError();
   }
   if (le == hipSuccess) le = hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -701,12 +712,12 @@ fr3d_status fr3d_recover_c(fr3d_ctx* c, const void* zeta, const void* V0, double
   HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
   const long long n = ncells(c);
   const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
-  dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 4096));
+  dim3 grid((unsigned)std::min<long long>((n + NT - 1) / NT, 2048));
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_recover<double>, grid, dim3(256), 0, c->stream, (const double*)zeta, (const double*)V0, ic2,
+    hipLaunchKernelGGL(k_recover<double>, grid, dim3(NT), 0, c->stream, (const double*)zeta, (const double*)V0, ic2,
                        fl, (double*)cout, n, cnt);
   else
-    hipLaunchKernelGGL(k_recover<float>, grid, dim3(256), 0, c->stream, (const float*)zeta, (const float*)V0, ic2, fl,
+    hipLaunchKernelGGL(k_recover<float>, grid, dim3(NT), 0, c->stream, (const float*)zeta, (const float*)V0, ic2, fl,
                        (float*)cout, n, cnt);
   LCHK(c, hipGetLastError());
   if (ncl) {
@@ -767,7 +778,7 @@ fr3d_status fr3d_add_noise(fr3d_ctx* c, void* F, const void* e, double delta_rel
   if (!F || !e) return fail(c, FR3D_E_INVALID, "null array");
   if (!(delta_rel >= 0) || !std::isfinite(delta_rel)) return fail(c, FR3D_E_INVALID, "delta_rel must be >= 0");
   const long long n = ncells(c);
-  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, (long long)c->norm_part_n);
+  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, std::min<long long>(1024, (long long)c->norm_part_n));
   double* nrm = c->scal + 2;
   if (c->esz == 8)
     hipLaunchKernelGGL(k_norms2<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)F, (const double*)e, n,

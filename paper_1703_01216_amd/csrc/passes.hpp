@@ -60,7 +60,7 @@ struct FwdArgs {
   int kind;
   // energy epilogue
   BinGeom bg;
-  double* bins_part;  // [gridDim][64]
+  double* bins_part;  // [z-pass workgroups][64]
   double* bins_out;   // [64] energies
   float* feat_out;    // [65] features
   uint32_t* ticket;
@@ -78,22 +78,30 @@ struct InvArgs {
 };
 
 // ------------------------------------------------------------------ host launchers
+// Stream and, when timing, the event pair recorded at the pass kernel's start
+// and end (hipExtLaunchKernel).
+struct Launch {
+  hipStream_t s;
+  hipEvent_t e0, e1;
+};
+
 // Each returns hipSuccess or the launch error; P is the transform length of
 // the pass axis and selects the compiled instance.
 template <typename T>
-hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
+hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>
-hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
-// mode 0: data (pruned input, full output, energy epilogue); 1: kernel (full input, octant output)
+hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, const Launch& L);
+// mode 0: data (pruned input, full output, energy partials + final features kernel);
+// mode 1: kernel (full input, octant output)
 template <typename T>
-hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, hipStream_t s);
+hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, const Launch& L);
 // mode 0: Tikhonov filter (u^, r^); 1: multiply by k^ (forward operator)
 template <typename T>
-hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>
-hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>
-hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, hipStream_t s);
+hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, const Launch& L);
 
 bool supported_length(int P);
 

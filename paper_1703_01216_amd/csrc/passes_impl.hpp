@@ -1,9 +1,20 @@
 // Pass kernels of the padded 3D transforms (layouts in passes.hpp).  Included
 // by one translation unit per precision, which instantiates the launchers.
+//
+// Every kernel first issues all of its global loads into registers, then
+// writes the tile to LDS, so each wave keeps its whole share of the tile in
+// flight at once; stores go straight from LDS to memory.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "passes.hpp"
 
 namespace fr3d {
+
+template <int TOTAL> struct Per {
+  static constexpr int n = (TOTAL + NT - 1) / NT;  // elements per thread
+  static __device__ __forceinline__ bool ok(int e) { return TOTAL % NT == 0 || e < TOTAL; }
+};
 
 // ============================================================ forward x pass
 // Real-to-complex transform along x.  Two real rows share one complex pencil
@@ -35,22 +46,35 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
   const int y0 = blockIdx.x * (2 * C);
-  load_twiddles<T, P, NT>(tw, twg, tid);
+  const c2<T> twv = twg[tid % P];
   T* ldsr = reinterpret_cast<T*>(lds);
   if constexpr (!GEN) {
-    // rows y0 .. y0+2C-1 of plane z are contiguous: 2C*N floats
+    // rows y0 .. y0+2C-1 of plane z are contiguous: 2C*N values
+    constexpr int TOT = 2 * C * N;
+    using PE = Per<TOT>;
     const int rows = min(2 * C, a.ny_in - y0);
     const T* src = F + ((size_t)z * a.ny_in + y0) * N;
-    for (int e = tid; e < 2 * C * N; e += NT) {
-      const int r = e / N, x = e % N;
-      const T v = r < rows ? src[e] : (T)0;
-      ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = v;
+    T v[PE::n];
+#pragma unroll
+    for (int i = 0; i < PE::n; ++i) {
+      const int e = tid + i * NT;
+      v[i] = (PE::ok(e) && e / N < rows) ? src[e] : (T)0;
+    }
+    if (tid < P) tw[tid] = twv;
+#pragma unroll
+    for (int i = 0; i < PE::n; ++i) {
+      const int e = tid + i * NT;
+      if (PE::ok(e)) {
+        const int r = e / N, x = e % N;
+        ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = v[i];
+      }
     }
     for (int e = tid; e < C * (P - N); e += NT) {
       const int c = e / (P - N), x = N + e % (P - N);
       lds[c * LD + x] = mk<T>(0, 0);
     }
   } else {
+    if (tid < P) tw[tid] = twv;
     for (int e = tid; e < 2 * C * P; e += NT) {
       const int r = e / P, x = e % P;
       const int yb = y0 + r;
@@ -63,6 +87,7 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = (T)v;
     }
   }
+  for (int m = tid + NT; m < P; m += NT) tw[m] = twg[m];
   __syncthreads();
   tile_fft<T, P, C, LD, NT, false, -1>(lds, tw, tid);
   const int kxn = P / 2 + 1;
@@ -88,17 +113,26 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
   constexpr int C = Tile<T, P>::C;
   constexpr int LD = P + 1;
   constexpr int NIN = PRUNE ? P / 2 : P;
+  constexpr int TOT = C * NIN;
+  using PE = Per<TOT>;
   __shared__ c2<T> lds[C * LD];
   __shared__ c2<T> tw[P];
   const int tid = threadIdx.x;
   const long long nrows = (long long)a.kx_n * a.nz_in;
   const long long row0 = (long long)blockIdx.x * C;
   const int rows = (int)min((long long)C, nrows - row0);
-  load_twiddles<T, P, NT>(tw, twg, tid);
   const c2<T>* src = A + row0 * NIN;
-  for (int e = tid; e < C * NIN; e += NT) {
-    const int r = e / NIN, y = e % NIN;
-    lds[r * LD + y] = r < rows ? src[e] : mk<T>(0, 0);
+  c2<T> v[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    v[i] = (PE::ok(e) && e / NIN < rows) ? src[e] : mk<T>(0, 0);
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (PE::ok(e)) lds[(e / NIN) * LD + e % NIN] = v[i];
   }
   if constexpr (PRUNE) {
     for (int e = tid; e < C * (P - NIN); e += NT) {
@@ -109,17 +143,14 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
   __syncthreads();
   tile_fft<T, P, C, LD, NT, false, -1>(lds, tw, tid);
   c2<T>* dst = B + row0 * P;
-  for (int e = tid; e < rows * P; e += NT) {
-    const int r = e / P, y = e % P;
-    dst[e] = lds[r * LD + y];
-  }
+  for (int e = tid; e < rows * P; e += NT) dst[e] = lds[(e / P) * LD + e % P];
 }
 
 // ============================================================ forward z pass
 // Complex transform along z of C consecutive ky-columns of one kx plane.
-// MODE 0 (data): n inputs, P outputs, fused radial-energy epilogue whose last
-// workgroup also forms the predictor features.  MODE 1 (kernel spectrum): P
-// inputs, only kz <= P/2 and ky <= Py/2 stored (the octant).
+// MODE 0 (data): n inputs, P outputs, fused radial-energy epilogue writing
+// per-workgroup bin partials.  MODE 1 (kernel spectrum): P inputs, only
+// kz <= P/2 and ky <= Py/2 stored (the octant).
 template <typename T, int P, int MODE>
 __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* __restrict__ S, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
@@ -127,21 +158,29 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   constexpr int LD = C;
   constexpr int NIN = MODE == 0 ? P / 2 : P;
   constexpr int NOUT = MODE == 0 ? P : P / 2 + 1;
+  constexpr int TOT = C * NIN;
+  using PE = Per<TOT>;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double bins[64];
-  __shared__ int last;
   const int tid = threadIdx.x;
   const int kx = blockIdx.y;
   const int ky0 = blockIdx.x * C;
   const int py = a.py;
-  load_twiddles<T, P, NT>(tw, twg, tid);
-  if (MODE == 0 && tid < 64) bins[tid] = 0.0;
   const c2<T>* src = B + (size_t)kx * NIN * py;
-  for (int e = tid; e < C * NIN; e += NT) {
-    const int z = e / C, col = e % C;
-    const int ky = ky0 + col;
-    lds[z * LD + col] = ky < py ? src[(size_t)z * py + ky] : mk<T>(0, 0);
+  c2<T> v[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    const int ky = ky0 + e % C;
+    v[i] = (PE::ok(e) && ky < py) ? src[(size_t)(e / C) * py + ky] : mk<T>(0, 0);
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+  if (MODE == 0 && tid < 64) bins[tid] = 0.0;
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (PE::ok(e)) lds[e] = v[i];  // row e / C, column e % C
   }
   if constexpr (NIN < P) {
     for (int e = tid; e < C * (P - NIN); e += NT) lds[NIN * LD + e] = mk<T>(0, 0);
@@ -157,56 +196,27 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       const int kz = e / C, col = e % C;
       const int ky = ky0 + col;
       if (ky >= py) continue;
-      const c2<T> v = lds[kz * LD + col];
-      dst[(size_t)kz * py + ky] = v;
+      const c2<T> u = lds[e];
+      dst[(size_t)kz * py + ky] = u;
       const int b = energy_bin(a.bg, kx, ky, kz);
       if (b != cur) {
         if (cur >= 0) atomicAdd(&bins[cur], acc);
         cur = b;
         acc = 0.0;
       }
-      acc += w * ((double)v.x * v.x + (double)v.y * v.y);
+      acc += w * ((double)u.x * u.x + (double)u.y * u.y);
     }
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();
-    const int nblk = gridDim.x * gridDim.y;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (tid < 64) a.bins_part[(size_t)bid * 64 + tid] = bins[tid];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(a.ticket, 1u) == (unsigned)(nblk - 1));
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // deterministic final sum: bin = tid & 63, four partial lanes per bin
-    double s = 0.0;
-    const int bin = tid & 63, part = tid >> 6;
-    for (int k = part; k < nblk; k += NT / 64)
-      s += __hip_atomic_load(&a.bins_part[(size_t)k * 64 + bin], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (part == 0) bins[bin] = 0.0;
-    __syncthreads();
-    for (int p = 0; p < NT / 64; ++p) {
-      if (part == p) bins[bin] += s;
-      __syncthreads();
-    }
-    if (tid < 64) a.bins_out[tid] = bins[tid];
-    if (tid == 0) {
-      double tot = 0.0;
-      for (int b = 0; b < 64; ++b) tot += bins[b];
-      const double mean = tot / 64.0;
-      for (int b = 0; b < 64; ++b) a.feat_out[b] = (float)log10(bins[b] / mean + 1e-30);
-      const double fnorm = sqrt(tot / ((double)a.bg.px * a.bg.py * a.bg.pz));
-      a.feat_out[64] = (float)log10(a.delta / fnorm);
-      *a.ticket = 0u;
-    }
   } else {
     const int oy = py / 2 + 1;
     c2<T>* dst = S + (size_t)kx * NOUT * oy;
     for (int e = tid; e < C * NOUT; e += NT) {
       const int kz = e / C, col = e % C;
       const int ky = ky0 + col;
-      if (ky < oy) dst[(size_t)kz * oy + ky] = lds[kz * LD + col];
+      if (ky < oy) dst[(size_t)kz * oy + ky] = lds[e];
     }
   }
 }
@@ -216,14 +226,18 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 // coefficients from the octant of k^, rounded to T):
 //   MODE 0: u^ = conj(k^) f^ / (s + a),  r^ = -a f^ / (s + a)   (Tikhonov, s = |k^|^2)
 //   MODE 1: u^ = k^ f^,  r^ = 0                                  (forward operator)
-// transforms both along z and writes z < nz as (u, r) pairs.
+// transforms u^ and then r^ along z in the same LDS tile and writes z < nz
+// as (u, r) pairs.
 template <typename T, int P, int MODE>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C / 2 > 0 ? Tile<T, P>::C / 2 : 1;
-  constexpr int NC = 2 * C;
-  constexpr int LD = NC;
+  constexpr int C = Tile<T, P>::C;
+  constexpr int LD = C;
   constexpr int NOUT = P / 2;
+  constexpr int TOT = C * P;
+  constexpr int TOTO = C * NOUT;
+  using PE = Per<TOT>;
+  using PO = Per<TOTO>;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   if (a.ctrl && !a.ctrl->active) return;
@@ -233,44 +247,68 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int ky0 = blockIdx.x * C;
   const int py = a.py;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
-  load_twiddles<T, P, NT>(tw, twg, tid);
   const c2<T>* src = S + (size_t)kx * P * py;
   const double2* oc = a.oct + (size_t)kx * oz * oy;
-  for (int e = tid; e < C * P; e += NT) {
-    const int kz = e / C, col = e % C;
-    const int ky = ky0 + col;
-    c2<T> u = mk<T>(0, 0), r = mk<T>(0, 0);
-    if (ky < py) {
-      const c2<T> f = src[(size_t)kz * py + ky];
-      const int mz = kz <= P / 2 ? kz : P - kz;
-      const int my = ky <= py / 2 ? ky : py - ky;
-      double2 k = oc[(size_t)mz * oy + my];
-      if (kz > P / 2) k.y = -k.y;
-      const double fx = (double)f.x, fy = (double)f.y;
-      if constexpr (MODE == 0) {
-        const double s = k.x * k.x + k.y * k.y;
-        const double d = 1.0 / (s + aa);
-        const double cx = k.x * d, cy = -k.y * d;  // conj(k^) / (s + a)
-        u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
-        const double cr = -aa * d;
-        r = mk<T>((T)(fx * cr), (T)(fy * cr));
-      } else {
-        u = mk<T>((T)(fx * k.x - fy * k.y), (T)(fx * k.y + fy * k.x));
-      }
+  c2<T> f[PE::n];
+  double2 k[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    const int kz = e / C, ky = ky0 + e % C;
+    const bool ok = PE::ok(e) && ky < py;
+    const int mz = kz <= P / 2 ? kz : P - kz;
+    const int my = ky <= py / 2 ? ky : py - ky;
+    f[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
+    k[i] = ok ? oc[(size_t)mz * oy + my] : make_double2(0.0, 0.0);
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+  c2<T> r[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    const int kz = e / C;
+    double2 kk = k[i];
+    if (kz > P / 2) kk.y = -kk.y;
+    const double fx = (double)f[i].x, fy = (double)f[i].y;
+    c2<T> u;
+    if constexpr (MODE == 0) {
+      const double s = kk.x * kk.x + kk.y * kk.y;
+      const double d = 1.0 / (s + aa);
+      const double cx = kk.x * d, cy = -kk.y * d;  // conj(k^) / (s + a)
+      u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
+      const double cr = -aa * d;
+      r[i] = mk<T>((T)(fx * cr), (T)(fy * cr));
+    } else {
+      u = mk<T>((T)(fx * kk.x - fy * kk.y), (T)(fx * kk.y + fy * kk.x));
+      r[i] = mk<T>(0, 0);
     }
-    lds[kz * LD + col] = u;
-    lds[kz * LD + C + col] = r;
+    if (PE::ok(e)) lds[e] = u;
   }
   __syncthreads();
-  tile_fft<T, P, NC, LD, NT, true, +1>(lds, tw, tid);
+  tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+  c2<T> uo[PO::n];
+#pragma unroll
+  for (int i = 0; i < PO::n; ++i) {
+    const int e = tid + i * NT;
+    uo[i] = PO::ok(e) ? lds[e] : mk<T>(0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (PE::ok(e)) lds[e] = r[i];
+  }
+  __syncthreads();
+  if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
   c4<T>* dst = W1 + (size_t)kx * NOUT * py;
-  for (int e = tid; e < C * NOUT; e += NT) {
-    const int z = e / C, col = e % C;
-    const int ky = ky0 + col;
-    if (ky >= py) continue;
-    const c2<T> u = lds[z * LD + col], r = lds[z * LD + C + col];
+#pragma unroll
+  for (int i = 0; i < PO::n; ++i) {
+    const int e = tid + i * NT;
+    const int z = e / C, ky = ky0 + e % C;
+    if (!PO::ok(e) || ky >= py) continue;
+    const c2<T> w = lds[e];
     c4<T> v;
-    v.x = u.x; v.y = u.y; v.z = r.x; v.w = r.y;
+    v.x = uo[i].x; v.y = uo[i].y; v.z = w.x; v.w = w.y;
     dst[(size_t)z * py + ky] = v;
   }
 }
@@ -284,6 +322,8 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
   constexpr int NC = 2 * C;
   constexpr int LD = P + 1;
   constexpr int NOUT = P / 2;
+  constexpr int TOT = C * P;
+  using PE = Per<TOT>;
   __shared__ c2<T> lds[NC * LD];
   __shared__ c2<T> tw[P];
   if (a.ctrl && !a.ctrl->active) return;
@@ -291,15 +331,22 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
   const long long nrows = (long long)a.kx_n * a.nz;
   const long long row0 = (long long)blockIdx.x * C;
   const int rows = (int)min((long long)C, nrows - row0);
-  load_twiddles<T, P, NT>(tw, twg, tid);
   const c4<T>* src = W1 + row0 * P;
-  for (int e = tid; e < C * P; e += NT) {
+  c4<T> v[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (PE::ok(e) && e / P < rows) v[i] = src[e];
+    else { v[i].x = v[i].y = v[i].z = v[i].w = (T)0; }
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (!PE::ok(e)) continue;
     const int r = e / P, y = e % P;
-    c4<T> v;
-    if (r < rows) v = src[e];
-    else { v.x = v.y = v.z = v.w = (T)0; }
-    lds[(2 * r) * LD + y] = mk<T>(v.x, v.y);
-    lds[(2 * r + 1) * LD + y] = mk<T>(v.z, v.w);
+    lds[(2 * r) * LD + y] = mk<T>(v[i].x, v[i].y);
+    lds[(2 * r + 1) * LD + y] = mk<T>(v[i].z, v[i].w);
   }
   __syncthreads();
   tile_fft<T, P, NC, LD, NT, false, +1>(lds, tw, tid);
@@ -307,9 +354,9 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
   for (int e = tid; e < rows * NOUT; e += NT) {
     const int r = e / NOUT, y = e % NOUT;
     const c2<T> u = lds[(2 * r) * LD + y], w = lds[(2 * r + 1) * LD + y];
-    c4<T> v;
-    v.x = u.x; v.y = u.y; v.z = w.x; v.w = w.y;
-    dst[e] = v;
+    c4<T> o;
+    o.x = u.x; o.y = u.y; o.z = w.x; o.w = w.y;
+    dst[e] = o;
   }
 }
 
@@ -327,6 +374,8 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   constexpr int LD = C + 1;
   constexpr int NOUT = P / 2;
   constexpr int KXN = P / 2 + 1;
+  constexpr int TOT = C * KXN;
+  using PE = Per<TOT>;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double red[NT / 64];
@@ -336,16 +385,23 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   const int z = blockIdx.y;
   const int y0 = blockIdx.x * C;
   const int ny = a.ny;
-  load_twiddles<T, P, NT>(tw, twg, tid);
-  for (int e = tid; e < C * KXN; e += NT) {
+  c4<T> v[PE::n];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    const int kx = e / C, y = y0 + e % C;
+    if (PE::ok(e) && y < ny) v[i] = W2[((size_t)kx * a.nz + z) * ny + y];
+    else { v[i].x = v[i].y = v[i].z = v[i].w = (T)0; }
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+#pragma unroll
+  for (int i = 0; i < PE::n; ++i) {
+    const int e = tid + i * NT;
+    if (!PE::ok(e)) continue;
     const int kx = e / C, col = e % C;
-    const int y = y0 + col;
-    c4<T> v;
-    if (y < ny) v = W2[((size_t)kx * a.nz + z) * ny + y];
-    else { v.x = v.y = v.z = v.w = (T)0; }
     // Z(kx) = U + iR
-    lds[kx * LD + col] = mk<T>(v.x - v.w, v.y + v.z);
-    if (kx > 0 && kx < P / 2) lds[(P - kx) * LD + col] = mk<T>(v.x + v.w, v.z - v.y);
+    lds[kx * LD + col] = mk<T>(v[i].x - v[i].w, v[i].y + v[i].z);
+    if (kx > 0 && kx < P / 2) lds[(P - kx) * LD + col] = mk<T>(v[i].x + v[i].w, v[i].z - v[i].y);
   }
   __syncthreads();
   tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
@@ -355,8 +411,8 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   const int rows = min(C, ny - y0);
   for (int e = tid; e < rows * NOUT; e += NT) {
     const int col = e / NOUT, x = e % NOUT;
-    const c2<T> v = lds[x * LD + col];
-    const T zeta = v.x * sc, res = v.y * sc;
+    const c2<T> u = lds[x * LD + col];
+    const T zeta = u.x * sc, res = u.y * sc;
     dst[e] = zeta;
     zz += (double)zeta * zeta;
     rr += (double)res * res;
@@ -388,6 +444,39 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   }
 }
 
+// Radial energies and predictor features from the z pass's per-workgroup bin
+// partials: workgroup b sums bin b over all partials in a fixed order; the
+// last workgroup forms x_b = log10(E_b / mean E + 1e-30) and
+// x_64 = log10(delta / ||F||) with ||F||^2 = sum E / (Px Py Pz) (Parseval).
+static __global__ __launch_bounds__(NT) void k_bins_final(FwdArgs a, int nblk) {
+  __shared__ double red[NT / 64];
+  __shared__ int last;
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += NT) s += a.bins_part[(size_t)k * 64 + b];
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) {
+    a.bins_out[b] = s;
+    __threadfence();
+    last = (atomicAdd(a.ticket, 1u) == 63u);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double E[64], tot = 0.0;
+    for (int i = 0; i < 64; ++i) {
+      E[i] = __hip_atomic_load(&a.bins_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tot += E[i];
+    }
+    const double mean = tot / 64.0;
+    for (int i = 0; i < 64; ++i) a.feat_out[i] = (float)log10(E[i] / mean + 1e-30);
+    const double fnorm = sqrt(tot / ((double)a.bg.px * a.bg.py * a.bg.pz));
+    a.feat_out[64] = (float)log10(a.delta / fnorm);
+    *a.ticket = 0u;
+  }
+}
+
 // ============================================================ dispatch
 #define FR3D_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
@@ -404,124 +493,118 @@ inline bool supported_length_impl(int P) {
 
 static inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+template <typename K, typename... Args>
+static inline hipError_t go(K kern, dim3 g, const Launch& L, Args... args) {
+  if (L.e0) hipExtLaunchKernelGGL(kern, g, dim3(NT), 0, L.s, L.e0, L.e1, 0, args...);
+  else hipLaunchKernelGGL(kern, g, dim3(NT), 0, L.s, args...);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, hipStream_t s) {
+hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    dim3 g(cdiv(a.ny_in, 2 * Tile<T, p>::C), a.nz_in);                                         \
-    if (gen) hipLaunchKernelGGL((k_fx<T, p, true>), g, dim3(NT), 0, s, F, A, a, tw);           \
-    else hipLaunchKernelGGL((k_fx<T, p, false>), g, dim3(NT), 0, s, F, A, a, tw);              \
-    break;                                                                                     \
+#define X(p)                                                                                         \
+  case p: {                                                                                          \
+    dim3 g(cdiv(a.ny_in, 2 * Tile<T, p>::C), a.nz_in);                                               \
+    return gen ? go(k_fx<T, p, true>, g, L, F, A, a, tw) : go(k_fx<T, p, false>, g, L, F, A, a, tw); \
   }
     FR3D_SIZES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, hipStream_t s) {
+hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   const long long nrows = (long long)a.kx_n * a.nz_in;
   switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    dim3 g(cdiv(nrows, Tile<T, p>::C));                                                        \
-    if (prune) hipLaunchKernelGGL((k_fy<T, p, true>), g, dim3(NT), 0, s, A, B, a, tw);         \
-    else hipLaunchKernelGGL((k_fy<T, p, false>), g, dim3(NT), 0, s, A, B, a, tw);              \
-    break;                                                                                     \
+#define X(p)                                                                                             \
+  case p: {                                                                                              \
+    dim3 g(cdiv(nrows, Tile<T, p>::C));                                                                  \
+    return prune ? go(k_fy<T, p, true>, g, L, A, B, a, tw) : go(k_fy<T, p, false>, g, L, A, B, a, tw);   \
   }
     FR3D_SIZES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, hipStream_t s) {
+hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    const int cols = mode == 0 ? a.py : a.py / 2 + 1;                                          \
-    dim3 g(cdiv(cols, Tile<T, p>::C), a.kx_n);                                                 \
-    if (mode == 0) hipLaunchKernelGGL((k_fz<T, p, 0>), g, dim3(NT), 0, s, B, S, a, tw);        \
-    else hipLaunchKernelGGL((k_fz<T, p, 1>), g, dim3(NT), 0, s, B, S, a, tw);                  \
-    break;                                                                                     \
+#define X(p)                                                                                             \
+  case p: {                                                                                              \
+    const int cols = mode == 0 ? a.py : a.py / 2 + 1;                                                    \
+    dim3 g(cdiv(cols, Tile<T, p>::C), a.kx_n);                                                           \
+    if (mode != 0) return go(k_fz<T, p, 1>, g, L, B, S, a, tw);                                          \
+    hipError_t e = go(k_fz<T, p, 0>, g, L, B, S, a, tw);                                                 \
+    if (e != hipSuccess) return e;                                                                       \
+    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                   \
+    return hipGetLastError();                                                                            \
   }
     FR3D_SIZES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L) {
+  switch (P) {
+#define X(p)                                                                                               \
+  case p: {                                                                                                \
+    dim3 g(cdiv(a.py, Tile<T, p>::C), a.kx_n);                                                             \
+    return mode == 0 ? go(k_iz<T, p, 0>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1>, g, L, S, W1, a, tw);      \
+  }
+    FR3D_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename T> constexpr int half_tile(int c) { return c / 2 > 0 ? c / 2 : 1; }
 
 template <typename T>
-hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, hipStream_t s) {
-  switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    dim3 g(cdiv(a.py, half_tile<T>(Tile<T, p>::C)), a.kx_n);                                   \
-    if (mode == 0) hipLaunchKernelGGL((k_iz<T, p, 0>), g, dim3(NT), 0, s, S, W1, a, tw);       \
-    else hipLaunchKernelGGL((k_iz<T, p, 1>), g, dim3(NT), 0, s, S, W1, a, tw);                 \
-    break;                                                                                     \
-  }
-    FR3D_SIZES(X)
-#undef X
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, hipStream_t s) {
+hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   const long long nrows = (long long)a.kx_n * a.nz;
   switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    dim3 g(cdiv(nrows, half_tile<T>(Tile<T, p>::C)));                                          \
-    hipLaunchKernelGGL((k_iy<T, p>), g, dim3(NT), 0, s, W1, W2, a, tw);                        \
-    break;                                                                                     \
+#define X(p)                                                  \
+  case p: {                                                   \
+    dim3 g(cdiv(nrows, half_tile<T>(Tile<T, p>::C)));         \
+    return go(k_iy<T, p>, g, L, W1, W2, a, tw);               \
   }
     FR3D_SIZES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, hipStream_t s) {
+hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                   \
-  case p: {                                                                                    \
-    dim3 g(cdiv(a.ny, Tile<T, p>::C), a.nz);                                                   \
-    if (mode == 0) hipLaunchKernelGGL((k_ix<T, p, 0>), g, dim3(NT), 0, s, W2, out, a, tw);     \
-    else hipLaunchKernelGGL((k_ix<T, p, 1>), g, dim3(NT), 0, s, W2, out, a, tw);               \
-    break;                                                                                     \
+#define X(p)                                                                                               \
+  case p: {                                                                                                \
+    dim3 g(cdiv(a.ny, Tile<T, p>::C), a.nz);                                                               \
+    return mode == 0 ? go(k_ix<T, p, 0>, g, L, W2, out, a, tw) : go(k_ix<T, p, 1>, g, L, W2, out, a, tw);  \
   }
     FR3D_SIZES(X)
 #undef X
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 #define FR3D_INST(T)                                                                                          \
-  template hipError_t launch_fx<T>(int, bool, const T*, c2<T>*, const FwdArgs&, const c2<T>*, hipStream_t);   \
-  template hipError_t launch_fy<T>(int, bool, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, hipStream_t); \
-  template hipError_t launch_fz<T>(int, int, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, hipStream_t);  \
-  template hipError_t launch_iz<T>(int, int, const c2<T>*, c4<T>*, const InvArgs&, const c2<T>*, hipStream_t);  \
-  template hipError_t launch_iy<T>(int, const c4<T>*, c4<T>*, const InvArgs&, const c2<T>*, hipStream_t);       \
-  template hipError_t launch_ix<T>(int, int, const c4<T>*, T*, const InvArgs&, const c2<T>*, hipStream_t);
+  template hipError_t launch_fx<T>(int, bool, const T*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&); \
+  template hipError_t launch_fy<T>(int, bool, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&); \
+  template hipError_t launch_fz<T>(int, int, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&);  \
+  template hipError_t launch_iz<T>(int, int, const c2<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);  \
+  template hipError_t launch_iy<T>(int, const c4<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);       \
+  template hipError_t launch_ix<T>(int, int, const c4<T>*, T*, const InvArgs&, const c2<T>*, const Launch&);
 
 }  // namespace fr3d

@@ -255,10 +255,13 @@ def test_deterministic(fr3d):
     assert outs[0][1] == outs[1][1]
 
 
-@pytest.mark.parametrize("index", [0, 1])
+@pytest.mark.parametrize("index", [0, 1, 2])
 def test_workload2_full_size(fr3d, index):
     # 128^3 grids padded to 256^3, FP32 transforms, bisection to the
-    # discrepancy; oracle evaluated at the device's alpha.
+    # discrepancy; the oracle is evaluated at the device's alpha.  With 1%
+    # noise the residual on Y stays above delta down to alpha = 1e-8 (the
+    # padded data's block edges are not fitted there), so the rule returns
+    # NOROOT_LOW; the oracle must agree that no root lies in the range.
     from paper_1703_01216_amd import inputs
     from oracle import synth
     inst = inputs.workload_instance(2, index)
@@ -270,9 +273,15 @@ def test_workload2_full_size(fr3d, index):
     c.set_data(Fd, d["delta"])
     zeta = torch.empty_like(Fd)
     rep = c.solve_discrepancy(zeta)
-    assert rep["flags"] == 0
-    o = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), Fh, rep["alpha"])
-    assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + 1e-5
+    khat = np.fft.fftn(sample_kernel(g))
+    o = tikhonov.solve_spectral(g, khat, Fh, rep["alpha"])
     err = rel_l2(host(zeta), o["zeta"])
-    print(f"workload 2 #{index}: alpha={rep['alpha']:.4e} evals={rep['n_evals']} rel_l2={err:.2e}")
+    print(f"workload 2 #{index} delta_rel={inst['delta_rel']}: alpha={rep['alpha']:.4e} evals={rep['n_evals']} "
+          f"flags={rep['flags']} rel_l2={err:.2e} oracle r/delta={o['r_norm'] / d['delta']:.6f}")
+    if rep["flags"] == fr3d.NOROOT_LOW:
+        assert rep["alpha"] == 1e-8 and rep["n_evals"] == 2
+        assert o["r_norm"] > d["delta"]
+    else:
+        assert rep["flags"] == 0
+        assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + 1e-5
     assert err < 1e-5
