@@ -89,6 +89,24 @@ def cpu_baseline(n, mean_evals, n_sample_evals=3):
                       f"{mean_evals:.2f} evaluations per solve"}
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Plain device-to-device copy of a 1 GiB buffer (read + write = 2 GiB per
+    copy): the practical HBM ceiling and the calibration kernel for counters."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GB_s": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +115,8 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the plain 1 GiB device copy used to calibrate traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -108,6 +128,10 @@ def main():
     from paper_1703_01216_amd import fr3d
 
     torch.cuda.set_device(0)
+    copy = copy_bandwidth(torch)
+    if args.copy_only:
+        print(json.dumps({"copy": copy}))
+        return
     n = args.n
     ctx = fr3d.Context(0)
     ctx.load_kernel(n, n, n, precision=32)
@@ -164,6 +188,7 @@ def main():
                    "mean_evals_per_solve": mean_evals},
         "roofline": roofline,
         "passes": passes,
+        "copy": copy,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, mean_evals)

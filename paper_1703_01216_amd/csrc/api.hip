@@ -29,7 +29,7 @@ __global__ void k_ctrl_init(Ctrl* c, Ctrl v) { *c = v; }
 // c = (1/c0^2 - xi)^(-1/2) with the argument clamped at 1e-6/c0^2.
 template <typename T>
 __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, double inv_c02, double floor_,
-                          T* __restrict__ c, long long n, unsigned long long* nclamp) {
+                          T* __restrict__ c, long long n, double* part) {
   __shared__ double red[NT / 64];
   double cl = 0.0;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
@@ -39,7 +39,18 @@ __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, 
     c[i] = (T)(1.0 / sqrt(arg));
   }
   cl = block_sum<NT>(cl, red);
-  if (threadIdx.x == 0 && cl > 0) atomicAdd(nclamp, (unsigned long long)cl);
+  if (threadIdx.x == 0) part[blockIdx.x] = cl;
+}
+
+// out[j] = sum over k < nblk of part[k*stride + j] for j < nout (one workgroup).
+__global__ void k_sum_parts(const double* __restrict__ part, int nblk, int stride, int nout, double* out) {
+  __shared__ double red[NT / 64];
+  for (int j = 0; j < nout; ++j) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += NT) s += part[(size_t)k * stride + j];
+    s = block_sum<NT>(s, red);
+    if (threadIdx.x == 0) out[j] = s;
+  }
 }
 
 // V0(x) = -(A0/4 pi) sum_l 1/|x - x_l| at R's cell centres (Sec. 6 point sources).
@@ -60,13 +71,11 @@ __global__ void k_v0(T* __restrict__ V0, int nx, int ny, int nz, double h, doubl
   }
 }
 
-// Sum of squares of two arrays in FP64, per-block partials then a fixed-order
-// final sum by the last block: out[0] = ||a||^2, out[1] = ||b||^2.
+// Sum of squares of two arrays in FP64, per-block partials (summed in a fixed
+// order by k_sum_parts): part[2 blk] = ||a||^2 part, part[2 blk + 1] = ||b||^2 part.
 template <typename T>
-__global__ void k_norms2(const T* __restrict__ a, const T* __restrict__ b, long long n, double2* part,
-                         uint32_t* ticket, double* out) {
+__global__ void k_norms2(const T* __restrict__ a, const T* __restrict__ b, long long n, double* part) {
   __shared__ double red[NT / 64];
-  __shared__ int last;
   double sa = 0.0, sb = 0.0;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const double va = a[i], vb = b[i];
@@ -76,24 +85,8 @@ __global__ void k_norms2(const T* __restrict__ a, const T* __restrict__ b, long 
   sa = block_sum<NT>(sa, red);
   sb = block_sum<NT>(sb, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = make_double2(sa, sb);
-    __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double pa = 0.0, pb = 0.0;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += NT) {
-    pa += __hip_atomic_load(&part[k].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pb += __hip_atomic_load(&part[k].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  pa = block_sum<NT>(pa, red);
-  pb = block_sum<NT>(pb, red);
-  if (threadIdx.x == 0) {
-    out[0] = pa;
-    out[1] = pb;
-    *ticket = 0u;
+    part[2 * blockIdx.x] = sa;
+    part[2 * blockIdx.x + 1] = sb;
   }
 }
 
@@ -376,7 +369,6 @@ InvArgs inv_args(fr3d_ctx* c, bool search) {
   a.oct = c->oct;
   a.ctrl = search ? c->ctrl : nullptr;
   a.norm_part = c->norm_part;
-  a.ticket = c->tickets + 1;
   return a;
 }
 
@@ -708,24 +700,23 @@ fr3d_status fr3d_recover_c(fr3d_ctx* c, const void* zeta, const void* V0, double
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!zeta || !V0 || !cout) return fail(c, FR3D_E_INVALID, "null array");
   if (!(c0 > 0) || !std::isfinite(c0)) return fail(c, FR3D_E_INVALID, "c0 must be finite and > 0");
-  unsigned long long* cnt = (unsigned long long*)c->scal;
-  HIPCHK(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream));
   const long long n = ncells(c);
+  double* part = (double*)c->norm_part;  // >= 2 nz ny doubles
   const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
-  dim3 grid((unsigned)std::min<long long>((n + NT - 1) / NT, 2048));
+  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 2048);
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_recover<double>, grid, dim3(NT), 0, c->stream, (const double*)zeta, (const double*)V0, ic2,
-                       fl, (double*)cout, n, cnt);
+    hipLaunchKernelGGL(k_recover<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)zeta, (const double*)V0,
+                       ic2, fl, (double*)cout, n, part);
   else
-    hipLaunchKernelGGL(k_recover<float>, grid, dim3(NT), 0, c->stream, (const float*)zeta, (const float*)V0, ic2, fl,
-                       (float*)cout, n, cnt);
+    hipLaunchKernelGGL(k_recover<float>, dim3(nb), dim3(NT), 0, c->stream, (const float*)zeta, (const float*)V0, ic2,
+                       fl, (float*)cout, n, part);
   LCHK(c, hipGetLastError());
   if (ncl) {
-    HIPCHK(c, hipMemcpyAsync(c->scal_host, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, c->stream, (const double*)part, (int)nb, 1, 1, c->scal);
+    LCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    unsigned long long v;
-    std::memcpy(&v, c->scal_host, sizeof v);
-    *ncl = (int64_t)v;
+    *ncl = (int64_t)c->scal_host[0];
   }
   return FR3D_OK;
 }
@@ -778,14 +769,15 @@ fr3d_status fr3d_add_noise(fr3d_ctx* c, void* F, const void* e, double delta_rel
   if (!F || !e) return fail(c, FR3D_E_INVALID, "null array");
   if (!(delta_rel >= 0) || !std::isfinite(delta_rel)) return fail(c, FR3D_E_INVALID, "delta_rel must be >= 0");
   const long long n = ncells(c);
-  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, std::min<long long>(1024, (long long)c->norm_part_n));
+  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 1024);
   double* nrm = c->scal + 2;
+  double* part = (double*)c->norm_part;
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_norms2<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)F, (const double*)e, n,
-                       c->norm_part, c->tickets + 2, nrm);
+    hipLaunchKernelGGL(k_norms2<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)F, (const double*)e, n, part);
   else
-    hipLaunchKernelGGL(k_norms2<float>, dim3(nb), dim3(NT), 0, c->stream, (const float*)F, (const float*)e, n,
-                       c->norm_part, c->tickets + 2, nrm);
+    hipLaunchKernelGGL(k_norms2<float>, dim3(nb), dim3(NT), 0, c->stream, (const float*)F, (const float*)e, n, part);
+  LCHK(c, hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, c->stream, (const double*)part, (int)nb, 2, 2, nrm);
   LCHK(c, hipGetLastError());
   dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 4096));
   if (c->esz == 8)

@@ -60,7 +60,7 @@ struct FwdArgs {
   int kind;
   // energy epilogue
   BinGeom bg;
-  double* bins_part;  // [z-pass workgroups][64]
+  double* bins_part;  // [64][z-pass workgroups]
   double* bins_out;   // [64] energies
   float* feat_out;    // [65] features
   uint32_t* ticket;
@@ -73,8 +73,7 @@ struct InvArgs {
   double scale;             // 1/(Px Py Pz)
   const double2* oct;
   Ctrl* ctrl;               // null for the forward operator (no search)
-  double2* norm_part;       // [gridDim][2]
-  uint32_t* ticket;
+  double2* norm_part;       // [x-pass workgroups] (||r||^2, ||zeta||^2) partials
 };
 
 // ------------------------------------------------------------------ host launchers

@@ -209,7 +209,8 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (tid < 64) a.bins_part[(size_t)bid * 64 + tid] = bins[tid];
+    const int nblk = gridDim.x * gridDim.y;
+    if (tid < 64) a.bins_part[(size_t)tid * nblk + bid] = bins[tid];
   } else {
     const int oy = py / 2 + 1;
     c2<T>* dst = S + (size_t)kx * NOUT * oy;
@@ -379,7 +380,6 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double red[NT / 64];
-  __shared__ int last;
   if (a.ctrl && !a.ctrl->active) return;
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
@@ -418,30 +418,27 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
     rr += (double)res * res;
   }
   if constexpr (MODE == 0) {
-    const int nblk = gridDim.x * gridDim.y;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     const double sz = block_sum<NT>(zz, red);
     const double sr = block_sum<NT>(rr, red);
-    if (tid == 0) {
-      a.norm_part[bid] = make_double2(sr, sz);
-      __threadfence();
-      last = (atomicAdd(a.ticket, 1u) == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double pr = 0.0, pz = 0.0;
-    for (int k = tid; k < nblk; k += NT) {
-      pr += __hip_atomic_load(&a.norm_part[k].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pz += __hip_atomic_load(&a.norm_part[k].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const double tr = block_sum<NT>(pr, red);
-    const double tz = block_sum<NT>(pz, red);
-    if (tid == 0) {
-      *a.ticket = 0u;
-      ctrl_advance(a.ctrl, tr, tz);
-    }
+    if (tid == 0) a.norm_part[bid] = make_double2(sr, sz);
   }
+}
+
+// Final sum of the x pass's norm partials in a fixed order (one workgroup),
+// then one step of the alpha search.
+static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
+  __shared__ double red[NT / 64];
+  if (!a.ctrl->active) return;
+  double pr = 0.0, pz = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += NT) {
+    const double2 v = a.norm_part[k];
+    pr += v.x;
+    pz += v.y;
+  }
+  const double tr = block_sum<NT>(pr, red);
+  const double tz = block_sum<NT>(pz, red);
+  if (threadIdx.x == 0) ctrl_advance(a.ctrl, tr, tz);
 }
 
 // Radial energies and predictor features from the z pass's per-workgroup bin
@@ -452,8 +449,9 @@ static __global__ __launch_bounds__(NT) void k_bins_final(FwdArgs a, int nblk) {
   __shared__ double red[NT / 64];
   __shared__ int last;
   const int b = blockIdx.x;
+  const double* row = a.bins_part + (size_t)b * nblk;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += NT) s += a.bins_part[(size_t)k * 64 + b];
+  for (int k = threadIdx.x; k < nblk; k += NT) s += row[k];
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) {
     a.bins_out[b] = s;
@@ -463,17 +461,15 @@ static __global__ __launch_bounds__(NT) void k_bins_final(FwdArgs a, int nblk) {
   __syncthreads();
   if (!last) return;
   __threadfence();
-  if (threadIdx.x == 0) {
-    double E[64], tot = 0.0;
-    for (int i = 0; i < 64; ++i) {
-      E[i] = __hip_atomic_load(&a.bins_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      tot += E[i];
+  if (threadIdx.x < 64) {
+    const double E = __hip_atomic_load(&a.bins_out[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double tot = wave_sum<double>(E);
+    a.feat_out[threadIdx.x] = (float)log10(E / (tot / 64.0) + 1e-30);
+    if (threadIdx.x == 0) {
+      const double fnorm = sqrt(tot / ((double)a.bg.px * a.bg.py * a.bg.pz));
+      a.feat_out[64] = (float)log10(a.delta / fnorm);
+      *a.ticket = 0u;
     }
-    const double mean = tot / 64.0;
-    for (int i = 0; i < 64; ++i) a.feat_out[i] = (float)log10(E[i] / mean + 1e-30);
-    const double fnorm = sqrt(tot / ((double)a.bg.px * a.bg.py * a.bg.pz));
-    a.feat_out[64] = (float)log10(a.delta / fnorm);
-    *a.ticket = 0u;
   }
 }
 
@@ -590,7 +586,11 @@ hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a,
 #define X(p)                                                                                               \
   case p: {                                                                                                \
     dim3 g(cdiv(a.ny, Tile<T, p>::C), a.nz);                                                               \
-    return mode == 0 ? go(k_ix<T, p, 0>, g, L, W2, out, a, tw) : go(k_ix<T, p, 1>, g, L, W2, out, a, tw);  \
+    if (mode != 0) return go(k_ix<T, p, 1>, g, L, W2, out, a, tw);                                        \
+    hipError_t e = go(k_ix<T, p, 0>, g, L, W2, out, a, tw);                                                \
+    if (e != hipSuccess) return e;                                                                         \
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                      \
+    return hipGetLastError();                                                                              \
   }
     FR3D_SIZES(X)
 #undef X
