@@ -93,6 +93,7 @@ typedef struct {
   double target;            /* (tau delta + h_op ||zeta||)^2 + mu^2, square-rooted */
   int32_t n_evals;          /* number of alpha evaluations (inverse transforms) */
   int32_t flags;            /* FR3D_* report flags */
+  int64_t n_clamped;        /* cells clamped by the recovery of c (batch with recovery), else -1 */
 } fr3d_report;
 
 /* Defaults of fr3d_dp_opts. */
@@ -106,6 +107,11 @@ fr3d_status fr3d_create(fr3d_ctx** out, int32_t device, void* hip_stream);
 fr3d_status fr3d_destroy(fr3d_ctx* ctx);
 /* Change the stream later work is enqueued on. */
 fr3d_status fr3d_set_stream(fr3d_ctx* ctx, void* hip_stream);
+/* Number of lanes (1..64) of the batch solver.  Lane 0 runs on the context's
+ * stream; each further lane owns a stream (default priority) and its own data
+ * spectrum, workspaces and search state (about 1.3 P^3 complex values each);
+ * all lanes share the kernel spectrum. */
+fr3d_status fr3d_set_lanes(fr3d_ctx* ctx, int32_t lanes);
 
 /* Sample K at every wrapped cell offset of the P^3 box (zero in the slot no
  * pair of cells reaches), take its FP64 3D DFT and keep the octant
@@ -133,6 +139,20 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
  * (synchronises). */
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
                                    fr3d_report* rep);
+
+/* Solve n instances on the lanes: for item i, set the data F_devs[i] with
+ * noise level deltas[i], choose alpha by the discrepancy principle (opts,
+ * NULL = defaults) writing zeta_devs[i], and, if c_devs is not NULL, recover
+ * c into c_devs[i] from V0_dev and c0.  Instances run concurrently, one per
+ * lane; each lane advances one evaluation at a time and the host polls the
+ * lanes, so no evaluation is launched after its search has ended.  The
+ * caller's stream is ordered before and after the whole batch.  reps[i]
+ * receives each item's report (n_clamped when c is recovered).  Returns when
+ * every search has finished (recoveries may still be in flight on the
+ * context's stream). */
+fr3d_status fr3d_solve_batch(fr3d_ctx* ctx, int32_t n, const void* const* F_devs, const double* deltas,
+                             void* const* zeta_devs, const fr3d_dp_opts* opts, const void* V0_dev, double c0,
+                             void* const* c_devs, fr3d_report* reps);
 
 /* Algorithm 1 step 4: xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2) on R; where
  * 1/c0^2 - xi < 1e-6/c0^2 the argument is clamped and the cell counted in
@@ -166,6 +186,30 @@ fr3d_status fr3d_get_data_spectrum(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
 fr3d_status fr3d_get_features(fr3d_ctx* ctx, float* feat_dev, double* energy_dev);
 /* |k^|max^2 of the loaded kernel (host). */
 fr3d_status fr3d_get_smax(fr3d_ctx* ctx, double* smax);
+
+/* The alpha predictor (not part of the paper): a perceptron 65 -> 128 ->
+ * 128 -> 1 with exact-erf GELU, bfloat16 matrix-core products with FP32
+ * accumulation, FP32 master weights and Adam.  Input: the 65 features of a
+ * data set (fr3d_get_features), standardised by norm = (mu[65], sigma[65],
+ * t_mu, t_sigma); output log10 alpha = t_mu + t_sigma y.  Parameters (FP32,
+ * host arrays): W1[128][65], b1[128], W2[128][128], b2[128], w3[128], b3 --
+ * 25089 values.  With fr3d_dp_opts.use_predictor the network's prediction
+ * for the set data is the first point of the search. */
+fr3d_status fr3d_predictor_set(fr3d_ctx* ctx, const float* params, int64_t n_params, const float* norm);
+fr3d_status fr3d_predictor_get(fr3d_ctx* ctx, float* params, float* norm);
+/* y_dev[b] = predicted log10 alpha for raw features X_dev[b][65], b < B (device arrays). */
+fr3d_status fr3d_predictor_forward(fr3d_ctx* ctx, const float* X_dev, int32_t B, float* y_dev);
+/* One training step on B rows (device arrays X_dev[B][65], t_dev[B] = log10
+ * alpha targets): gradients of the mean squared error in standardised units,
+ * then Adam (beta 0.9/0.999, eps 1e-8) with learning rate lr if lr > 0.
+ * loss_dev (1 float) and grad_dev (25089 floats) receive the loss and the
+ * gradients when not NULL. */
+fr3d_status fr3d_predictor_train_step(fr3d_ctx* ctx, const float* X_dev, const float* t_dev, int32_t B, double lr,
+                                      float* loss_dev, float* grad_dev);
+/* Checkpoint: parameters, normalisation, Adam moments and step, with a
+ * checksum; load rejects a corrupt or foreign file with FR3D_E_INVALID. */
+fr3d_status fr3d_predictor_save(fr3d_ctx* ctx, const char* path);
+fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
 
 /* Per-pass timing with HIP events on the context's stream (for measurement).
  * Pass ids: 0..2 forward x,y,z; 3..5 inverse z,y,x. */

@@ -1,6 +1,14 @@
-// C-ABI of the solver (declared in include/fr3d.h): context, workspaces,
-// kernel spectrum, data transform, alpha evaluations and search, recovery,
-// source potential, forward operator and noise.
+// C-ABI of the solver (declared in include/fr3d.h): context, lanes,
+// kernel spectrum, data transform, alpha evaluations and search, batch
+// scheduler, recovery, source potential, forward operator, noise and the
+// alpha predictor.
+//
+// A context holds one geometry: the FP64 kernel-spectrum octant and the
+// twiddle tables, shared read-only by its lanes.  A lane holds everything one
+// solve in flight needs: a stream, the data spectrum, the inverse-pass
+// workspaces, a device control block and its pinned host mirror.  Lane 0
+// runs on the caller's stream and serves the single-solve calls; the batch
+// call keeps every lane busy with its own instance.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,10 +20,12 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fr3d.h"
 #include "control.hpp"
+#include "mlp.hpp"
 #include "passes.hpp"
 
 using namespace fr3d;
@@ -25,8 +35,8 @@ namespace {
 
 __global__ void k_ctrl_init(Ctrl* c, Ctrl v) { *c = v; }
 
-// zeta = xi V0 is not formed here; recovery: xi = zeta / V0 and
-// c = (1/c0^2 - xi)^(-1/2) with the argument clamped at 1e-6/c0^2.
+// Recovery (Algorithm 1, step 4): xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2)
+// with the argument clamped at 1e-6/c0^2; per-block counts of clamped cells.
 template <typename T>
 __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, double inv_c02, double floor_,
                           T* __restrict__ c, long long n, double* part) {
@@ -42,7 +52,7 @@ __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, 
   if (threadIdx.x == 0) part[blockIdx.x] = cl;
 }
 
-// out[j] = sum over k < nblk of part[k*stride + j] for j < nout (one workgroup).
+// out[j] = sum over k < nblk of part[k*stride + j] for j < nout (one workgroup, fixed order).
 __global__ void k_sum_parts(const double* __restrict__ part, int nblk, int stride, int nout, double* out) {
   __shared__ double red[NT / 64];
   for (int j = 0; j < nout; ++j) {
@@ -71,8 +81,7 @@ __global__ void k_v0(T* __restrict__ V0, int nx, int ny, int nz, double h, doubl
   }
 }
 
-// Sum of squares of two arrays in FP64, per-block partials (summed in a fixed
-// order by k_sum_parts): part[2 blk] = ||a||^2 part, part[2 blk + 1] = ||b||^2 part.
+// Per-block sums of squares of two arrays in FP64 (part[2 blk], part[2 blk + 1]).
 template <typename T>
 __global__ void k_norms2(const T* __restrict__ a, const T* __restrict__ b, long long n, double* part) {
   __shared__ double red[NT / 64];
@@ -90,7 +99,7 @@ __global__ void k_norms2(const T* __restrict__ a, const T* __restrict__ b, long 
   }
 }
 
-// F += e * (delta_rel ||F|| / ||e||); the factor comes from nrm = (||F||^2, ||e||^2).
+// F += e * (delta_rel ||F|| / ||e||); nrm = (||F||^2, ||e||^2).
 template <typename T>
 __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long long n, double delta_rel,
                             const double* nrm) {
@@ -99,11 +108,9 @@ __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long lon
     F[i] = (T)((double)F[i] + f * (double)e[i]);
 }
 
-// max |k^|^2 over the octant (it covers every value of |k^| by symmetry):
-// per-block maxima, then the last block takes the maximum of those.
-__global__ void k_smax(const double2* __restrict__ oct, long long n, double* part, uint32_t* ticket, double* out) {
+// Per-block maxima of |k^|^2 over the octant (it covers every value of |k^|).
+__global__ void k_smax_part(const double2* __restrict__ oct, long long n, double* part) {
   __shared__ double red[NT];
-  __shared__ int last;
   double m = 0.0;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
     const double2 k = oct[i];
@@ -115,63 +122,72 @@ __global__ void k_smax(const double2* __restrict__ oct, long long n, double* par
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = red[0];
-    __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  m = 0.0;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += NT)
-    m = fmax(m, __hip_atomic_load(&part[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_parts(const double* __restrict__ part, int n, double* out) {
+  __shared__ double red[NT];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < n; k += NT) m = fmax(m, part[k]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    *out = red[0];
-    *ticket = 0u;
-  }
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 }  // namespace
 
 // ============================================================ context
+struct Lane {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* spec = nullptr;  // data spectrum S
+  void* work = nullptr;  // forward A, B / inverse W1, W2
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;  // pinned
+  double* bins_part = nullptr;
+  double2* norm_part = nullptr;
+  double* energy = nullptr;
+  float* feat = nullptr;
+  double* scal = nullptr;       // small FP64 scratch
+  double* scal_host = nullptr;  // pinned
+  uint32_t* ticket = nullptr;
+  hipEvent_t ev = nullptr;      // completion marker polled by the batch scheduler
+  bool has_data = false;
+  double delta = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[6];  // timing event pairs per pass
+};
+
 struct fr3d_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
   std::string err;
-  bool has_kernel = false, has_data = false;
+  bool has_kernel = false;
   fr3d_geom g{};
   int px = 0, py = 0, pz = 0, kxn = 0;
   double D = 0;
-  size_t esz = 4;  // sizeof(T)
+  size_t esz = 4;
   double smax = 0;
-  double delta = 0;
-  // device buffers
   double2* oct = nullptr;
-  void* spec = nullptr;
-  void* work = nullptr;
-  size_t spec_bytes = 0, work_bytes = 0;
-  Ctrl* ctrl = nullptr;
-  Ctrl* ctrl_host = nullptr;  // pinned
-  uint32_t* tickets = nullptr;
-  double* bins_part = nullptr;
-  size_t bins_part_n = 0;
-  double2* norm_part = nullptr;
-  size_t norm_part_n = 0;
-  double* energy = nullptr;
-  float* feat = nullptr;
-  double* scal = nullptr;     // small FP64 scratch (norms, s_max)
-  double* scal_host = nullptr;  // pinned
+  size_t spec_bytes = 0, work_bytes = 0, bins_part_n = 0, norm_part_n = 0;
   std::map<int, void*> tw32, tw64;
+  std::vector<Lane> lanes;  // lanes[0] runs on the caller's stream
+  int nlanes_wanted = 1;
+  // predictor
+  bool has_pred = false;
+  float* pred_p = nullptr;     // parameters, FP32 master copy
+  float* pred_norm = nullptr;  // 132 normalisation values
+  float* pred_m = nullptr;
+  float* pred_v = nullptr;
+  float* pred_g = nullptr;
+  float* pred_loss = nullptr;
+  void* pred_work = nullptr;
+  int pred_cap = 0;
+  long long pred_step = 0;
   // timing
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[6];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double acc_ms[6] = {0, 0, 0, 0, 0, 0};
   long long cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -199,22 +215,78 @@ fr3d_status fail(fr3d_ctx* c, fr3d_status s, const char* fmt, ...) {
                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                          \
   } while (0)
 
+#define LCHK(c, call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail((c), FR3D_E_DEVICE, "launch %s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
 template <typename P> void dfree(P*& p) {
   if (p) (void)hipFree((void*)p);
   p = nullptr;
 }
+template <typename P> void hfree(P*& p) {
+  if (p) (void)hipHostFree((void*)p);
+  p = nullptr;
+}
 
-void free_geometry_buffers(fr3d_ctx* c) {
+void free_lane_geometry(Lane& L) {
+  dfree(L.spec);
+  dfree(L.work);
+  dfree(L.bins_part);
+  dfree(L.norm_part);
+  L.has_data = false;
+}
+
+void free_lane(Lane& L) {
+  free_lane_geometry(L);
+  dfree(L.ctrl);
+  hfree(L.ctrl_host);
+  dfree(L.energy);
+  dfree(L.feat);
+  dfree(L.scal);
+  hfree(L.scal_host);
+  dfree(L.ticket);
+  if (L.ev) (void)hipEventDestroy(L.ev);
+  L.ev = nullptr;
+  if (L.own_stream && L.stream) (void)hipStreamDestroy(L.stream);
+  L.stream = nullptr;
+}
+
+fr3d_status init_lane(fr3d_ctx* c, Lane& L, hipStream_t stream, bool own) {
+  L.stream = stream;
+  L.own_stream = own;
+  HIPCHK(c, hipMalloc(&L.ctrl, sizeof(Ctrl)));
+  HIPCHK(c, hipHostMalloc(&L.ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
+  HIPCHK(c, hipMalloc(&L.energy, 64 * sizeof(double)));
+  HIPCHK(c, hipMalloc(&L.feat, 65 * sizeof(float)));
+  HIPCHK(c, hipMalloc(&L.scal, 16 * sizeof(double)));
+  HIPCHK(c, hipHostMalloc(&L.scal_host, 16 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(c, hipMalloc(&L.ticket, 4 * sizeof(uint32_t)));
+  HIPCHK(c, hipMemset(L.ticket, 0, 4 * sizeof(uint32_t)));
+  HIPCHK(c, hipMemset(L.ctrl, 0, sizeof(Ctrl)));
+  HIPCHK(c, hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+  std::memset(L.ctrl_host, 0, sizeof(Ctrl));
+  return FR3D_OK;
+}
+
+fr3d_status alloc_lane_geometry(fr3d_ctx* c, Lane& L) {
+  free_lane_geometry(L);
+  HIPCHK(c, hipMalloc(&L.spec, c->spec_bytes));
+  HIPCHK(c, hipMalloc(&L.work, c->work_bytes));
+  HIPCHK(c, hipMalloc(&L.bins_part, c->bins_part_n * 64 * sizeof(double)));
+  HIPCHK(c, hipMalloc(&L.norm_part, c->norm_part_n * sizeof(double2)));
+  return FR3D_OK;
+}
+
+void free_geometry(fr3d_ctx* c) {
   dfree(c->oct);
-  dfree(c->spec);
-  dfree(c->work);
-  dfree(c->bins_part);
-  dfree(c->norm_part);
   for (auto& kv : c->tw32) (void)hipFree(kv.second);
   for (auto& kv : c->tw64) (void)hipFree(kv.second);
   c->tw32.clear();
   c->tw64.clear();
-  c->has_kernel = c->has_data = false;
+  for (auto& L : c->lanes) free_lane_geometry(L);
+  c->has_kernel = false;
 }
 
 // e^{-2 pi i m/P}: the angle is formed and evaluated in extended precision
@@ -262,49 +334,38 @@ fr3d_status get_twiddles(fr3d_ctx* c, int P, bool dbl, void** out) {
   return FR3D_OK;
 }
 
-fr3d_status ensure(fr3d_ctx* c, void** p, size_t& have, size_t need) {
-  if (have >= need && *p) return FR3D_OK;
-  if (*p) (void)hipFree(*p);
-  *p = nullptr;
-  have = 0;
-  HIPCHK(c, hipMalloc(p, need));
-  have = need;
-  return FR3D_OK;
-}
-
 // --------------------------------------------------------------- timing
 // With timing on, each pass kernel is launched with an event pair recorded at
 // its own start and end.
-Launch mkL(fr3d_ctx* c, int pass) {
-  Launch L{c->stream, nullptr, nullptr};
-  if (!c->timing) return L;
+Launch mkL(fr3d_ctx* c, Lane& L, int pass) {
+  Launch r{L.stream, nullptr, nullptr};
+  if (!c->timing) return r;
   std::pair<hipEvent_t, hipEvent_t> p;
   if (!c->ev_pool.empty()) { p = c->ev_pool.back(); c->ev_pool.pop_back(); }
-  else if (hipEventCreate(&p.first) != hipSuccess || hipEventCreate(&p.second) != hipSuccess) return L;
-  c->ev[pass].push_back(p);
-  L.e0 = p.first;
-  L.e1 = p.second;
-  return L;
+  else if (hipEventCreate(&p.first) != hipSuccess || hipEventCreate(&p.second) != hipSuccess) return r;
+  L.tev[pass].push_back(p);
+  r.e0 = p.first;
+  r.e1 = p.second;
+  return r;
 }
 
-// Accumulate recorded pass times.  keep_inv >= 0 counts only the first
-// keep_inv launches of each inverse pass (the later launches of a search
-// return at once after the search has finished).
-void tcollect(fr3d_ctx* c, long long keep_inv = -1) {
-  (void)hipStreamSynchronize(c->stream);
+// Accumulate a lane's recorded pass times (its stream must be idle).
+// keep_inv >= 0 counts only the first keep_inv launches of each inverse pass
+// since the last collection (later launches of a search return at once).
+void tcollect(fr3d_ctx* c, Lane& L, long long keep_inv = -1) {
   for (int p = 0; p < 6; ++p) {
-    const size_t lim = (keep_inv >= 0 && p >= 3) ? std::min<size_t>(c->ev[p].size(), (size_t)keep_inv) : c->ev[p].size();
-    for (size_t i = 0; i < c->ev[p].size(); ++i) {
-      auto& e = c->ev[p][i];
+    const size_t lim = (keep_inv >= 0 && p >= 3) ? std::min<size_t>(L.tev[p].size(), (size_t)keep_inv) : L.tev[p].size();
+    for (size_t i = 0; i < L.tev[p].size(); ++i) {
+      auto& e = L.tev[p][i];
       float ms = 0;
       if (i < lim && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) { c->acc_ms[p] += ms; c->cnt[p] += 1; }
       c->ev_pool.push_back(e);
     }
-    c->ev[p].clear();
+    L.tev[p].clear();
   }
 }
 
-// --------------------------------------------------------------- geometry
+// --------------------------------------------------------------- geometry helpers
 int gap_default(int nz, int q) {
   if (q < 0) return nz + (nz + 3) / 4;
   return nz + (q + 1) * ((nz + 7) / 8);
@@ -329,19 +390,19 @@ template <typename T> struct Bufs {
   c4<T>* W2;
 };
 
-template <typename T> Bufs<T> bufs(fr3d_ctx* c) {
+template <typename T> Bufs<T> bufs(fr3d_ctx* c, Lane& L) {
   Bufs<T> b;
   const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny;
   const size_t nB = (size_t)c->kxn * c->g.nz * c->py;
-  b.S = (c2<T>*)c->spec;
-  b.W1 = (c4<T>*)c->work;
+  b.S = (c2<T>*)L.spec;
+  b.W1 = (c4<T>*)L.work;
   b.W2 = b.W1 + nB;
-  b.A = (c2<T>*)c->work;
+  b.A = (c2<T>*)L.work;
   b.B = b.A + nA;
   return b;
 }
 
-FwdArgs fwd_args(fr3d_ctx* c, bool kernel) {
+FwdArgs fwd_args(fr3d_ctx* c, Lane& L, bool kernel) {
   FwdArgs a{};
   a.nz_in = kernel ? c->pz : c->g.nz;
   a.ny_in = kernel ? c->py : c->g.ny;
@@ -353,67 +414,71 @@ FwdArgs fwd_args(fr3d_ctx* c, bool kernel) {
   a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
   a.kind = c->g.kind;
   a.bg = bin_geom(c->px, c->py, c->pz);
-  a.bins_part = c->bins_part;
-  a.bins_out = c->energy;
-  a.feat_out = c->feat;
-  a.ticket = c->tickets + 0;
-  a.delta = c->delta;
+  a.bins_part = L.bins_part;
+  a.bins_out = L.energy;
+  a.feat_out = L.feat;
+  a.ticket = L.ticket;
+  a.delta = L.delta;
   return a;
 }
 
-InvArgs inv_args(fr3d_ctx* c, bool search) {
+InvArgs inv_args(fr3d_ctx* c, Lane& L, bool search) {
   InvArgs a{};
   a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
   a.kx_n = c->kxn; a.py = c->py; a.pz = c->pz;
   a.scale = 1.0 / ((double)c->px * c->py * c->pz);
   a.oct = c->oct;
-  a.ctrl = search ? c->ctrl : nullptr;
-  a.norm_part = c->norm_part;
+  a.ctrl = search ? L.ctrl : nullptr;
+  a.norm_part = L.norm_part;
   return a;
 }
 
-#define LCHK(c, call)                                                                         \
-  do {                                                                                        \
-    hipError_t e_ = (call);                                                                   \
-    if (e_ != hipSuccess) return fail((c), FR3D_E_DEVICE, "launch %s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-template <typename T> fr3d_status forward_data(fr3d_ctx* c, const T* F) {
-  void *twx, *twy, *twz;
+template <typename T> fr3d_status forward_data(fr3d_ctx* c, Lane& L, const T* F) {
   const bool dbl = sizeof(T) == 8;
-  if (get_twiddles(c, c->px, dbl, &twx) || get_twiddles(c, c->py, dbl, &twy) || get_twiddles(c, c->pz, dbl, &twz))
-    return FR3D_E_DEVICE;
-  Bufs<T> b = bufs<T>(c);
-  FwdArgs a = fwd_args(c, false);
-  LCHK(c, launch_fx<T>(c->px, false, F, b.A, a, (const c2<T>*)twx, mkL(c, 0)));
-  LCHK(c, launch_fy<T>(c->py, true, b.A, b.B, a, (const c2<T>*)twy, mkL(c, 1)));
-  LCHK(c, launch_fz<T>(c->pz, 0, b.B, b.S, a, (const c2<T>*)twz, mkL(c, 2)));
-  return FR3D_OK;
-}
-
-template <typename T> fr3d_status inverse(fr3d_ctx* c, int mode, T* out) {
   void *twx, *twy, *twz;
+  fr3d_status st;
+  if ((st = get_twiddles(c, c->px, dbl, &twx)) || (st = get_twiddles(c, c->py, dbl, &twy)) ||
+      (st = get_twiddles(c, c->pz, dbl, &twz)))
+    return st;
+  Bufs<T> b = bufs<T>(c, L);
+  FwdArgs a = fwd_args(c, L, false);
+  LCHK(c, launch_fx<T>(c->px, false, F, b.A, a, (const c2<T>*)twx, mkL(c, L, 0)));
+  LCHK(c, launch_fy<T>(c->py, true, b.A, b.B, a, (const c2<T>*)twy, mkL(c, L, 1)));
+  LCHK(c, launch_fz<T>(c->pz, 0, b.B, b.S, a, (const c2<T>*)twz, mkL(c, L, 2)));
+  return FR3D_OK;
+}
+
+template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out) {
   const bool dbl = sizeof(T) == 8;
-  if (get_twiddles(c, c->px, dbl, &twx) || get_twiddles(c, c->py, dbl, &twy) || get_twiddles(c, c->pz, dbl, &twz))
-    return FR3D_E_DEVICE;
-  Bufs<T> b = bufs<T>(c);
-  InvArgs a = inv_args(c, mode == 0);
-  LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, 3)));
-  LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, 4)));
-  LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, 5)));
+  void *twx, *twy, *twz;
+  fr3d_status st;
+  if ((st = get_twiddles(c, c->px, dbl, &twx)) || (st = get_twiddles(c, c->py, dbl, &twy)) ||
+      (st = get_twiddles(c, c->pz, dbl, &twz)))
+    return st;
+  Bufs<T> b = bufs<T>(c, L);
+  InvArgs a = inv_args(c, L, mode == 0);
+  LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
+  LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, L, 4)));
+  LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, L, 5)));
   return FR3D_OK;
 }
 
-fr3d_status launch_ctrl(fr3d_ctx* c, const Ctrl& v) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, c->stream, c->ctrl, v);
-  LCHK(c, hipGetLastError());
+fr3d_status set_data_lane(fr3d_ctx* c, Lane& L, const void* F, double delta) {
+  L.delta = delta;
+  fr3d_status s = c->esz == 8 ? forward_data<double>(c, L, (const double*)F) : forward_data<float>(c, L, (const float*)F);
+  if (s) return s;
+  L.has_data = true;
   return FR3D_OK;
 }
 
-Ctrl ctrl_base(fr3d_ctx* c) {
+fr3d_status eval_lane(fr3d_ctx* c, Lane& L, void* zeta) {
+  return c->esz == 8 ? inverse<double>(c, L, 0, (double*)zeta) : inverse<float>(c, L, 0, (float*)zeta);
+}
+
+Ctrl ctrl_base(fr3d_ctx* c, Lane& L) {
   Ctrl v{};
   v.a_scale = c->g.alpha_relative ? c->smax : 1.0;
-  v.delta = c->delta;
+  v.delta = L.delta;
   v.tau = 1.0;
   v.h_op = 0.0;
   v.mu = 0.0;
@@ -427,14 +492,62 @@ Ctrl ctrl_base(fr3d_ctx* c) {
   return v;
 }
 
-fr3d_status read_ctrl(fr3d_ctx* c) {
-  HIPCHK(c, hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
+  fr3d_dp_opts_default(d);
+  if (o) *d = *o;
+  if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
+      !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
+      !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi))
+    return fail(c, FR3D_E_INVALID, "bad search options");
+  if (d->use_predictor && !c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
   return FR3D_OK;
 }
 
-void fill_report(fr3d_ctx* c, fr3d_report* r) {
-  const Ctrl& h = *c->ctrl_host;
+// Initial control block of a search with options d; with the predictor the
+// first point is written on the device by the network's forward pass.
+fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_evals) {
+  Ctrl v = ctrl_base(c, L);
+  v.lo = d.log10_alpha_lo;
+  v.hi = d.log10_alpha_hi;
+  v.max_steps = d.max_steps;
+  v.tol = d.tol;
+  v.acc_lo = d.accept_lo;
+  v.acc_hi = d.accept_hi;
+  v.tau = d.tau;
+  v.h_op = d.h_op;
+  v.mu = d.mu;
+  v.state = ST_HI;
+  v.t = v.hi;
+  v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, L.stream, L.ctrl, v);
+  LCHK(c, hipGetLastError());
+  if (d.use_predictor) {
+    LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream));
+    // seed + one walk step per decade + bisection + final re-evaluation
+    *max_evals = 1 + (int)std::ceil(d.log10_alpha_hi - d.log10_alpha_lo) + d.max_steps + 1;
+  } else {
+    *max_evals = 2 + d.max_steps + 1;
+  }
+  return FR3D_OK;
+}
+
+fr3d_status fixed_search(fr3d_ctx* c, Lane& L, double alpha) {
+  Ctrl v = ctrl_base(c, L);
+  v.state = ST_FIXED;
+  v.t = std::log10(alpha);
+  v.alpha_abs = alpha * v.a_scale;
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, L.stream, L.ctrl, v);
+  LCHK(c, hipGetLastError());
+  return FR3D_OK;
+}
+
+fr3d_status post_ctrl(fr3d_ctx* c, Lane& L) {
+  HIPCHK(c, hipMemcpyAsync(L.ctrl_host, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, L.stream));
+  HIPCHK(c, hipEventRecord(L.ev, L.stream));
+  return FR3D_OK;
+}
+
+void fill_report(const Ctrl& h, fr3d_report* r) {
   r->alpha = std::pow(10.0, h.t);
   r->residual = std::sqrt(h.r2);
   r->zeta_norm = std::sqrt(h.z2);
@@ -442,19 +555,105 @@ void fill_report(fr3d_ctx* c, fr3d_report* r) {
   r->target = h.target;
   r->n_evals = h.n_evals;
   r->flags = h.flags;
+  r->n_clamped = -1;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  return s ? std::atoi(s) : dflt;
+}
+
+// Single search on lane 0, chunks of evaluations between host reads.
+fr3d_status run_search(fr3d_ctx* c, int max_evals, void* zeta, fr3d_report* rep) {
+  Lane& L = c->lanes[0];
+  const int chunk = std::max(1, env_int("FR3D_EVAL_CHUNK", 4));
+  int launched = 0;
+  fr3d_status s;
+  for (;;) {
+    const int k = std::min(chunk, max_evals - launched);
+    for (int i = 0; i < k; ++i)
+      if ((s = eval_lane(c, L, zeta))) return s;
+    launched += k;
+    if ((s = post_ctrl(c, L))) return s;
+    HIPCHK(c, hipEventSynchronize(L.ev));
+    if (!L.ctrl_host->active || launched >= max_evals) break;
+  }
+  if (c->timing) tcollect(c, L, L.ctrl_host->n_evals);
+  if (L.ctrl_host->active) return fail(c, FR3D_E_DEVICE, "alpha search did not finish in %d evaluations", max_evals);
+  if (rep) fill_report(*L.ctrl_host, rep);
+  return FR3D_OK;
 }
 
 bool need(fr3d_ctx* c, bool kernel, bool data) {
   if (kernel && !c->has_kernel) { fail(c, FR3D_E_STATE, "no kernel loaded"); return false; }
-  if (data && !c->has_data) { fail(c, FR3D_E_STATE, "no data set"); return false; }
+  if (data && !c->lanes[0].has_data) { fail(c, FR3D_E_STATE, "no data set"); return false; }
   return true;
 }
 
 long long ncells(fr3d_ctx* c) { return (long long)c->g.nx * c->g.ny * c->g.nz; }
 
-int env_int(const char* name, int dflt) {
-  const char* s = std::getenv(name);
-  return s ? std::atoi(s) : dflt;
+fr3d_status launch_recover(fr3d_ctx* c, Lane& L, const void* zeta, const void* V0, double c0, void* cout,
+                           bool count) {
+  const long long n = ncells(c);
+  double* part = (double*)L.norm_part;  // >= 2 nz ny doubles
+  const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
+  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 2048);
+  if (c->esz == 8)
+    hipLaunchKernelGGL(k_recover<double>, dim3(nb), dim3(NT), 0, L.stream, (const double*)zeta, (const double*)V0,
+                       ic2, fl, (double*)cout, n, part);
+  else
+    hipLaunchKernelGGL(k_recover<float>, dim3(nb), dim3(NT), 0, L.stream, (const float*)zeta, (const float*)V0, ic2,
+                       fl, (float*)cout, n, part);
+  LCHK(c, hipGetLastError());
+  if (count) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, L.stream, (const double*)part, (int)nb, 1, 1, L.scal);
+    LCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(L.scal_host, L.scal, sizeof(double), hipMemcpyDeviceToHost, L.stream));
+  }
+  return FR3D_OK;
+}
+
+fr3d_status ensure_lanes(fr3d_ctx* c) {
+  const int want = std::max(1, c->nlanes_wanted);
+  while ((int)c->lanes.size() < want) {
+    hipStream_t s;
+    HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    c->lanes.emplace_back();
+    Lane& L = c->lanes.back();
+    fr3d_status st = init_lane(c, L, s, true);
+    if (st) return st;
+    if (c->has_kernel && (st = alloc_lane_geometry(c, L))) return st;
+  }
+  return FR3D_OK;
+}
+
+fr3d_status pred_ensure_work(fr3d_ctx* c, int B) {
+  if (B <= c->pred_cap && c->pred_work) return FR3D_OK;
+  dfree(c->pred_work);
+  const int cap = std::max(B, 256);
+  HIPCHK(c, hipMalloc(&c->pred_work, mlp_work_bytes(cap)));
+  c->pred_cap = cap;
+  return FR3D_OK;
+}
+
+fr3d_status pred_alloc(fr3d_ctx* c) {
+  if (c->pred_p) return FR3D_OK;
+  HIPCHK(c, hipMalloc(&c->pred_p, MLP_NP * sizeof(float)));
+  HIPCHK(c, hipMalloc(&c->pred_m, MLP_NP * sizeof(float)));
+  HIPCHK(c, hipMalloc(&c->pred_v, MLP_NP * sizeof(float)));
+  HIPCHK(c, hipMalloc(&c->pred_g, MLP_NP * sizeof(float)));
+  HIPCHK(c, hipMalloc(&c->pred_norm, MLP_NNORM * sizeof(float)));
+  HIPCHK(c, hipMalloc(&c->pred_loss, 4 * sizeof(float)));
+  return FR3D_OK;
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
 }
 
 }  // namespace
@@ -501,17 +700,8 @@ fr3d_status fr3d_create(fr3d_ctx** out, int32_t device, void* stream) {
   fr3d_ctx* c = new (std::nothrow) fr3d_ctx;
   if (!c) return FR3D_E_NOMEM;
   c->device = device;
-  c->stream = (hipStream_t)stream;
-  bool ok = hipMalloc(&c->ctrl, sizeof(Ctrl)) == hipSuccess &&
-            hipHostMalloc(&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess &&
-            hipMalloc(&c->tickets, 16 * sizeof(uint32_t)) == hipSuccess &&
-            hipMalloc(&c->energy, 64 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->feat, 65 * sizeof(float)) == hipSuccess &&
-            hipMalloc(&c->scal, 16 * sizeof(double)) == hipSuccess &&
-            hipHostMalloc(&c->scal_host, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
-            hipMemset(c->tickets, 0, 16 * sizeof(uint32_t)) == hipSuccess &&
-            hipMemset(c->ctrl, 0, sizeof(Ctrl)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
-  if (!ok) {
+  c->lanes.emplace_back();
+  if (init_lane(c, c->lanes[0], (hipStream_t)stream, false) != FR3D_OK || hipDeviceSynchronize() != hipSuccess) {
     fr3d_destroy(c);
     return FR3D_E_NOMEM;
   }
@@ -522,27 +712,36 @@ fr3d_status fr3d_create(fr3d_ctx** out, int32_t device, void* stream) {
 fr3d_status fr3d_destroy(fr3d_ctx* c) {
   if (!c) return FR3D_E_INVALID;
   (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
-  free_geometry_buffers(c);
-  dfree(c->ctrl);
-  if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
-  if (c->scal_host) (void)hipHostFree(c->scal_host);
-  dfree(c->tickets);
-  dfree(c->energy);
-  dfree(c->feat);
-  dfree(c->scal);
-  for (int p = 0; p < 6; ++p)
-    for (auto& e : c->ev[p]) c->ev_pool.push_back(e);
+  for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
+  free_geometry(c);
+  for (auto& L : c->lanes) {
+    for (int p = 0; p < 6; ++p)
+      for (auto& e : L.tev[p]) c->ev_pool.push_back(e);
+    free_lane(L);
+  }
   for (auto& e : c->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  dfree(c->pred_p);
+  dfree(c->pred_m);
+  dfree(c->pred_v);
+  dfree(c->pred_g);
+  dfree(c->pred_norm);
+  dfree(c->pred_loss);
+  dfree(c->pred_work);
   delete c;
   return FR3D_OK;
 }
 
 fr3d_status fr3d_set_stream(fr3d_ctx* c, void* stream) {
   if (!c) return FR3D_E_INVALID;
-  c->stream = (hipStream_t)stream;
+  c->lanes[0].stream = (hipStream_t)stream;
   return FR3D_OK;
+}
+
+fr3d_status fr3d_set_lanes(fr3d_ctx* c, int32_t lanes) {
+  if (!c) return FR3D_E_INVALID;
+  if (lanes < 1 || lanes > 64) return fail(c, FR3D_E_INVALID, "lanes must be in [1, 64]");
+  c->nlanes_wanted = lanes;
+  return ensure_lanes(c);
 }
 
 fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
@@ -559,8 +758,8 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   const double D = g->D > 0 ? g->D : (double)gap_default(g->nz, g->q);
   if (D < g->nz) return fail(c, FR3D_E_INVALID, "D must be >= nz (R and Y disjoint)");
   HIPCHK(c, hipSetDevice(c->device));
-  HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
-  free_geometry_buffers(c);
+  for (auto& L : c->lanes) HIPCHK(c, L.stream ? hipStreamSynchronize(L.stream) : hipDeviceSynchronize());
+  free_geometry(c);
   c->g = *g;
   c->D = D;
   c->px = 2 * g->nx; c->py = 2 * g->ny; c->pz = 2 * g->nz;
@@ -571,53 +770,51 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   const size_t nA = kxn * g->nz * g->ny, nB = kxn * g->nz * c->py;
   c->spec_bytes = nS * 2 * c->esz;
   c->work_bytes = (nA + nB) * 4 * c->esz;  // W1 + W2 (pairs) cover A + B
+  c->bins_part_n = (size_t)kxn * c->py;    // >= workgroups of the z pass
+  c->norm_part_n = (size_t)g->nz * g->ny;  // >= workgroups of the x pass
   const size_t noct = kxn * (c->pz / 2 + 1) * (c->py / 2 + 1);
   HIPCHK(c, hipMalloc(&c->oct, noct * sizeof(double2)));
-  HIPCHK(c, hipMalloc(&c->spec, c->spec_bytes));
-  HIPCHK(c, hipMalloc(&c->work, c->work_bytes));
-  // partial-sum buffers sized for the largest grid of either precision
-  c->bins_part_n = (size_t)kxn * c->py;  // >= blocks of the z pass
-  HIPCHK(c, hipMalloc(&c->bins_part, c->bins_part_n * 64 * sizeof(double)));
-  c->norm_part_n = (size_t)g->nz * g->ny;  // >= blocks of the x pass
-  HIPCHK(c, hipMalloc(&c->norm_part, c->norm_part_n * sizeof(double2)));
-
+  fr3d_status st;
+  for (auto& L : c->lanes)
+    if ((st = alloc_lane_geometry(c, L))) return st;
+  Lane& L0 = c->lanes[0];
   // kernel spectrum in FP64 through full (unpruned) passes; temporaries freed after
   double2 *Ak = nullptr, *Bk = nullptr;
   HIPCHK(c, hipMalloc(&Ak, nS * sizeof(double2)));
   hipError_t e2 = hipMalloc(&Bk, nS * sizeof(double2));
   if (e2 != hipSuccess) { (void)hipFree(Ak); return fail(c, FR3D_E_NOMEM, "kernel spectrum workspace: %s", hipGetErrorString(e2)); }
   void *twx, *twy, *twz;
-  fr3d_status st = FR3D_OK;
   if ((st = get_twiddles(c, c->px, true, &twx)) || (st = get_twiddles(c, c->py, true, &twy)) ||
       (st = get_twiddles(c, c->pz, true, &twz))) {
     (void)hipFree(Ak); (void)hipFree(Bk);
     return st;
   }
-  FwdArgs a = fwd_args(c, true);
-  const Launch L{c->stream, nullptr, nullptr};
-  hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, L);
-  if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, L);
-  if (le == hipSuccess) le = launch_fz<double>(c->pz, 1, Bk, c->oct, a, (const double2*)twz, L);
+  FwdArgs a = fwd_args(c, L0, true);
+  const Launch Lk{L0.stream, nullptr, nullptr};
+  hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, Lk);
+  if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, Lk);
+  if (le == hipSuccess) le = launch_fz<double>(c->pz, 1, Bk, c->oct, a, (const double2*)twz, Lk);
+  const unsigned nb = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 1024);
   if (le == hipSuccess) {
-    const unsigned nb = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 1024);
-    hipLaunchKernelGGL(k_smax, dim3(nb), dim3(NT), 0, c->stream, c->oct, (long long)noct, (double*)Ak,
-                       c->tickets + 3, c->scal);
+    hipLaunchKernelGGL(k_smax_part, dim3(nb), dim3(NT), 0, L0.stream, c->oct, (long long)noct, (double*)Ak);
     le = hipGetLastError();
   }
-  if (le == hipSuccess) le = hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-  if (le == hipSuccess) le = hipStreamSynchronize(c->stream);
+  if (le == hipSuccess) {
+    hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(NT), 0, L0.stream, (const double*)Ak, (int)nb, L0.scal);
+    le = hipGetLastError();
+  }
+  if (le == hipSuccess) le = hipMemcpyAsync(L0.scal_host, L0.scal, sizeof(double), hipMemcpyDeviceToHost, L0.stream);
+  if (le == hipSuccess) le = hipStreamSynchronize(L0.stream);
   (void)hipFree(Ak);
   (void)hipFree(Bk);
   if (le != hipSuccess) return fail(c, FR3D_E_DEVICE, "kernel spectrum: %s", hipGetErrorString(le));
-  c->smax = c->scal_host[0];
+  c->smax = L0.scal_host[0];
   if (!(c->smax > 0) || !std::isfinite(c->smax)) return fail(c, FR3D_E_DEVICE, "kernel spectrum has no energy");
-  // precision twiddles for the data passes
   const bool dbl = c->esz == 8;
   if ((st = get_twiddles(c, c->px, dbl, &twx)) || (st = get_twiddles(c, c->py, dbl, &twy)) ||
       (st = get_twiddles(c, c->pz, dbl, &twz)))
     return st;
   c->has_kernel = true;
-  c->has_data = false;
   return FR3D_OK;
 }
 
@@ -626,46 +823,17 @@ fr3d_status fr3d_set_data(fr3d_ctx* c, const void* F, double delta) {
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!F) return fail(c, FR3D_E_INVALID, "F is null");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(c, FR3D_E_INVALID, "delta must be finite and >= 0");
-  c->delta = delta;
-  fr3d_status s = c->esz == 8 ? forward_data<double>(c, (const double*)F) : forward_data<float>(c, (const float*)F);
-  if (s) return s;
-  c->has_data = true;
-  return FR3D_OK;
+  return set_data_lane(c, c->lanes[0], F, delta);
 }
 
-static fr3d_status run_search(fr3d_ctx* c, const Ctrl& init, int max_evals, void* zeta, fr3d_report* rep) {
-  if (c->timing) tcollect(c);
-  fr3d_status s = launch_ctrl(c, init);
-  if (s) return s;
-  const int chunk = std::max(1, env_int("FR3D_EVAL_CHUNK", 4));
-  int launched = 0;
-  for (;;) {
-    const int k = std::min(chunk, max_evals - launched);
-    for (int i = 0; i < k; ++i) {
-      s = c->esz == 8 ? inverse<double>(c, 0, (double*)zeta) : inverse<float>(c, 0, (float*)zeta);
-      if (s) return s;
-    }
-    launched += k;
-    if ((s = read_ctrl(c))) return s;
-    if (!c->ctrl_host->active || launched >= max_evals) break;
-  }
-  if (c->timing) tcollect(c, c->ctrl_host->n_evals);
-  if (c->ctrl_host->active) return fail(c, FR3D_E_DEVICE, "alpha search did not finish in %d evaluations", max_evals);
-  if (rep) fill_report(c, rep);
-  return FR3D_OK;
-}
-
-fr3d_status fr3d_solve_alpha(fr3d_ctx* c, double alpha_rel, void* zeta, fr3d_report* rep) {
-  // alpha_rel is in the context's alpha units (geom.alpha_relative)
+fr3d_status fr3d_solve_alpha(fr3d_ctx* c, double alpha, void* zeta, fr3d_report* rep) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, true)) return FR3D_E_STATE;
   if (!zeta) return fail(c, FR3D_E_INVALID, "zeta is null");
-  if (!(alpha_rel > 0) || !std::isfinite(alpha_rel)) return fail(c, FR3D_E_INVALID, "alpha must be finite and > 0");
-  Ctrl v = ctrl_base(c);
-  v.state = ST_FIXED;
-  v.t = std::log10(alpha_rel);
-  v.alpha_abs = alpha_rel * v.a_scale;
-  return run_search(c, v, 1, zeta, rep);
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(c, FR3D_E_INVALID, "alpha must be finite and > 0");
+  fr3d_status s = fixed_search(c, c->lanes[0], alpha);
+  if (s) return s;
+  return run_search(c, 1, zeta, rep);
 }
 
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zeta, fr3d_report* rep) {
@@ -673,26 +841,98 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
   if (!need(c, true, true)) return FR3D_E_STATE;
   if (!zeta) return fail(c, FR3D_E_INVALID, "zeta is null");
   fr3d_dp_opts d;
-  fr3d_dp_opts_default(&d);
-  if (o) d = *o;
-  if (!(d.log10_alpha_lo < d.log10_alpha_hi) || !std::isfinite(d.log10_alpha_lo) || !std::isfinite(d.log10_alpha_hi) ||
-      d.max_steps < 0 || d.max_steps > 200 || !(d.tol >= 0) || !(d.tau > 0) || !(d.h_op >= 0) || !(d.mu >= 0))
-    return fail(c, FR3D_E_INVALID, "bad search options");
-  if (d.use_predictor) return fail(c, FR3D_E_STATE, "no predictor loaded");
-  Ctrl v = ctrl_base(c);
-  v.lo = d.log10_alpha_lo;
-  v.hi = d.log10_alpha_hi;
-  v.max_steps = d.max_steps;
-  v.tol = d.tol;
-  v.acc_lo = d.accept_lo;
-  v.acc_hi = d.accept_hi;
-  v.tau = d.tau;
-  v.h_op = d.h_op;
-  v.mu = d.mu;
-  v.state = ST_HI;
-  v.t = v.hi;
-  v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
-  return run_search(c, v, 2 + d.max_steps + 1, zeta, rep);
+  fr3d_status s = check_opts(c, o, &d);
+  if (s) return s;
+  int max_evals = 0;
+  if ((s = start_search(c, c->lanes[0], d, &max_evals))) return s;
+  return run_search(c, max_evals, zeta, rep);
+}
+
+// Batch scheduler: instance i goes to the next free lane, which runs
+// set_data, the search and (optionally) recovery on its own stream.  Each lane
+// advances one evaluation at a time; the host polls the lanes' completion
+// events and enqueues the next step of whichever lane is ready, so the lanes'
+// work overlaps on the device and no evaluation is launched after its search
+// has finished.
+fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const double* deltas, void* const* zetas,
+                             const fr3d_dp_opts* o, const void* V0, double c0, void* const* c_out,
+                             fr3d_report* reps) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, false)) return FR3D_E_STATE;
+  if (n < 0 || (n > 0 && (!F || !deltas || !zetas || !reps))) return fail(c, FR3D_E_INVALID, "null batch arrays");
+  if (c_out && (!V0 || !(c0 > 0) || !std::isfinite(c0))) return fail(c, FR3D_E_INVALID, "recovery needs V0 and c0 > 0");
+  for (int i = 0; i < n; ++i) {
+    if (!F[i] || !zetas[i] || (c_out && !c_out[i])) return fail(c, FR3D_E_INVALID, "null array in batch item %d", i);
+    if (!(deltas[i] >= 0) || !std::isfinite(deltas[i])) return fail(c, FR3D_E_INVALID, "bad delta in batch item %d", i);
+  }
+  fr3d_dp_opts d;
+  fr3d_status s = check_opts(c, o, &d);
+  if (s) return s;
+  if ((s = ensure_lanes(c))) return s;
+  const int nl = (int)c->lanes.size();
+  // order: the caller's stream before every lane, every lane before the caller's stream
+  hipEvent_t fence;
+  HIPCHK(c, hipEventCreateWithFlags(&fence, hipEventDisableTiming));
+  HIPCHK(c, hipEventRecord(fence, c->lanes[0].stream));
+  for (int l = 1; l < nl; ++l) HIPCHK(c, hipStreamWaitEvent(c->lanes[l].stream, fence, 0));
+  enum { IDLE, SEARCH, RECOVER };
+  std::vector<int> item(nl, -1), state(nl, IDLE), launched(nl, 0), limit(nl, 0);
+  int next = 0, done = 0;
+  s = FR3D_OK;
+  while (done < n && s == FR3D_OK) {
+    bool progressed = false;
+    for (int l = 0; l < nl && s == FR3D_OK; ++l) {
+      Lane& L = c->lanes[l];
+      if (state[l] == IDLE) {
+        if (next >= n) continue;
+        const int i = next++;
+        item[l] = i;
+        if ((s = set_data_lane(c, L, F[i], deltas[i]))) break;
+        if ((s = start_search(c, L, d, &limit[l]))) break;
+        if ((s = eval_lane(c, L, zetas[i]))) break;
+        launched[l] = 1;
+        if ((s = post_ctrl(c, L))) break;
+        state[l] = SEARCH;
+        progressed = true;
+        continue;
+      }
+      const hipError_t q = hipEventQuery(L.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) { s = fail(c, FR3D_E_DEVICE, "lane %d: %s", l, hipGetErrorString(q)); break; }
+      progressed = true;
+      const int i = item[l];
+      if (state[l] == SEARCH) {
+        if (L.ctrl_host->active && launched[l] < limit[l]) {
+          if ((s = eval_lane(c, L, zetas[i]))) break;
+          launched[l] += 1;
+          if ((s = post_ctrl(c, L))) break;
+          continue;
+        }
+        if (L.ctrl_host->active) { s = fail(c, FR3D_E_DEVICE, "search of item %d did not finish", i); break; }
+        fill_report(*L.ctrl_host, &reps[i]);
+        if (c->timing) tcollect(c, L, L.ctrl_host->n_evals);
+        if (c_out) {
+          if ((s = launch_recover(c, L, zetas[i], V0, c0, c_out[i], true))) break;
+          if (hipEventRecord(L.ev, L.stream) != hipSuccess) { s = fail(c, FR3D_E_DEVICE, "event record"); break; }
+          state[l] = RECOVER;
+          continue;
+        }
+      } else {
+        reps[i].n_clamped = (int64_t)L.scal_host[0];
+      }
+      state[l] = IDLE;
+      done += 1;
+    }
+    if (!progressed && s == FR3D_OK) std::this_thread::yield();
+  }
+  for (int l = 1; l < nl; ++l) {
+    (void)hipEventRecord(fence, c->lanes[l].stream);
+    (void)hipStreamWaitEvent(c->lanes[0].stream, fence, 0);
+  }
+  if (s != FR3D_OK)
+    for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
+  (void)hipEventDestroy(fence);
+  return s;
 }
 
 fr3d_status fr3d_recover_c(fr3d_ctx* c, const void* zeta, const void* V0, double c0, void* cout, int64_t* ncl) {
@@ -700,23 +940,12 @@ fr3d_status fr3d_recover_c(fr3d_ctx* c, const void* zeta, const void* V0, double
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!zeta || !V0 || !cout) return fail(c, FR3D_E_INVALID, "null array");
   if (!(c0 > 0) || !std::isfinite(c0)) return fail(c, FR3D_E_INVALID, "c0 must be finite and > 0");
-  const long long n = ncells(c);
-  double* part = (double*)c->norm_part;  // >= 2 nz ny doubles
-  const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
-  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 2048);
-  if (c->esz == 8)
-    hipLaunchKernelGGL(k_recover<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)zeta, (const double*)V0,
-                       ic2, fl, (double*)cout, n, part);
-  else
-    hipLaunchKernelGGL(k_recover<float>, dim3(nb), dim3(NT), 0, c->stream, (const float*)zeta, (const float*)V0, ic2,
-                       fl, (float*)cout, n, part);
-  LCHK(c, hipGetLastError());
+  Lane& L = c->lanes[0];
+  fr3d_status s = launch_recover(c, L, zeta, V0, c0, cout, ncl != nullptr);
+  if (s) return s;
   if (ncl) {
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, c->stream, (const double*)part, (int)nb, 1, 1, c->scal);
-    LCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    *ncl = (int64_t)c->scal_host[0];
+    HIPCHK(c, hipStreamSynchronize(L.stream));
+    *ncl = (int64_t)L.scal_host[0];
   }
   return FR3D_OK;
 }
@@ -738,11 +967,12 @@ fr3d_status fr3d_source_potential(fr3d_ctx* c, double A0, void* V0) {
       s.z[5 * k + l] = hz[k] * h;
     }
   const long long n = ncells(c);
+  Lane& L = c->lanes[0];
   dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 4096));
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_v0<double>, grid, dim3(256), 0, c->stream, (double*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
+    hipLaunchKernelGGL(k_v0<double>, grid, dim3(256), 0, L.stream, (double*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
   else
-    hipLaunchKernelGGL(k_v0<float>, grid, dim3(256), 0, c->stream, (float*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
+    hipLaunchKernelGGL(k_v0<float>, grid, dim3(256), 0, L.stream, (float*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
   LCHK(c, hipGetLastError());
   return FR3D_OK;
 }
@@ -751,15 +981,16 @@ fr3d_status fr3d_apply_operator(fr3d_ctx* c, const void* zeta, void* F) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!zeta || !F) return fail(c, FR3D_E_INVALID, "null array");
+  Lane& L = c->lanes[0];
   fr3d_status s;
   if (c->esz == 8) {
-    if ((s = forward_data<double>(c, (const double*)zeta))) return s;
-    s = inverse<double>(c, 1, (double*)F);
+    if ((s = forward_data<double>(c, L, (const double*)zeta))) return s;
+    s = inverse<double>(c, L, 1, (double*)F);
   } else {
-    if ((s = forward_data<float>(c, (const float*)zeta))) return s;
-    s = inverse<float>(c, 1, (float*)F);
+    if ((s = forward_data<float>(c, L, (const float*)zeta))) return s;
+    s = inverse<float>(c, L, 1, (float*)F);
   }
-  c->has_data = false;  // the spectrum buffer now holds zeta's transform
+  L.has_data = false;  // the spectrum buffer now holds zeta's transform
   return s;
 }
 
@@ -768,26 +999,27 @@ fr3d_status fr3d_add_noise(fr3d_ctx* c, void* F, const void* e, double delta_rel
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!F || !e) return fail(c, FR3D_E_INVALID, "null array");
   if (!(delta_rel >= 0) || !std::isfinite(delta_rel)) return fail(c, FR3D_E_INVALID, "delta_rel must be >= 0");
+  Lane& L = c->lanes[0];
   const long long n = ncells(c);
   const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 1024);
-  double* nrm = c->scal + 2;
-  double* part = (double*)c->norm_part;
+  double* nrm = L.scal + 2;
+  double* part = (double*)L.norm_part;
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_norms2<double>, dim3(nb), dim3(NT), 0, c->stream, (const double*)F, (const double*)e, n, part);
+    hipLaunchKernelGGL(k_norms2<double>, dim3(nb), dim3(NT), 0, L.stream, (const double*)F, (const double*)e, n, part);
   else
-    hipLaunchKernelGGL(k_norms2<float>, dim3(nb), dim3(NT), 0, c->stream, (const float*)F, (const float*)e, n, part);
+    hipLaunchKernelGGL(k_norms2<float>, dim3(nb), dim3(NT), 0, L.stream, (const float*)F, (const float*)e, n, part);
   LCHK(c, hipGetLastError());
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, c->stream, (const double*)part, (int)nb, 2, 2, nrm);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, L.stream, (const double*)part, (int)nb, 2, 2, nrm);
   LCHK(c, hipGetLastError());
   dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 4096));
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_add_noise<double>, grid, dim3(256), 0, c->stream, (double*)F, (const double*)e, n, delta_rel, nrm);
+    hipLaunchKernelGGL(k_add_noise<double>, grid, dim3(256), 0, L.stream, (double*)F, (const double*)e, n, delta_rel, nrm);
   else
-    hipLaunchKernelGGL(k_add_noise<float>, grid, dim3(256), 0, c->stream, (float*)F, (const float*)e, n, delta_rel, nrm);
+    hipLaunchKernelGGL(k_add_noise<float>, grid, dim3(256), 0, L.stream, (float*)F, (const float*)e, n, delta_rel, nrm);
   LCHK(c, hipGetLastError());
-  HIPCHK(c, hipMemcpyAsync(c->scal_host, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (delta) *delta = delta_rel * std::sqrt(c->scal_host[0]);
+  HIPCHK(c, hipMemcpyAsync(L.scal_host, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+  HIPCHK(c, hipStreamSynchronize(L.stream));
+  if (delta) *delta = delta_rel * std::sqrt(L.scal_host[0]);
   return FR3D_OK;
 }
 
@@ -796,7 +1028,7 @@ fr3d_status fr3d_get_octant(fr3d_ctx* c, void* out, int64_t bytes) {
   if (!need(c, true, false)) return FR3D_E_STATE;
   const size_t n = (size_t)c->kxn * (c->pz / 2 + 1) * (c->py / 2 + 1) * sizeof(double2);
   if (!out || bytes < (int64_t)n) return fail(c, FR3D_E_INVALID, "need %zu bytes", n);
-  HIPCHK(c, hipMemcpyAsync(out, c->oct, n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->oct, n, hipMemcpyDeviceToDevice, c->lanes[0].stream));
   return FR3D_OK;
 }
 
@@ -804,15 +1036,16 @@ fr3d_status fr3d_get_data_spectrum(fr3d_ctx* c, void* out, int64_t bytes) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (!out || bytes < (int64_t)c->spec_bytes) return fail(c, FR3D_E_INVALID, "need %zu bytes", c->spec_bytes);
-  HIPCHK(c, hipMemcpyAsync(out, c->spec, c->spec_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->lanes[0].spec, c->spec_bytes, hipMemcpyDeviceToDevice, c->lanes[0].stream));
   return FR3D_OK;
 }
 
 fr3d_status fr3d_get_features(fr3d_ctx* c, float* feat, double* energy) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, true)) return FR3D_E_STATE;
-  if (feat) HIPCHK(c, hipMemcpyAsync(feat, c->feat, 65 * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-  if (energy) HIPCHK(c, hipMemcpyAsync(energy, c->energy, 64 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  Lane& L = c->lanes[0];
+  if (feat) HIPCHK(c, hipMemcpyAsync(feat, L.feat, 65 * sizeof(float), hipMemcpyDeviceToDevice, L.stream));
+  if (energy) HIPCHK(c, hipMemcpyAsync(energy, L.energy, 64 * sizeof(double), hipMemcpyDeviceToDevice, L.stream));
   return FR3D_OK;
 }
 
@@ -825,18 +1058,151 @@ fr3d_status fr3d_get_smax(fr3d_ctx* c, double* smax) {
 
 fr3d_status fr3d_set_timing(fr3d_ctx* c, int32_t enable) {
   if (!c) return FR3D_E_INVALID;
-  if (c->timing && !enable) tcollect(c);
+  for (auto& L : c->lanes) {
+    (void)hipStreamSynchronize(L.stream);
+    tcollect(c, L);
+  }
   c->timing = enable != 0;
   return FR3D_OK;
 }
 
 fr3d_status fr3d_get_timing(fr3d_ctx* c, int32_t pass, double* total_ms, int64_t* launches) {
   if (!c || pass < 0 || pass > 5) return FR3D_E_INVALID;
-  tcollect(c);
+  for (auto& L : c->lanes) {
+    (void)hipStreamSynchronize(L.stream);
+    tcollect(c, L);
+  }
   if (total_ms) *total_ms = c->acc_ms[pass];
   if (launches) *launches = c->cnt[pass];
   c->acc_ms[pass] = 0;
   c->cnt[pass] = 0;
+  return FR3D_OK;
+}
+
+// ------------------------------------------------------------ predictor
+fr3d_status fr3d_predictor_set(fr3d_ctx* c, const float* params, int64_t n_params, const float* norm) {
+  if (!c) return FR3D_E_INVALID;
+  if (!params || !norm || n_params != MLP_NP) return fail(c, FR3D_E_INVALID, "need %d parameters and norm[%d]", MLP_NP, MLP_NNORM);
+  for (int i = 0; i < MLP_IN; ++i)
+    if (!(norm[MLP_IN + i] > 0) || !std::isfinite(norm[MLP_IN + i]))
+      return fail(c, FR3D_E_INVALID, "feature deviations must be finite and > 0");
+  if (!(norm[2 * MLP_IN + 1] > 0) || !std::isfinite(norm[2 * MLP_IN + 1]))
+    return fail(c, FR3D_E_INVALID, "target deviation must be finite and > 0");
+  fr3d_status s = pred_alloc(c);
+  if (s) return s;
+  hipStream_t st = c->lanes[0].stream;
+  HIPCHK(c, hipMemcpyAsync(c->pred_p, params, MLP_NP * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->pred_norm, norm, MLP_NNORM * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemsetAsync(c->pred_m, 0, MLP_NP * sizeof(float), st));
+  HIPCHK(c, hipMemsetAsync(c->pred_v, 0, MLP_NP * sizeof(float), st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  c->pred_step = 0;
+  c->has_pred = true;
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_predictor_get(fr3d_ctx* c, float* params, float* norm) {
+  if (!c) return FR3D_E_INVALID;
+  if (!c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  hipStream_t st = c->lanes[0].stream;
+  if (params) HIPCHK(c, hipMemcpyAsync(params, c->pred_p, MLP_NP * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (norm) HIPCHK(c, hipMemcpyAsync(norm, c->pred_norm, MLP_NNORM * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_predictor_forward(fr3d_ctx* c, const float* X, int32_t B, float* y) {
+  if (!c) return FR3D_E_INVALID;
+  if (!c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  if (!X || !y || B <= 0) return fail(c, FR3D_E_INVALID, "need X, y and B > 0");
+  LCHK(c, mlp_forward(c->pred_p, c->pred_norm, X, B, y, nullptr, nullptr, c->lanes[0].stream));
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_predictor_train_step(fr3d_ctx* c, const float* X, const float* t, int32_t B, double lr,
+                                      float* loss, float* grad) {
+  if (!c) return FR3D_E_INVALID;
+  if (!c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  if (!X || !t || B <= 0 || B > 65536) return fail(c, FR3D_E_INVALID, "need X, t and 0 < B <= 65536");
+  if (!(lr >= 0) || !std::isfinite(lr)) return fail(c, FR3D_E_INVALID, "lr must be finite and >= 0");
+  fr3d_status s = pred_ensure_work(c, B);
+  if (s) return s;
+  MlpWork w;
+  mlp_work_carve(&w, c->pred_work, c->pred_cap);
+  hipStream_t st = c->lanes[0].stream;
+  LCHK(c, mlp_forward(c->pred_p, c->pred_norm, X, B, nullptr, &w, nullptr, st));
+  const long long step = lr > 0 ? c->pred_step + 1 : c->pred_step;
+  const double c1 = 1.0 - std::pow(0.9, (double)std::max(1LL, step));
+  const double c2 = 1.0 - std::pow(0.999, (double)std::max(1LL, step));
+  LCHK(c, mlp_backward_adam(c->pred_p, c->pred_norm, t, B, &w, c->pred_g, c->pred_loss, c->pred_m, c->pred_v, lr, c1,
+                            c2, st));
+  if (lr > 0) c->pred_step = step;
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, c->pred_loss, sizeof(float), hipMemcpyDeviceToDevice, st));
+  if (grad) HIPCHK(c, hipMemcpyAsync(grad, c->pred_g, MLP_NP * sizeof(float), hipMemcpyDeviceToDevice, st));
+  return FR3D_OK;
+}
+
+// File: "FR3DMLP1", int32 n_params, int32 n_norm, int64 step, params, norm,
+// Adam m, Adam v (FP32 little-endian), uint64 FNV-1a of everything before it.
+fr3d_status fr3d_predictor_save(fr3d_ctx* c, const char* path) {
+  if (!c || !path) return FR3D_E_INVALID;
+  if (!c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  std::vector<float> p(MLP_NP), nm(MLP_NNORM), m(MLP_NP), v(MLP_NP);
+  hipStream_t st = c->lanes[0].stream;
+  HIPCHK(c, hipMemcpyAsync(p.data(), c->pred_p, MLP_NP * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(nm.data(), c->pred_norm, MLP_NNORM * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(m.data(), c->pred_m, MLP_NP * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(v.data(), c->pred_v, MLP_NP * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  std::string buf("FR3DMLP1");
+  const int32_t np = MLP_NP, nn = MLP_NNORM;
+  const int64_t step = c->pred_step;
+  buf.append((const char*)&np, 4).append((const char*)&nn, 4).append((const char*)&step, 8);
+  buf.append((const char*)p.data(), p.size() * 4).append((const char*)nm.data(), nm.size() * 4);
+  buf.append((const char*)m.data(), m.size() * 4).append((const char*)v.data(), v.size() * 4);
+  const uint64_t h = fnv1a(buf.data(), buf.size());
+  buf.append((const char*)&h, 8);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, FR3D_E_INVALID, "cannot open %s for writing", path);
+  const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
+  const int cl = std::fclose(f);
+  if (w != buf.size() || cl != 0) return fail(c, FR3D_E_INVALID, "write to %s failed", path);
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_predictor_load(fr3d_ctx* c, const char* path) {
+  if (!c || !path) return FR3D_E_INVALID;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, FR3D_E_INVALID, "cannot open %s", path);
+  std::string buf;
+  char tmp[65536];
+  size_t r;
+  while ((r = std::fread(tmp, 1, sizeof tmp, f)) > 0) buf.append(tmp, r);
+  std::fclose(f);
+  const size_t want = 8 + 16 + (size_t)(3 * MLP_NP + MLP_NNORM) * 4 + 8;
+  if (buf.size() != want || buf.compare(0, 8, "FR3DMLP1") != 0) return fail(c, FR3D_E_INVALID, "%s: not a predictor file", path);
+  uint64_t h;
+  std::memcpy(&h, buf.data() + buf.size() - 8, 8);
+  if (h != fnv1a(buf.data(), buf.size() - 8)) return fail(c, FR3D_E_INVALID, "%s: checksum mismatch", path);
+  int32_t np, nn;
+  int64_t step;
+  std::memcpy(&np, buf.data() + 8, 4);
+  std::memcpy(&nn, buf.data() + 12, 4);
+  std::memcpy(&step, buf.data() + 16, 8);
+  if (np != MLP_NP || nn != MLP_NNORM) return fail(c, FR3D_E_INVALID, "%s: wrong network shape", path);
+  std::vector<float> all((buf.size() - 32) / 4);
+  std::memcpy(all.data(), buf.data() + 24, all.size() * 4);
+  const float* p = all.data();
+  const float* nm = p + MLP_NP;
+  const float* m = nm + MLP_NNORM;
+  const float* v = m + MLP_NP;
+  fr3d_status s = fr3d_predictor_set(c, p, MLP_NP, nm);
+  if (s) return s;
+  hipStream_t st = c->lanes[0].stream;
+  HIPCHK(c, hipMemcpyAsync(c->pred_m, m, MLP_NP * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->pred_v, v, MLP_NP * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  c->pred_step = step;
   return FR3D_OK;
 }
 

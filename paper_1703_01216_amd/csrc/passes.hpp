@@ -44,7 +44,7 @@ __device__ __forceinline__ int energy_bin(const BinGeom& g, int kx, int ky, int 
   const long long mz = kz <= g.pz / 2 ? kz : kz - g.pz;
   const long long U = 4 * (mx * mx * g.fx + my * my * g.fy + mz * mz * g.fz);
   const long long U4 = 4096 * U;
-  int b = (int)floor(64.0 * sqrt((double)U / ((double)g.L3)));
+  int b = (int)(64.0f * sqrtf((float)U / (float)g.L3));  // estimate, corrected exactly below
   if ((long long)(b + 1) * (b + 1) * g.L3 <= U4) b += 1;
   if ((long long)b * b * g.L3 > U4) b -= 1;
   return b < 63 ? b : 63;

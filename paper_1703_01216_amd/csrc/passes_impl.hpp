@@ -192,11 +192,10 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     const double w = (kx == 0 || 2 * kx == a.bg.px) ? 1.0 : 2.0;
     int cur = -1;
     double acc = 0.0;
-    for (int e = tid; e < C * P; e += NT) {
-      const int kz = e / C, col = e % C;
+    auto visit = [&](int kz, int col) {
       const int ky = ky0 + col;
-      if (ky >= py) continue;
-      const c2<T> u = lds[e];
+      if (ky >= py) return;
+      const c2<T> u = lds[kz * LD + col];
       dst[(size_t)kz * py + ky] = u;
       const int b = energy_bin(a.bg, kx, ky, kz);
       if (b != cur) {
@@ -205,6 +204,15 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
         acc = 0.0;
       }
       acc += w * ((double)u.x * u.x + (double)u.y * u.y);
+    };
+    if constexpr (C <= NT && NT % C == 0) {
+      // each thread walks a run of consecutive kz in one column: its bin
+      // changes rarely, so few LDS atomics
+      constexpr int RPC = C * P / NT;
+      const int col = tid % C, k0 = (tid / C) * RPC;
+      for (int j = 0; j < RPC; ++j) visit(k0 + j, col);
+    } else {
+      for (int e = tid; e < C * P; e += NT) visit(e / C, e % C);
     }
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();

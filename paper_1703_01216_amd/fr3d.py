@@ -26,8 +26,12 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch",
+    "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
+    "fr3d_predictor_save", "fr3d_predictor_load",
 ]
+N_PARAMS = 25089
+N_NORM = 132
 
 
 class Geom(ctypes.Structure):
@@ -47,7 +51,8 @@ class DpOpts(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("residual", ctypes.c_double),
                 ("zeta_norm", ctypes.c_double), ("delta", ctypes.c_double),
-                ("target", ctypes.c_double), ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("target", ctypes.c_double), ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("n_clamped", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +90,15 @@ def load_library(path: str = LIB_PATH):
         "fr3d_get_timing": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "fr3d_status_string": (ctypes.c_char_p, [I32]),
         "fr3d_last_error": (ctypes.c_char_p, [P]),
+        "fr3d_set_lanes": (I32, [P, I32]),
+        "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
+                                   ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), ctypes.POINTER(Report)]),
+        "fr3d_predictor_set": (I32, [P, ctypes.POINTER(ctypes.c_float), I64, ctypes.POINTER(ctypes.c_float)]),
+        "fr3d_predictor_get": (I32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+        "fr3d_predictor_forward": (I32, [P, P, I32, P]),
+        "fr3d_predictor_train_step": (I32, [P, P, P, I32, D, P, P]),
+        "fr3d_predictor_save": (I32, [P, ctypes.c_char_p]),
+        "fr3d_predictor_load": (I32, [P, ctypes.c_char_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -229,6 +243,55 @@ class Context:
         d = ctypes.c_double()
         self._chk(self._lib.fr3d_get_smax(self._ctx, ctypes.byref(d)))
         return d.value
+
+    def set_lanes(self, lanes: int):
+        self._chk(self._lib.fr3d_set_lanes(self._ctx, int(lanes)))
+
+    def solve_batch(self, F_list, deltas, zetas, opts: DpOpts | None = None, V0=None, c0=1.0, c_list=None, **kw):
+        n = len(F_list)
+        if len(deltas) != n or len(zetas) != n or (c_list is not None and len(c_list) != n):
+            raise ValueError("batch lists must have equal lengths")
+        o = opts if opts is not None else default_opts(**kw)
+        PA = ctypes.c_void_p * max(n, 1)
+        Fa = PA(*[self._arr(f, "F").value for f in F_list])
+        Za = PA(*[self._arr(z, "zeta").value for z in zetas])
+        Da = (ctypes.c_double * max(n, 1))(*[float(d) for d in deltas])
+        reps = (Report * max(n, 1))()
+        Ca = PA(*[self._arr(cc, "c").value for cc in c_list]) if c_list is not None else None
+        v0 = self._arr(V0, "V0") if c_list is not None else None
+        self._chk(self._lib.fr3d_solve_batch(self._ctx, n, Fa, Da, Za, ctypes.byref(o), v0, float(c0), Ca, reps))
+        return [reps[i].as_dict() for i in range(n)]
+
+    # ------------------------------------------------------------ predictor
+    def predictor_set(self, params, norm):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        nm = np.ascontiguousarray(norm, dtype=np.float32).ravel()
+        if p.size != N_PARAMS or nm.size != N_NORM:
+            raise ValueError(f"need {N_PARAMS} parameters and {N_NORM} normalisation values")
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._chk(self._lib.fr3d_predictor_set(self._ctx, p.ctypes.data_as(fp), p.size, nm.ctypes.data_as(fp)))
+
+    def predictor_get(self):
+        import numpy as np
+        p = np.empty(N_PARAMS, dtype=np.float32)
+        nm = np.empty(N_NORM, dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._chk(self._lib.fr3d_predictor_get(self._ctx, p.ctypes.data_as(fp), nm.ctypes.data_as(fp)))
+        return p, nm
+
+    def predictor_forward(self, X, y):
+        self._chk(self._lib.fr3d_predictor_forward(self._ctx, _ptr(X), int(X.shape[0]), _ptr(y)))
+
+    def predictor_train_step(self, X, t, lr, loss=None, grad=None):
+        self._chk(self._lib.fr3d_predictor_train_step(self._ctx, _ptr(X), _ptr(t), int(X.shape[0]), float(lr),
+                                                      _ptr(loss), _ptr(grad)))
+
+    def predictor_save(self, path):
+        self._chk(self._lib.fr3d_predictor_save(self._ctx, os.fsencode(path)))
+
+    def predictor_load(self, path):
+        self._chk(self._lib.fr3d_predictor_load(self._ctx, os.fsencode(path)))
 
     def set_timing(self, on: bool):
         self._chk(self._lib.fr3d_set_timing(self._ctx, 1 if on else 0))

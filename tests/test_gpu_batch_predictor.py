@@ -1,0 +1,211 @@
+"""GPU checks of the batch scheduler and the alpha predictor, through the C-ABI.
+
+* Batch: every item's zeta and report equal the single-solve results bit for bit
+  (the lanes run the same kernels on their own streams).
+* Predictor: BF16-MFMA/FP32 forward and gradients against the BF16-emulating
+  FP64 oracle on identical weights and inputs (<= 2e-3 relative L2 per
+  tensor); Adam against its formula; checkpoint round trip; the seeded search
+  takes the oracle rule's decisions (FP64 path).
+"""
+import numpy as np
+import pytest
+
+from oracle import discrepancy, mlp, tikhonov
+from oracle.geometry import sample_kernel
+
+from gpu_helpers import geom, instance, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fr3d():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_01216_amd import fr3d as m
+    return m
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def flat_params(p):
+    return np.concatenate([p[name].ravel() for name, _ in mlp.PARAM_SHAPES]).astype(np.float32)
+
+
+def unflat(v):
+    out, o = {}, 0
+    for name, shape in mlp.PARAM_SHAPES:
+        n = int(np.prod(shape))
+        out[name] = np.asarray(v[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
+def identity_norm():
+    nm = np.zeros(132, np.float32)
+    nm[65:130] = 1.0
+    nm[131] = 1.0
+    return nm
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_batch_equals_single(fr3d, precision):
+    g = geom(16, 16, 16)
+    dt = torch.float64 if precision == 64 else torch.float32
+    items = [instance(g, 60 + i, (0.01, 0.03, 0.05)[i % 3]) for i in range(5)]
+    Fs = [torch.tensor(d["F"], dtype=dt, device="cuda") for d in items]
+    deltas = [d["delta"] for d in items]
+    c = fr3d.Context()
+    c.load_kernel(16, 16, 16, precision=precision)
+    single = []
+    for F, dl in zip(Fs, deltas):
+        z = torch.empty_like(F)
+        c.set_data(F, dl)
+        single.append((c.solve_discrepancy(z), z))
+    c.set_lanes(3)
+    zs = [torch.empty_like(F) for F in Fs]
+    V = torch.empty_like(Fs[0])
+    c.source_potential(V)
+    cs = [torch.empty_like(F) for F in Fs]
+    reps = c.solve_batch(Fs, deltas, zs, V0=V, c0=1.0, c_list=cs)
+    torch.cuda.synchronize()
+    for (rep1, z1), rep2, z2, cc in zip(single, reps, zs, cs):
+        assert np.array_equal(host(z1), host(z2))
+        for k in ("alpha", "residual", "zeta_norm", "n_evals", "flags"):
+            assert rep1[k] == rep2[k]
+        n_cl = c.recover_c(z2, V, 1.0, torch.empty_like(z2))
+        assert rep2["n_clamped"] == n_cl
+
+
+def test_batch_empty_and_errors(fr3d):
+    g = geom(8, 8, 8)
+    c = fr3d.Context()
+    c.load_kernel(8, 8, 8, precision=32)
+    assert c.solve_batch([], [], []) == []
+    F = torch.zeros((8, 8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(fr3d.Fr3dError):
+        c.solve_batch([F], [-1.0], [torch.empty_like(F)])
+    with pytest.raises(fr3d.Fr3dError):
+        c.set_lanes(0)
+
+
+def test_predictor_forward_matches_oracle(fr3d):
+    p = mlp.init_params(5)
+    flat = flat_params(p)
+    p32 = unflat(flat)
+    rg = np.random.default_rng(7)
+    X = rg.standard_normal((200, 65)).astype(np.float32)
+    c = fr3d.Context()
+    c.predictor_set(flat, identity_norm())
+    y = torch.empty(200, dtype=torch.float32, device="cuda")
+    c.predictor_forward(torch.tensor(X, device="cuda"), y)
+    yo, _ = mlp.forward(p32, X.astype(np.float64), bf16=True)
+    assert rel_l2(host(y), yo) < 2e-3
+    # normalisation and de-normalisation are applied around the network
+    nm = identity_norm()
+    nm[:65] = 0.5
+    nm[65:130] = 2.0
+    nm[130], nm[131] = -4.0, 1.5
+    c.predictor_set(flat, nm)
+    c.predictor_forward(torch.tensor(X, device="cuda"), y)
+    yo2, _ = mlp.forward(p32, (X.astype(np.float64) - 0.5) / 2.0, bf16=True)
+    assert rel_l2(host(y), -4.0 + 1.5 * yo2) < 2e-3
+
+
+def test_predictor_gradients_match_oracle(fr3d):
+    p = mlp.init_params(9)
+    flat = flat_params(p)
+    p32 = unflat(flat)
+    rg = np.random.default_rng(8)
+    B = 256
+    X = rg.standard_normal((B, 65)).astype(np.float32)
+    t = rg.standard_normal(B).astype(np.float32)
+    c = fr3d.Context()
+    c.predictor_set(flat, identity_norm())
+    grad = torch.empty(fr3d.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    c.predictor_train_step(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"), 0.0, loss, grad)
+    yo, cache = mlp.forward(p32, X.astype(np.float64), bf16=True)
+    go = mlp.backward(p32, cache, t.astype(np.float64), bf16=True)
+    gg = unflat(host(grad))
+    for name, _ in mlp.PARAM_SHAPES:
+        assert rel_l2(gg[name], go[name]) < 2e-3, name
+    assert float(host(loss)[0]) == pytest.approx(mlp.loss(yo, t), rel=2e-3)
+    # lr = 0 leaves the parameters alone
+    p_after, _ = c.predictor_get()
+    assert np.array_equal(p_after, flat)
+
+
+def test_predictor_adam_step(fr3d):
+    flat = flat_params(mlp.init_params(11))
+    rg = np.random.default_rng(9)
+    X = torch.tensor(rg.standard_normal((64, 65)).astype(np.float32), device="cuda")
+    t = torch.tensor(rg.standard_normal(64).astype(np.float32), device="cuda")
+    c = fr3d.Context()
+    c.predictor_set(flat, identity_norm())
+    grad = torch.empty(fr3d.N_PARAMS, dtype=torch.float32, device="cuda")
+    c.predictor_train_step(X, t, 1e-3, None, grad)
+    p1, _ = c.predictor_get()
+    g = host(grad)
+    # first Adam step from zero moments: p - lr g / (|g| + eps)  (bias corrected)
+    expect = flat.astype(np.float64) - 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.abs(p1 - expect).max() < 2e-6
+    # the loss decreases over a few steps on a fixed batch
+    losses = []
+    lt = torch.empty(1, dtype=torch.float32, device="cuda")
+    for _ in range(30):
+        c.predictor_train_step(X, t, 1e-3, lt, None)
+        losses.append(float(host(lt)[0]))
+    assert losses[-1] < losses[0]
+
+
+def test_predictor_checkpoint(fr3d, tmp_path):
+    flat = flat_params(mlp.init_params(12))
+    nm = identity_norm()
+    nm[130] = -3.0
+    c = fr3d.Context()
+    c.predictor_set(flat, nm)
+    path = str(tmp_path / "pred.bin")
+    c.predictor_save(path)
+    c2 = fr3d.Context()
+    c2.predictor_load(path)
+    p2, n2 = c2.predictor_get()
+    assert np.array_equal(p2, flat) and np.array_equal(n2, nm)
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 0xFF
+    bad = str(tmp_path / "bad.bin")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(fr3d.Fr3dError) as ei:
+        c2.predictor_load(bad)
+    assert ei.value.status == fr3d.E_INVALID
+
+
+@pytest.mark.parametrize("bias", [-3.0, -6.5, 0.7, -20.0])
+def test_seeded_search_matches_rule_fp64(fr3d, bias):
+    # The network's output is steered by its last bias; the device search from
+    # that seed takes the oracle rule's decisions (FP64, same evaluations).
+    g = geom(16, 16, 16)
+    d = instance(g, 70, 0.02)
+    c = fr3d.Context()
+    c.load_kernel(16, 16, 16, precision=64)
+    p = mlp.init_params(13)
+    for k in ("W1", "W2", "w3"):
+        p[k] = p[k] * 0.0
+    p["b3"][:] = bias
+    c.predictor_set(flat_params(p), identity_norm())
+    F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    rep = c.solve_discrepancy(z, use_predictor=1)
+    khat = np.fft.fftn(sample_kernel(g))
+
+    def ev(a):
+        o = tikhonov.solve_spectral(g, khat, d["F"], a)
+        return o["r_norm"], o["zeta_norm"]
+    ref = discrepancy.seeded(ev, d["delta"], bias)
+    assert rep["flags"] == ref["flags"]
+    assert rep["n_evals"] == ref["n_evals"]
+    assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
