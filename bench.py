@@ -1,15 +1,22 @@
-"""Benchmark: regularised 3D solves per second at 256^3 to the discrepancy delta.
+"""Benchmark: regularised 3D solves per second at 256^3 to the discrepancy delta,
+learned alpha vs bisection.
 
-Workload (default): 128^3 grids on R and Y padded to 256^3, FP32 complex
-transforms with FP64 kernel spectrum, norms and alpha search; each instance
-has 5-10 Gaussian/box inclusions with amplitudes U[0.05, 0.8] and noise
-delta in {1%, 3%, 5%}.  One step solves a batch of instances: for each,
-set the data (forward transform), choose alpha by the discrepancy principle
-(bisection in log10 alpha over [1e-8, 1]) and recover c.  Inputs are
-synthesised on the GPU through the library's own forward operator before
-the timed region and stay resident in HBM.
+Workload: 128^3 grids on R and Y padded to 256^3 (default gap D = 160 cells),
+FP32 complex transforms with the FP64 kernel spectrum, norms and alpha search.
+A batch of instances with 5-10 Gaussian/box inclusions of amplitude
+U[0.05, 0.8] and noise delta cycling through 1%, 3%, 5% is synthesised on
+the GPU through the library's own forward operator before any timing and
+stays resident in HBM.  One step solves the whole batch with the lane
+scheduler: per instance the forward transform of F, the alpha search and the
+recovery of c.
 
-    python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--no-cpu]
+Three searches run on the same batch:
+  learned     -- the trained predictor's alpha first; accept r/delta in [0.9, 1.1],
+                 else decade walk + bisection to the same window (the headline value)
+  bisection   -- plain bisection over log10 alpha in [-8, 0] to the same window
+  bisection3  -- plain bisection to |r/delta - 1| <= 1e-3
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--lanes L] [--no-cpu]
 
 Prints one JSON line.  Only the CPU-baseline leg calls the oracle.
 """
@@ -17,7 +24,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -32,8 +38,9 @@ PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 
 
 def pass_bytes(n, esz=4):
-    """Algorithmic bytes of each pass for a cubic n^3 grid padded to P = 2n
-    (reads of nonzero inputs + writes of kept outputs; complex = 2*esz)."""
+    """Algorithmic bytes of each pass for a cubic n^3 grid padded to P = 2n:
+    reads of the nonzero inputs plus writes of the kept outputs (complex =
+    2 esz; the kernel-spectrum octant is FP64 complex)."""
     P = 2 * n
     kx = P // 2 + 1
     c = 2 * esz
@@ -48,22 +55,20 @@ def pass_bytes(n, esz=4):
     }
 
 
-def make_instances(ctx, torch, n, batch, first_index=0):
+def make_instances(ctx, torch, n, batch):
     from paper_1703_01216_amd import inputs
-    insts = []
     V0 = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
     ctx.source_potential(V0, 1.0)
+    Fs, deltas = [], []
     for i in range(batch):
-        inst = inputs.workload_instance(2, first_index + i, n=n)
-        xi = torch.tensor(inst["xi"], dtype=torch.float32, device="cuda")
-        zeta_true = xi * V0
-        F = torch.empty_like(zeta_true)
-        ctx.apply_operator(zeta_true, F)
-        e = torch.tensor(inst["noise"], dtype=torch.float32, device="cuda")
-        delta = ctx.add_noise(F, e, inst["delta_rel"])
-        insts.append(dict(F=F, delta=delta, zeta=torch.empty_like(F), c=torch.empty_like(F),
-                          delta_rel=inst["delta_rel"], index=first_index + i))
-    return insts, V0
+        seed = inputs.instance_seed(2, i)
+        xi = inputs.xi_torch((n, n, n), inputs.inclusion_params((n, n, n), seed))
+        F = torch.empty_like(xi)
+        ctx.apply_operator(xi * V0, F)
+        e = inputs.noise_torch((n, n, n), seed)
+        deltas.append(ctx.add_noise(F, e, (0.01, 0.03, 0.05)[i % 3]))
+        Fs.append(F)
+    return Fs, deltas, V0
 
 
 def cpu_baseline(n, mean_evals, n_sample_evals=3):
@@ -82,11 +87,10 @@ def cpu_baseline(n, mean_evals, n_sample_evals=3):
     for k in range(n_sample_evals):
         tikhonov.solve_spectral(g, khat, d["F"], 10.0 ** (-2 - k))
     dt = (time.perf_counter() - t0) / n_sample_evals
-    value = 1.0 / (dt * mean_evals)
-    return {"value": value, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample_evals} oracle alpha evaluations (numpy.fft FP64, single thread) on one "
-                      f"{n}^3 instance padded to {2 * n}^3, {dt:.2f} s each, scaled to the GPU's mean "
-                      f"{mean_evals:.2f} evaluations per solve"}
+    return {"value": 1.0 / (dt * mean_evals), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample_evals} oracle alpha evaluations (numpy.fft FP64, single thread, each with its own "
+                      f"forward transform) on one {n}^3 instance padded to {2 * n}^3, {dt:.2f} s each, scaled to "
+                      f"the GPU learned path's mean {mean_evals:.2f} evaluations per solve"}
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
@@ -107,14 +111,50 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GB_s": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def run_mode(ctx, torch, Fs, deltas, V0, opts, steps, warmup, timing=False):
+    zs = [torch.empty_like(F) for F in Fs]
+    cs = [torch.empty_like(F) for F in Fs]
+    reps = None
+    for _ in range(warmup):
+        reps = ctx.solve_batch(Fs, deltas, zs, opts=opts, V0=V0, c0=1.0, c_list=cs)
+    torch.cuda.synchronize()
+    if timing:
+        ctx.set_timing(True)
+        for p in range(6):
+            ctx.get_timing(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals, flags = [], []
+    for _ in range(steps):
+        reps = ctx.solve_batch(Fs, deltas, zs, opts=opts, V0=V0, c0=1.0, c_list=cs)
+        evals += [r["n_evals"] for r in reps]
+        flags += [r["flags"] for r in reps]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing_out = None
+    if timing:
+        timing_out = {PASS_NAMES[p]: ctx.get_timing(p) for p in range(6)}
+        ctx.set_timing(False)
+    el = t1 - t0
+    n = len(Fs) * steps
+    reached = sum(1 for f in flags if (f & 3) == 0)
+    return dict(solves_per_s=n / el, ms_per_step=el / steps * 1e3, mean_evals=sum(evals) / len(evals),
+                reached_delta_frac=reached / len(flags),
+                noroot_low=sum(1 for f in flags if f & 2) / len(flags),
+                fallback_frac=sum(1 for f in flags if f & 16) / len(flags)), timing_out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--lanes", type=int, default=8)
+    ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="learned,bisection,bisection3")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 1 GiB device copy used to calibrate traffic counters")
     args = ap.parse_args()
@@ -135,63 +175,59 @@ def main():
     n = args.n
     ctx = fr3d.Context(0)
     ctx.load_kernel(n, n, n, precision=32)
-    insts, V0 = make_instances(ctx, torch, n, args.batch)
-    print(f"[bench] {len(insts)} instances of {n}^3 ready", file=sys.stderr, flush=True)
-
-    def step():
-        evals = []
-        for it in insts:
-            ctx.set_data(it["F"], it["delta"])
-            rep = ctx.solve_discrepancy(it["zeta"])
-            ctx.recover_c(it["zeta"], V0, 1.0, it["c"])
-            evals.append(rep["n_evals"])
-            it["rep"] = rep
-        return evals
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    for p in range(6):
-        ctx.get_timing(p)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evals = []
-    for _ in range(args.steps):
-        evals += step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = {PASS_NAMES[p]: ctx.get_timing(p) for p in range(6)}
-    ctx.set_timing(False)
-    elapsed = t1 - t0
-    solves = args.steps * len(insts)
-    value = solves / elapsed
-    mean_evals = sum(evals) / len(evals)
+    ctx.set_lanes(args.lanes)
+    modes = args.modes.split(",")
+    if "learned" in modes:
+        if not os.path.exists(args.predictor):
+            print(f"[bench] no predictor at {args.predictor}; skipping the learned search", file=sys.stderr)
+            modes.remove("learned")
+        else:
+            ctx.predictor_load(args.predictor)
+    Fs, deltas, V0 = make_instances(ctx, torch, n, args.batch)
+    print(f"[bench] {len(Fs)} instances of {n}^3 ready", file=sys.stderr, flush=True)
+    window = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
+    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **window),
+                 "bisection": fr3d.default_opts(**window),
+                 "bisection3": fr3d.default_opts(tol=1e-3)}
+    results, timing = {}, None
+    head = modes[0]
+    for m in modes:
+        r, tm = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup, timing=(m == head))
+        results[m] = r
+        if tm is not None:
+            timing = tm
+        print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)
     pb = pass_bytes(n)
     passes = {}
     for name, (ms, cnt) in timing.items():
         if cnt:
             avg = ms / cnt
-            passes[name] = {"avg_us": avg * 1e3, "launches": cnt, "GB_s": pb[name] / (avg * 1e-3) / 1e9}
-    dom = max(passes, key=lambda k: passes[k]["avg_us"] * passes[k]["launches"])
+            passes[name] = {"avg_us": avg * 1e3, "launches": cnt, "GB_s": pb[name] / (avg * 1e-3) / 1e9,
+                            "total_ms": ms}
+    dom = max(passes, key=lambda k: passes[k]["total_ms"])
     ach = passes[dom]["GB_s"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": pb[dom], "avg_launch_us": passes[dom]["avg_us"]}
+    H = results[head]
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": H["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": H["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{n}^3 grids padded to {2 * n}^3, batch {len(insts)} instances, "
-                               f"5-10 inclusions, delta 1/3/5%, bisection to tol 1e-3",
-                   "grid": n, "padded": 2 * n, "batch": len(insts), "search": "bisection",
-                   "mean_evals_per_solve": mean_evals},
+        "config": {"workload": f"{n}^3 grids padded to {2 * n}^3, batch of {len(Fs)} instances (5-10 inclusions, "
+                               f"delta 1/3/5%), forward transform + {head} alpha search to the discrepancy "
+                               f"+ recovery of c per solve, {args.lanes} lanes",
+                   "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
+                   "modes": results},
         "roofline": roofline,
         "passes": passes,
         "copy": copy,
     }
+    if "learned" in results and "bisection" in results:
+        out["config"]["speedup_learned_vs_bisection_same_window"] = (
+            results["learned"]["solves_per_s"] / results["bisection"]["solves_per_s"])
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, mean_evals)
+        out["cpu_baseline"] = cpu_baseline(n, H["mean_evals"])
     print(json.dumps(out))
 
 

@@ -143,7 +143,8 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void
 /* Solve n instances on the lanes: for item i, set the data F_devs[i] with
  * noise level deltas[i], choose alpha by the discrepancy principle (opts,
  * NULL = defaults) writing zeta_devs[i], and, if c_devs is not NULL, recover
- * c into c_devs[i] from V0_dev and c0.  Instances run concurrently, one per
+ * c into c_devs[i] from V0_dev and c0; feat_dev, if not NULL, receives each
+ * item's 65 predictor features (float [n][65], device).  Instances run concurrently, one per
  * lane; each lane advances one evaluation at a time and the host polls the
  * lanes, so no evaluation is launched after its search has ended.  The
  * caller's stream is ordered before and after the whole batch.  reps[i]
@@ -152,7 +153,7 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void
  * context's stream). */
 fr3d_status fr3d_solve_batch(fr3d_ctx* ctx, int32_t n, const void* const* F_devs, const double* deltas,
                              void* const* zeta_devs, const fr3d_dp_opts* opts, const void* V0_dev, double c0,
-                             void* const* c_devs, fr3d_report* reps);
+                             void* const* c_devs, float* feat_dev, fr3d_report* reps);
 
 /* Algorithm 1 step 4: xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2) on R; where
  * 1/c0^2 - xi < 1e-6/c0^2 the argument is clamped and the cell counted in

@@ -856,7 +856,7 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
 // has finished.
 fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const double* deltas, void* const* zetas,
                              const fr3d_dp_opts* o, const void* V0, double c0, void* const* c_out,
-                             fr3d_report* reps) {
+                             float* feat_out, fr3d_report* reps) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (n < 0 || (n > 0 && (!F || !deltas || !zetas || !reps))) return fail(c, FR3D_E_INVALID, "null batch arrays");
@@ -888,6 +888,12 @@ fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const
         const int i = next++;
         item[l] = i;
         if ((s = set_data_lane(c, L, F[i], deltas[i]))) break;
+        if (feat_out &&
+            hipMemcpyAsync(feat_out + (size_t)i * 65, L.feat, 65 * sizeof(float), hipMemcpyDeviceToDevice, L.stream) !=
+                hipSuccess) {
+          s = fail(c, FR3D_E_DEVICE, "feature copy");
+          break;
+        }
         if ((s = start_search(c, L, d, &limit[l]))) break;
         if ((s = eval_lane(c, L, zetas[i]))) break;
         launched[l] = 1;

@@ -92,7 +92,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_last_error": (ctypes.c_char_p, [P]),
         "fr3d_set_lanes": (I32, [P, I32]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
-                                   ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), ctypes.POINTER(Report)]),
+                                   ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
         "fr3d_predictor_set": (I32, [P, ctypes.POINTER(ctypes.c_float), I64, ctypes.POINTER(ctypes.c_float)]),
         "fr3d_predictor_get": (I32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
         "fr3d_predictor_forward": (I32, [P, P, I32, P]),
@@ -247,7 +247,8 @@ class Context:
     def set_lanes(self, lanes: int):
         self._chk(self._lib.fr3d_set_lanes(self._ctx, int(lanes)))
 
-    def solve_batch(self, F_list, deltas, zetas, opts: DpOpts | None = None, V0=None, c0=1.0, c_list=None, **kw):
+    def solve_batch(self, F_list, deltas, zetas, opts: DpOpts | None = None, V0=None, c0=1.0, c_list=None,
+                    feat=None, **kw):
         n = len(F_list)
         if len(deltas) != n or len(zetas) != n or (c_list is not None and len(c_list) != n):
             raise ValueError("batch lists must have equal lengths")
@@ -259,7 +260,10 @@ class Context:
         reps = (Report * max(n, 1))()
         Ca = PA(*[self._arr(cc, "c").value for cc in c_list]) if c_list is not None else None
         v0 = self._arr(V0, "V0") if c_list is not None else None
-        self._chk(self._lib.fr3d_solve_batch(self._ctx, n, Fa, Da, Za, ctypes.byref(o), v0, float(c0), Ca, reps))
+        if feat is not None and (feat.dtype != self.torch.float32 or feat.numel() < 65 * n or not feat.is_cuda):
+            raise ValueError("feat must be a float32 cuda tensor with room for n x 65 values")
+        self._chk(self._lib.fr3d_solve_batch(self._ctx, n, Fa, Da, Za, ctypes.byref(o), v0, float(c0), Ca,
+                                             _ptr(feat), reps))
         return [reps[i].as_dict() for i in range(n)]
 
     # ------------------------------------------------------------ predictor

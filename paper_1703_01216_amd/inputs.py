@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "instance_seed", "rng", "xi_blobs", "xi_inclusions", "xi_stress", "noise",
+    "instance_seed", "rng", "xi_blobs", "inclusion_params", "xi_inclusions", "xi_stress", "noise",
     "workload_instance",
 ]
 
@@ -77,22 +77,29 @@ def xi_blobs(shape, seed, count=3, amp=(0.1, 0.5), sigma=(2.0, 4.0), margin_frac
     return xi
 
 
-def xi_inclusions(shape, seed, count=(5, 10), amp=(0.05, 0.8), margin_frac=0.125):
-    """5-10 inclusions, Gaussian or box with probability 1/2 each.
-
-    Gaussian width s ~ U[n/16, n/8], box edge w ~ U[n/10, n/4] with n the
-    smallest grid extent; amplitudes ~ U[amp]."""
+def inclusion_params(shape, seed, count=(5, 10), amp=(0.05, 0.8), margin_frac=0.125):
+    """Parameters of 5-10 inclusions: list of (kind, centre (x,y,z), amplitude, size),
+    kind "gauss" (size = s ~ U[n/16, n/8]) or "box" (size = edge w ~ U[n/10, n/4]),
+    each with probability 1/2; n is the smallest grid extent."""
     g = rng(seed)
     n = min(shape)
     k = int(g.integers(count[0], count[1] + 1))
-    xi = np.zeros(shape, dtype=np.float64)
+    out = []
     for _ in range(k):
         c = _draw_centre(g, shape, margin_frac)
         a = g.uniform(*amp)
         if g.uniform() < 0.5:
-            xi += a * _gauss(shape, c, g.uniform(n / 16, n / 8))
+            out.append(("gauss", c, a, g.uniform(n / 16, n / 8)))
         else:
-            xi += a * _box(shape, c, g.uniform(n / 10, n / 4))
+            out.append(("box", c, a, g.uniform(n / 10, n / 4)))
+    return out
+
+
+def xi_inclusions(shape, seed, count=(5, 10), amp=(0.05, 0.8), margin_frac=0.125):
+    """The field of ``inclusion_params``: sum of a exp(-|x-c|^2/(2 s^2)) and a 1[|x-c|_inf <= w/2]."""
+    xi = np.zeros(shape, dtype=np.float64)
+    for kind, c, a, size in inclusion_params(shape, seed, count, amp, margin_frac):
+        xi += a * (_gauss(shape, c, size) if kind == "gauss" else _box(shape, c, size))
     return xi
 
 
@@ -117,6 +124,49 @@ def xi_stress(shape, seed, count=20, contrast=(0.3, 0.9), cap=0.95):
 def noise(shape, seed):
     """Standard normal draws on the data grid (stream offset from the xi draws)."""
     return rng(seed + 7_000_003).standard_normal(shape)
+
+
+def workload_params(cfg: int, index: int):
+    """Recipe of workload 5's training/inference instances without evaluating
+    any field: dict(shape, inclusions, delta_rel, q, seed).  Grid extent
+    n ~ U{64, 96, 128} (cubic), q ~ U{0..3}, delta_rel ~ U[0.5%, 5%]."""
+    if cfg != 5:
+        raise ValueError("parameter-only recipes exist for workload 5")
+    seed = instance_seed(cfg, index)
+    g = rng(seed + 13)
+    m = int(g.choice((64, 96, 128)))
+    shape = (m, m, m)
+    delta_rel = float(g.uniform(0.005, 0.05))
+    q = int(g.integers(0, 4))
+    return dict(shape=shape, inclusions=inclusion_params(shape, seed), delta_rel=delta_rel, q=q, seed=seed)
+
+
+def noise_torch(shape, seed, device="cuda"):
+    """Standard normal draws on the data grid from torch's generator on the
+    device (for instances generated in bulk on the GPU)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) + 7_000_003)
+    return torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
+
+
+def xi_torch(shape, inclusions, device="cuda"):
+    """``xi_inclusions`` evaluated with torch on the device (same formula)."""
+    import torch
+    nz, ny, nx = shape
+    z = (torch.arange(nz, device=device, dtype=torch.float32) + 0.5).view(nz, 1, 1)
+    y = (torch.arange(ny, device=device, dtype=torch.float32) + 0.5).view(1, ny, 1)
+    x = (torch.arange(nx, device=device, dtype=torch.float32) + 0.5).view(1, 1, nx)
+    xi = torch.zeros(shape, device=device, dtype=torch.float32)
+    for kind, c, a, size in inclusions:
+        if kind == "gauss":
+            r2 = (x - float(c[0])) ** 2 + (y - float(c[1])) ** 2 + (z - float(c[2])) ** 2
+            xi += float(a) * torch.exp(-r2 / (2.0 * float(size) ** 2))
+        else:
+            h = float(size) / 2
+            m = ((x - float(c[0])).abs() <= h) & ((y - float(c[1])).abs() <= h) & ((z - float(c[2])).abs() <= h)
+            xi += float(a) * m.to(torch.float32)
+    return xi
 
 
 def workload_instance(cfg: int, index: int, n=None):
