@@ -111,6 +111,27 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GB_s": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def kernel_timing(ctx, torch, Fs, deltas, opts, lanes):
+    """Per-pass kernel durations from HIP events recorded at each pass
+    kernel's start and end, on one lane so that no two pass kernels overlap:
+    the bisection search to 1e-3 over the whole batch."""
+    ctx.set_lanes(1)
+    zs = [torch.empty_like(F) for F in Fs]
+    ctx.solve_batch(Fs[:2], deltas[:2], zs[:2], opts=opts)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for p in range(6):
+        ctx.get_timing(p)
+    t0 = time.perf_counter()
+    ctx.solve_batch(Fs, deltas, zs, opts=opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = {PASS_NAMES[p]: ctx.get_timing(p) for p in range(6)}
+    ctx.set_timing(False)
+    ctx.set_lanes(lanes)
+    return tm, el
+
+
 def run_mode(ctx, torch, Fs, deltas, V0, opts, steps, warmup, timing=False):
     zs = [torch.empty_like(F) for F in Fs]
     cs = [torch.empty_like(F) for F in Fs]
@@ -155,6 +176,8 @@ def main():
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="learned,bisection,bisection3")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the single-lane kernel-timing section (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 1 GiB device copy used to calibrate traffic counters")
     args = ap.parse_args()
@@ -189,14 +212,15 @@ def main():
     mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **window),
                  "bisection": fr3d.default_opts(**window),
                  "bisection3": fr3d.default_opts(tol=1e-3)}
-    results, timing = {}, None
+    results = {}
     head = modes[0]
-    for m in modes:
-        r, tm = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup, timing=(m == head))
-        results[m] = r
-        if tm is not None:
-            timing = tm
-        print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)
+    if not args.roofline_only:
+        for m in modes:
+            r, _ = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup)
+            results[m] = r
+            print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)
+    timing, kt_el = kernel_timing(ctx, torch, Fs, deltas, mode_opts["bisection3"], args.lanes)
+    print(f"[bench] kernel timing section: {kt_el * 1e3:.1f} ms", file=sys.stderr, flush=True)
     pb = pass_bytes(n)
     passes = {}
     for name, (ms, cnt) in timing.items():
@@ -208,7 +232,11 @@ def main():
     ach = passes[dom]["GB_s"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": pb[dom], "avg_launch_us": passes[dom]["avg_us"]}
+                "bytes_per_launch": pb[dom], "avg_launch_us": passes[dom]["avg_us"],
+                "measured": "HIP events at kernel start/end, one lane, bisection to 1e-3 over the batch"}
+    if args.roofline_only:
+        print(json.dumps({"roofline": roofline, "passes": passes}))
+        return
     H = results[head]
     out = {
         "metric": METRIC, "value": H["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -223,6 +251,9 @@ def main():
         "passes": passes,
         "copy": copy,
     }
+    per_solve = sum(pb[k] for k in ("fwd_x", "fwd_y", "fwd_z")) + 2 * n ** 3 * 4 * 2
+    per_eval = sum(pb[k] for k in ("inv_z", "inv_y", "inv_x"))
+    out["config"]["aggregate_GB_s"] = H["solves_per_s"] * (per_solve + H["mean_evals"] * per_eval) / 1e9
     if "learned" in results and "bisection" in results:
         out["config"]["speedup_learned_vs_bisection_same_window"] = (
             results["learned"]["solves_per_s"] / results["bisection"]["solves_per_s"])

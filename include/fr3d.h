@@ -107,10 +107,11 @@ fr3d_status fr3d_create(fr3d_ctx** out, int32_t device, void* hip_stream);
 fr3d_status fr3d_destroy(fr3d_ctx* ctx);
 /* Change the stream later work is enqueued on. */
 fr3d_status fr3d_set_stream(fr3d_ctx* ctx, void* hip_stream);
-/* Number of lanes (1..64) of the batch solver.  Lane 0 runs on the context's
- * stream; each further lane owns a stream (default priority) and its own data
- * spectrum, workspaces and search state (about 1.3 P^3 complex values each);
- * all lanes share the kernel spectrum. */
+/* Number of lanes (1..64) the batch solver uses.  Lane 0 runs on the
+ * context's stream; each further lane owns a stream (default priority) and its
+ * own data spectrum, workspaces and search state (about 1.3 P^3 complex values
+ * each); all lanes share the kernel spectrum.  Lanes once created stay
+ * allocated; a smaller count only leaves the extra ones idle. */
 fr3d_status fr3d_set_lanes(fr3d_ctx* ctx, int32_t lanes);
 
 /* Sample K at every wrapped cell offset of the P^3 box (zero in the slot no

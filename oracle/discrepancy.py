@@ -12,8 +12,8 @@ Reading used (the paper cites the rule but does not write it out):
 tau = 1, h_op = mu = 0 is Morozov's principle.  r is the residual on Y.
 
 Plain search (bisection in t = log10 alpha):
-  evaluate t = hi;  rho < 0  -> stop, alpha = 10^hi, NOROOT_HIGH
-  evaluate t = lo;  rho > 0  -> stop, alpha = 10^lo, NOROOT_LOW
+  evaluate t = hi;  |r/T - 1| <= tol -> stop, alpha = 10^hi;  rho < 0 -> stop, NOROOT_HIGH
+  evaluate t = lo;  |r/T - 1| <= tol -> stop, alpha = 10^lo;  rho > 0 -> stop, NOROOT_LOW
   up to max_steps times: m = (lo + hi)/2, evaluate;
       |r/T - 1| <= tol -> stop, alpha = 10^m
       rho(m) < 0 -> lo = m, else hi = m
@@ -77,9 +77,13 @@ def bisection(evaluate, delta, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, tau=1.0,
     Returns dict(alpha, t, flags, n_evals, trace)."""
     ev = _Counter(evaluate, delta, tau, h_op, mu)
     rho, ratio, r, zn = ev(hi)
+    if abs(ratio - 1.0) <= tol:
+        return dict(alpha=10.0 ** hi, t=hi, flags=0, n_evals=ev.n, trace=ev.trace)
     if rho < 0:
         return dict(alpha=10.0 ** hi, t=hi, flags=NOROOT_HIGH, n_evals=ev.n, trace=ev.trace)
     rho, ratio, r, zn = ev(lo)
+    if abs(ratio - 1.0) <= tol:
+        return dict(alpha=10.0 ** lo, t=lo, flags=0, n_evals=ev.n, trace=ev.trace)
     if rho > 0:
         return dict(alpha=10.0 ** lo, t=lo, flags=NOROOT_LOW, n_evals=ev.n, trace=ev.trace)
     t, flags = _bisect(ev, lo, hi, max_steps, tol, 0)

@@ -869,7 +869,7 @@ fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const
   fr3d_status s = check_opts(c, o, &d);
   if (s) return s;
   if ((s = ensure_lanes(c))) return s;
-  const int nl = (int)c->lanes.size();
+  const int nl = std::max(1, std::min((int)c->lanes.size(), c->nlanes_wanted));
   // order: the caller's stream before every lane, every lane before the caller's stream
   hipEvent_t fence;
   HIPCHK(c, hipEventCreateWithFlags(&fence, hipEventDisableTiming));

@@ -13,8 +13,9 @@
 // every later pass kernel of that search returns at once, so the host can
 // enqueue evaluations ahead without reading anything back.
 //
-// Plain search: evaluate hi; rho < 0 -> done NOROOT_HIGH.  Evaluate lo;
-// rho > 0 -> done NOROOT_LOW.  Then bisect: m = (a+b)/2, accept when
+// Plain search: every evaluated point with |r/T - 1| <= tol is accepted.
+// Evaluate hi; rho < 0 -> done NOROOT_HIGH.  Evaluate lo; rho > 0 -> done
+// NOROOT_LOW.  Then bisect: m = (a+b)/2, accept when
 // |r/T - 1| <= tol, else a = m if rho < 0 else b = m; after max_steps the
 // answer is b (MAXITER), re-evaluated there if b was not the last point.
 // Seeded search: evaluate the predicted t0; accept inside [acc_lo, acc_hi];
@@ -87,11 +88,13 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
       ctrl_finish(c, 0);
       return;
     case ST_HI:
+      if (fabs(ratio - 1.0) <= c->tol) { ctrl_finish(c, 0); return; }
       if (rho < 0) { ctrl_finish(c, F_NOROOT_HIGH); return; }
       c->state = ST_LO;
       ctrl_set_t(c, c->lo);
       return;
     case ST_LO:
+      if (fabs(ratio - 1.0) <= c->tol) { ctrl_finish(c, 0); return; }
       if (rho > 0) { ctrl_finish(c, F_NOROOT_LOW); return; }
       c->a = c->lo; c->b = c->hi; c->steps = 0;
       c->state = ST_BISECT;

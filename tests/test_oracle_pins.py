@@ -329,6 +329,18 @@ def test_bisection_flags():
     assert res["trace"][-1][0] == res["t"]
 
 
+def test_range_ends_accepted_within_tolerance():
+    # An evaluated range end inside the tolerance is an answer, not a failure.
+    ev, delta, Fn = _identity_problem(0.5)   # r(1) = ||F||/2 = delta exactly
+    res = discrepancy.bisection(ev, delta, tol=1e-9)
+    assert res["flags"] == 0 and res["n_evals"] == 1 and res["alpha"] == 1.0
+    ev, delta, Fn = _identity_problem(0.05)
+    a_lo = 1e-8
+    r_lo = a_lo / (1 + a_lo) * Fn
+    res = discrepancy.bisection(ev, r_lo * 1.0004, tol=1e-3)
+    assert res["flags"] == 0 and res["n_evals"] == 2 and res["alpha"] == 1e-8
+
+
 def test_seeded_search():
     ev, delta, Fn = _identity_problem(0.03)
     t_star = math.log10(delta / (Fn - delta))
