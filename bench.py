@@ -35,6 +35,20 @@ if ROOT not in sys.path:
 METRIC = "regularized 3D solves/sec at 256^3 to discrepancy delta, learned-alpha vs bisection"
 HBM_PEAK_GBS = 8000.0
 PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
+# HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the
+# plain-copy calibration factors 2.000 and 1.000), valid only for the pass
+# sources with this digest; see profiles/passes_256cube_traffic.md.
+MEASURED_TRAFFIC = {"digest": "99b03132ad85d1a7", "n": 128,
+                    "bytes": {"inv_z": 263.3e6, "inv_y": 101.5e6, "inv_x": 42.3e6, "fwd_z": 105.8e6,
+                              "fwd_y": 50.8e6, "fwd_x": 25.2e6}}
+
+
+def pass_source_digest():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1703_01216_amd", "csrc")
+    src = b"".join(open(os.path.join(d, f), "rb").read()
+                   for f in ("fft_core.hpp", "passes.hpp", "passes_impl.hpp", "control.hpp"))
+    return hashlib.sha256(src).hexdigest()[:16]
 
 
 def pass_bytes(n, esz=4):
@@ -230,8 +244,11 @@ def main():
                             "total_ms": ms}
     dom = max(passes, key=lambda k: passes[k]["total_ms"])
     ach = passes[dom]["GB_s"]
+    traffic = None
+    if pass_source_digest() == MEASURED_TRAFFIC["digest"] and n == MEASURED_TRAFFIC["n"]:
+        traffic = MEASURED_TRAFFIC["bytes"].get(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_launch": pb[dom], "avg_launch_us": passes[dom]["avg_us"],
                 "measured": "HIP events at kernel start/end, one lane, bisection to 1e-3 over the batch"}
     if args.roofline_only:
