@@ -10,11 +10,11 @@ stays resident in HBM.  One step solves the whole batch with the lane
 scheduler: per instance the forward transform of F, the alpha search and the
 recovery of c.
 
-Three searches run on the same batch:
-  learned     -- the trained predictor's alpha first; accept r/delta in [0.9, 1.1],
-                 else decade walk + bisection to the same window (the headline value)
-  bisection   -- plain bisection over log10 alpha in [-8, 0] to the same window
-  bisection3  -- plain bisection to |r/delta - 1| <= 1e-3
+Four searches run on the same batch:
+  learned     -- the trained predictor's alpha first, then walk + regula falsi,
+                 every point accepted when |r/delta - 1| <= 1e-3 (the headline value)
+  bisection   -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
+  learned_w, bisection_w -- the same two with the wider acceptance |r/delta - 1| <= 0.1
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--lanes L] [--no-cpu]
 
@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--modes", default="learned,bisection,bisection3")
+    ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-lane kernel-timing section (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -222,10 +222,12 @@ def main():
             ctx.predictor_load(args.predictor)
     Fs, deltas, V0 = make_instances(ctx, torch, n, args.batch)
     print(f"[bench] {len(Fs)} instances of {n}^3 ready", file=sys.stderr, flush=True)
-    window = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
-    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **window),
-                 "bisection": fr3d.default_opts(**window),
-                 "bisection3": fr3d.default_opts(tol=1e-3)}
+    tight = dict(tol=1e-3, accept_lo=1 - 1e-3, accept_hi=1 + 1e-3)
+    wide = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
+    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **tight),
+                 "bisection": fr3d.default_opts(**tight),
+                 "learned_w": fr3d.default_opts(use_predictor=1, **wide),
+                 "bisection_w": fr3d.default_opts(**wide)}
     results = {}
     head = modes[0]
     if not args.roofline_only:
@@ -233,7 +235,7 @@ def main():
             r, _ = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup)
             results[m] = r
             print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)
-    timing, kt_el = kernel_timing(ctx, torch, Fs, deltas, mode_opts["bisection3"], args.lanes)
+    timing, kt_el = kernel_timing(ctx, torch, Fs, deltas, mode_opts["bisection"], args.lanes)
     print(f"[bench] kernel timing section: {kt_el * 1e3:.1f} ms", file=sys.stderr, flush=True)
     pb = pass_bytes(n)
     passes = {}
@@ -260,7 +262,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": H["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n}^3 grids padded to {2 * n}^3, batch of {len(Fs)} instances (5-10 inclusions, "
-                               f"delta 1/3/5%), forward transform + {head} alpha search to the discrepancy "
+                               f"delta 1/3/5%), forward transform + {head} alpha search to |r/delta - 1| <= 1e-3 "
                                f"+ recovery of c per solve, {args.lanes} lanes",
                    "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
                    "modes": results},
@@ -272,8 +274,11 @@ def main():
     per_eval = sum(pb[k] for k in ("inv_z", "inv_y", "inv_x"))
     out["config"]["aggregate_GB_s"] = H["solves_per_s"] * (per_solve + H["mean_evals"] * per_eval) / 1e9
     if "learned" in results and "bisection" in results:
-        out["config"]["speedup_learned_vs_bisection_same_window"] = (
+        out["config"]["speedup_learned_vs_bisection_tol_1e-3"] = (
             results["learned"]["solves_per_s"] / results["bisection"]["solves_per_s"])
+    if "learned_w" in results and "bisection_w" in results:
+        out["config"]["speedup_learned_vs_bisection_tol_0.1"] = (
+            results["learned_w"]["solves_per_s"] / results["bisection_w"]["solves_per_s"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, H["mean_evals"])
     print(json.dumps(out))

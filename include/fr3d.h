@@ -83,6 +83,7 @@ typedef struct {
   double accept_lo, accept_hi;           /* window for predicted points, default 0.9, 1.1 */
   double tau, h_op, mu;                  /* generalised principle, default 1, 0, 0 */
   int32_t use_predictor;                 /* 1: seed the search with the alpha predictor */
+  double seed_walk;                      /* first walk step from the seed in decades, default 0.25 */
 } fr3d_dp_opts;
 
 typedef struct {
@@ -134,10 +135,12 @@ fr3d_status fr3d_set_data(fr3d_ctx* ctx, const void* F_dev, double delta);
 fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_report* rep);
 
 /* Choose alpha by the discrepancy principle and write zeta at that alpha.
- * opts NULL = defaults.  Search rule: evaluate the range ends (hi first), then
- * bisect in log10 alpha; with use_predictor, start from the predicted alpha,
- * walk one decade at a time to a sign change, then bisect.  Fills *rep
- * (synchronises). */
+ * opts NULL = defaults.  Plain rule: evaluate the range ends (hi first), then
+ * bisect in log10 alpha; any point with |r/T - 1| <= tol is accepted.  With
+ * use_predictor: start from the predicted alpha (accepted inside [accept_lo,
+ * accept_hi] or within tol), walk toward the sign change with doubling steps
+ * from seed_walk decades, then Illinois regula falsi on r/T - 1 inside the
+ * bracket.  Fills *rep (synchronises). */
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
                                    fr3d_report* rep);
 

@@ -19,13 +19,16 @@ Plain search (bisection in t = log10 alpha):
       rho(m) < 0 -> lo = m, else hi = m
   otherwise alpha = 10^hi, MAXITER (re-evaluated there if hi was not the last point).
 
-Seeded search (a predicted t0 from the alpha predictor):
-  evaluate t0 (clipped to [lo, hi]); accept if acc_lo <= r/T <= acc_hi;
-  otherwise step one decade at a time away from t0 in the direction rho
-  points to (up if rho < 0), accepting any point inside the window, until
-  rho changes sign (bracket found) or the range end is reached (NOROOT_*);
-  then the plain bisection inside the bracket, whose ends are already known.
-  PRED_FALLBACK is set whenever the first point is not accepted.
+Seeded search (a predicted t0 from the alpha predictor; not in the paper):
+  a point is accepted when acc_lo <= r/T <= acc_hi or |r/T - 1| <= tol.
+  Evaluate t0 (clipped to [lo, hi]).  Otherwise walk away from it in the
+  direction rho points to (up if rho < 0) with steps walk, 2 walk, 4 walk, ...
+  (clipped to the range; NOROOT_* when a range end is reached without a sign
+  change) until rho changes sign, then regula falsi on g = r/T - 1 inside the
+  bracket with the Illinois modification (the function value kept at an end
+  that survives two steps in a row is halved), at most max_steps points;
+  otherwise alpha = 10^b, MAXITER.  PRED_FALLBACK is set whenever the first
+  point is not accepted.
 """
 from __future__ import annotations
 
@@ -91,39 +94,56 @@ def bisection(evaluate, delta, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, tau=1.0,
 
 
 def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=0.9, acc_hi=1.1,
-           tau=1.0, h_op=0.0, mu=0.0):
+           tau=1.0, h_op=0.0, mu=0.0, walk=0.25):
     """Seeded search from a predicted log10 alpha ``t0``."""
     ev = _Counter(evaluate, delta, tau, h_op, mu)
+
+    def ok(ratio):
+        return acc_lo <= ratio <= acc_hi or abs(ratio - 1.0) <= tol
+
+    def out(t, flags):
+        return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace)
+
     t = min(max(float(t0), lo), hi)
     rho, ratio, r, zn = ev(t)
-    if acc_lo <= ratio <= acc_hi:
-        return dict(alpha=10.0 ** t, t=t, flags=0, n_evals=ev.n, trace=ev.trace)
+    if ok(ratio):
+        return out(t, 0)
     flags = PRED_FALLBACK
-    if rho < 0:          # residual below target: alpha too small, move up
-        a = t
-        while True:
-            if a >= hi:
-                return dict(alpha=10.0 ** hi, t=hi, flags=flags | NOROOT_HIGH, n_evals=ev.n, trace=ev.trace)
-            tn = min(a + 1.0, hi)
-            rho, ratio, r, zn = ev(tn)
-            if acc_lo <= ratio <= acc_hi:
-                return dict(alpha=10.0 ** tn, t=tn, flags=flags, n_evals=ev.n, trace=ev.trace)
-            if rho >= 0:
-                b = tn
-                break
-            a = tn
-    else:                # residual above target: alpha too large, move down
-        b = t
-        while True:
-            if b <= lo:
-                return dict(alpha=10.0 ** lo, t=lo, flags=flags | NOROOT_LOW, n_evals=ev.n, trace=ev.trace)
-            tn = max(b - 1.0, lo)
-            rho, ratio, r, zn = ev(tn)
-            if acc_lo <= ratio <= acc_hi:
-                return dict(alpha=10.0 ** tn, t=tn, flags=flags, n_evals=ev.n, trace=ev.trace)
-            if rho <= 0:
-                a = tn
-                break
-            b = tn
-    t, flags = _bisect(ev, a, b, max_steps, tol, flags)
-    return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace)
+    step = walk
+    while True:                                   # walk to a sign change
+        up = rho < 0                              # residual below target: alpha too small
+        if up and t >= hi:
+            return out(hi, flags | NOROOT_HIGH)
+        if not up and t <= lo:
+            return out(lo, flags | NOROOT_LOW)
+        tn = min(t + step, hi) if up else max(t - step, lo)
+        rn, ration, _, _ = ev(tn)
+        if ok(ration):
+            return out(tn, flags)
+        if (up and rn >= 0) or (not up and rn <= 0):
+            if up:
+                a, ga, b, gb = t, ratio - 1.0, tn, ration - 1.0
+            else:
+                a, ga, b, gb = tn, ration - 1.0, t, ratio - 1.0
+            break
+        t, rho, ratio = tn, rn, ration
+        step *= 2.0
+    side = 0
+    for _ in range(max_steps):                    # Illinois regula falsi, g(a) < 0 < g(b)
+        m = b - gb * (b - a) / (gb - ga)
+        rm, ratiom, _, _ = ev(m)
+        if ok(ratiom):
+            return out(m, flags)
+        if rm < 0:
+            a, ga = m, ratiom - 1.0
+            if side == -1:
+                gb *= 0.5
+            side = -1
+        else:
+            b, gb = m, ratiom - 1.0
+            if side == 1:
+                ga *= 0.5
+            side = 1
+    if ev.last_t != b:
+        ev(b)
+    return out(b, flags | MAXITER)

@@ -487,6 +487,7 @@ Ctrl ctrl_base(fr3d_ctx* c, Lane& L) {
   v.acc_hi = 1.1;
   v.lo = -8.0;
   v.hi = 0.0;
+  v.walk = 0.25;
   v.max_steps = 40;
   v.active = 1;
   return v;
@@ -497,7 +498,8 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (o) *d = *o;
   if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
-      !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi))
+      !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
+      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->use_predictor && !c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
   return FR3D_OK;
@@ -516,6 +518,7 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_e
   v.tau = d.tau;
   v.h_op = d.h_op;
   v.mu = d.mu;
+  v.walk = d.seed_walk;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -523,8 +526,10 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_e
   LCHK(c, hipGetLastError());
   if (d.use_predictor) {
     LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream));
-    // seed + one walk step per decade + bisection + final re-evaluation
-    *max_evals = 1 + (int)std::ceil(d.log10_alpha_hi - d.log10_alpha_lo) + d.max_steps + 1;
+    // seed + doubling walk across the range + regula falsi + final re-evaluation
+    int walk = 0;
+    for (double w = d.seed_walk, span = 0; span < d.log10_alpha_hi - d.log10_alpha_lo; w *= 2) { span += w; ++walk; }
+    *max_evals = 1 + walk + d.max_steps + 1;
   } else {
     *max_evals = 2 + d.max_steps + 1;
   }
@@ -673,6 +678,7 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->h_op = 0.0;
   o->mu = 0.0;
   o->use_predictor = 0;
+  o->seed_walk = 0.25;
 }
 
 const char* fr3d_status_string(fr3d_status s) {

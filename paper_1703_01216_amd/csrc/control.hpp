@@ -18,9 +18,11 @@
 // NOROOT_LOW.  Then bisect: m = (a+b)/2, accept when
 // |r/T - 1| <= tol, else a = m if rho < 0 else b = m; after max_steps the
 // answer is b (MAXITER), re-evaluated there if b was not the last point.
-// Seeded search: evaluate the predicted t0; accept inside [acc_lo, acc_hi];
-// else walk one decade at a time toward the sign change (accepting any point
-// inside the window), then bisect inside the bracket.
+// Seeded search: a point is accepted when acc_lo <= r/T <= acc_hi or
+// |r/T - 1| <= tol.  Evaluate the predicted t0; otherwise walk toward the
+// sign change with steps walk, 2 walk, 4 walk, ... (NOROOT at a range end),
+// then regula falsi on g = r/T - 1 inside the bracket with the Illinois
+// modification (the value kept at an end that survives two steps is halved).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,8 +38,8 @@ enum : int32_t {
   ST_BISECT = 4,  // evaluating a bisection midpoint
   ST_FINAL = 5,   // re-evaluating b after the step limit
   ST_SEED = 6,    // evaluating the predicted point
-  ST_UP = 7,      // decade walk upward
-  ST_DOWN = 8,    // decade walk downward
+  ST_WALK = 7,    // walking from the seed toward the sign change
+  ST_FALSI = 8,   // regula falsi inside the bracket
   ST_DONE = 9,
 };
 
@@ -45,7 +47,7 @@ enum : int32_t { F_NOROOT_HIGH = 1, F_NOROOT_LOW = 2, F_MAXITER = 4, F_NAN = 8, 
 
 struct Ctrl {
   // settings
-  double a_scale, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi;
+  double a_scale, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi, walk;
   int32_t max_steps;
   // state
   int32_t state, active, n_evals, flags, steps;
@@ -54,8 +56,9 @@ struct Ctrl {
   double alpha_abs;  // 10^t * a_scale, read by the filter
   double r2, z2;     // norms of the last evaluation
   double target;     // T of the last evaluation
-  uint32_t ticket;   // last-workgroup counter of the final pass
-  uint32_t pad_;
+  double ga, gb;     // r/T - 1 at the bracket ends (seeded search)
+  double prev_t, prev_g, wstep;
+  int32_t side, up;
 };
 
 __device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {
@@ -116,42 +119,56 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
       ctrl_finish(c, F_MAXITER);
       return;
     case ST_SEED:
-      if (in_window) { ctrl_finish(c, 0); return; }
-      c->flags |= F_PRED_FALLBACK;
-      if (rho < 0) {
-        c->a = c->t;
-        if (c->a >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
-        c->state = ST_UP;
-        ctrl_set_t(c, fmin(c->a + 1.0, c->hi));
+    case ST_WALK: {
+      const double g = ratio - 1.0;
+      if (in_window || fabs(g) <= c->tol) { ctrl_finish(c, 0); return; }
+      if (c->state == ST_SEED) {
+        c->flags |= F_PRED_FALLBACK;
+        c->wstep = c->walk;
       } else {
-        c->b = c->t;
-        if (c->b <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
-        c->state = ST_DOWN;
-        ctrl_set_t(c, fmax(c->b - 1.0, c->lo));
+        const bool changed = c->up ? rho >= 0 : rho <= 0;
+        if (changed) {
+          if (c->up) { c->a = c->prev_t; c->ga = c->prev_g; c->b = c->t; c->gb = g; }
+          else { c->a = c->t; c->ga = g; c->b = c->prev_t; c->gb = c->prev_g; }
+          c->side = 0;
+          c->steps = 0;
+          c->state = ST_FALSI;
+          ctrl_set_t(c, c->b - c->gb * (c->b - c->a) / (c->gb - c->ga));
+          return;
+        }
+        c->wstep *= 2.0;
       }
+      c->up = rho < 0;
+      if (c->up && c->t >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
+      if (!c->up && c->t <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
+      c->prev_t = c->t;
+      c->prev_g = g;
+      c->state = ST_WALK;
+      ctrl_set_t(c, c->up ? fmin(c->t + c->wstep, c->hi) : fmax(c->t - c->wstep, c->lo));
       return;
-    case ST_UP:
-      if (in_window) { ctrl_finish(c, 0); return; }
-      if (rho >= 0) {
-        c->b = c->t; c->steps = 0; c->state = ST_BISECT;
-        ctrl_set_t(c, 0.5 * (c->a + c->b));
+    }
+    case ST_FALSI: {
+      const double g = ratio - 1.0;
+      if (in_window || fabs(g) <= c->tol) { ctrl_finish(c, 0); return; }
+      if (rho < 0) {
+        c->a = c->t; c->ga = g;
+        if (c->side == -1) c->gb *= 0.5;
+        c->side = -1;
+      } else {
+        c->b = c->t; c->gb = g;
+        if (c->side == 1) c->ga *= 0.5;
+        c->side = 1;
+      }
+      c->steps += 1;
+      if (c->steps >= c->max_steps) {
+        if (c->t == c->b) { ctrl_finish(c, F_MAXITER); return; }
+        c->state = ST_FINAL;
+        ctrl_set_t(c, c->b);
         return;
       }
-      c->a = c->t;
-      if (c->a >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
-      ctrl_set_t(c, fmin(c->a + 1.0, c->hi));
+      ctrl_set_t(c, c->b - c->gb * (c->b - c->a) / (c->gb - c->ga));
       return;
-    case ST_DOWN:
-      if (in_window) { ctrl_finish(c, 0); return; }
-      if (rho <= 0) {
-        c->a = c->t; c->steps = 0; c->state = ST_BISECT;
-        ctrl_set_t(c, 0.5 * (c->a + c->b));
-        return;
-      }
-      c->b = c->t;
-      if (c->b <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
-      ctrl_set_t(c, fmax(c->b - 1.0, c->lo));
-      return;
+    }
     default:
       ctrl_finish(c, 0);
       return;

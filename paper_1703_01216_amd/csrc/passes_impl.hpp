@@ -237,6 +237,24 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 //   MODE 1: u^ = k^ f^,  r^ = 0                                  (forward operator)
 // transforms u^ and then r^ along z in the same LDS tile and writes z < nz
 // as (u, r) pairs.
+//
+// Octant reuse: rows kz and P-kz need the same octant entry (conjugated), so
+// each thread loads f^ for such a pair of rows and the octant entry once;
+// tiles t and ntile-1-t of a plane need mirrored octant columns, so they are
+// dispatched as consecutive workgroups of the same XCD (workgroups go to
+// XCDs round robin) and share that XCD's L2.
+__device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& plane, int& tile) {
+  const int npair = (ntile + 1) / 2;
+  const int x = w & 7, s = w >> 3;
+  const int h = s & 1;
+  const int pidx = (s >> 1) * 8 + x;
+  plane = pidx / npair;
+  const int t = pidx % npair;
+  if (plane >= nplane) return false;
+  tile = h ? ntile - 1 - t : t;
+  return !(h && tile == t);
+}
+
 template <typename T, int P, int MODE>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
@@ -247,51 +265,92 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   constexpr int TOTO = C * NOUT;
   using PE = Per<TOT>;
   using PO = Per<TOTO>;
+  constexpr bool PAIRED = C <= NT && NT % C == 0 && (P / 2) % (NT / C) == 0;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   if (a.ctrl && !a.ctrl->active) return;
+  const int py = a.py;
+  const int ntile = (py + C - 1) / C;
+  int kx, tile;
+  if (!xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)) return;
   const double aa = MODE == 0 ? a.ctrl->alpha_abs : 0.0;
   const int tid = threadIdx.x;
-  const int kx = blockIdx.y;
-  const int ky0 = blockIdx.x * C;
-  const int py = a.py;
+  const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
   const c2<T>* src = S + (size_t)kx * P * py;
   const double2* oc = a.oct + (size_t)kx * oz * oy;
-  c2<T> f[PE::n];
-  double2 k[PE::n];
-#pragma unroll
-  for (int i = 0; i < PE::n; ++i) {
-    const int e = tid + i * NT;
-    const int kz = e / C, ky = ky0 + e % C;
-    const bool ok = PE::ok(e) && ky < py;
-    const int mz = kz <= P / 2 ? kz : P - kz;
-    const int my = ky <= py / 2 ? ky : py - ky;
-    f[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
-    k[i] = ok ? oc[(size_t)mz * oy + my] : make_double2(0.0, 0.0);
-  }
-  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
-  c2<T> r[PE::n];
-#pragma unroll
-  for (int i = 0; i < PE::n; ++i) {
-    const int e = tid + i * NT;
-    const int kz = e / C;
-    double2 kk = k[i];
-    if (kz > P / 2) kk.y = -kk.y;
-    const double fx = (double)f[i].x, fy = (double)f[i].y;
-    c2<T> u;
+  // filter of one point: u and r from f^ and the (possibly conjugated) k^
+  auto filt = [&](c2<T> f, double2 kk, c2<T>& u, c2<T>& r) {
+    const double fx = (double)f.x, fy = (double)f.y;
     if constexpr (MODE == 0) {
       const double s = kk.x * kk.x + kk.y * kk.y;
       const double d = 1.0 / (s + aa);
       const double cx = kk.x * d, cy = -kk.y * d;  // conj(k^) / (s + a)
       u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
       const double cr = -aa * d;
-      r[i] = mk<T>((T)(fx * cr), (T)(fy * cr));
+      r = mk<T>((T)(fx * cr), (T)(fy * cr));
     } else {
       u = mk<T>((T)(fx * kk.x - fy * kk.y), (T)(fx * kk.y + fy * kk.x));
-      r[i] = mk<T>(0, 0);
+      r = mk<T>(0, 0);
     }
-    if (PE::ok(e)) lds[e] = u;
+  };
+  c2<T> r[PE::n];
+  if constexpr (PAIRED) {
+    constexpr int TPC = NT / C;          // threads per column
+    constexpr int UPT = (P / 2) / TPC;   // row pairs per thread
+    const int col = tid % C, j = tid / C;
+    const int ky = ky0 + col;
+    const bool okc = ky < py;
+    const int my = ky <= py / 2 ? ky : py - ky;
+    c2<T> f0[UPT], f1[UPT];
+    double2 k[UPT];
+    double2 kmid = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int p = j + TPC * i;  // rows p and P-p (p = 0: rows 0 and P/2)
+      const int r1 = p == 0 ? P / 2 : P - p;
+      f0[i] = okc ? src[(size_t)p * py + ky] : mk<T>(0, 0);
+      f1[i] = okc ? src[(size_t)r1 * py + ky] : mk<T>(0, 0);
+      k[i] = okc ? oc[(size_t)p * oy + my] : make_double2(0.0, 0.0);
+    }
+    if (j == 0 && okc) kmid = oc[(size_t)(P / 2) * oy + my];
+    for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int p = j + TPC * i;
+      const int r1 = p == 0 ? P / 2 : P - p;
+      c2<T> u0, u1;
+      filt(f0[i], k[i], u0, r[2 * i]);
+      double2 k1 = k[i];
+      if (p == 0) k1 = kmid;
+      else k1.y = -k1.y;  // row P-p > P/2: conj
+      filt(f1[i], k1, u1, r[2 * i + 1]);
+      lds[p * LD + col] = u0;
+      lds[r1 * LD + col] = u1;
+    }
+  } else {
+    c2<T> f[PE::n];
+    double2 k[PE::n];
+#pragma unroll
+    for (int i = 0; i < PE::n; ++i) {
+      const int e = tid + i * NT;
+      const int kz = e / C, ky = ky0 + e % C;
+      const bool ok = PE::ok(e) && ky < py;
+      const int mz = kz <= P / 2 ? kz : P - kz;
+      const int my = ky <= py / 2 ? ky : py - ky;
+      f[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
+      k[i] = ok ? oc[(size_t)mz * oy + my] : make_double2(0.0, 0.0);
+    }
+    for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+#pragma unroll
+    for (int i = 0; i < PE::n; ++i) {
+      const int e = tid + i * NT;
+      double2 kk = k[i];
+      if (e / C > P / 2) kk.y = -kk.y;
+      c2<T> u;
+      filt(f[i], kk, u, r[i]);
+      if (PE::ok(e)) lds[e] = u;
+    }
   }
   __syncthreads();
   tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
@@ -302,10 +361,23 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     uo[i] = PO::ok(e) ? lds[e] : mk<T>(0, 0);
   }
   __syncthreads();
+  if constexpr (PAIRED) {
+    constexpr int TPC = NT / C;
+    constexpr int UPT = (P / 2) / TPC;
+    const int col = tid % C, j = tid / C;
 #pragma unroll
-  for (int i = 0; i < PE::n; ++i) {
-    const int e = tid + i * NT;
-    if (PE::ok(e)) lds[e] = r[i];
+    for (int i = 0; i < UPT; ++i) {
+      const int p = j + TPC * i;
+      const int r1 = p == 0 ? P / 2 : P - p;
+      lds[p * LD + col] = r[2 * i];
+      lds[r1 * LD + col] = r[2 * i + 1];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PE::n; ++i) {
+      const int e = tid + i * NT;
+      if (PE::ok(e)) lds[e] = r[i];
+    }
   }
   __syncthreads();
   if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
@@ -560,7 +632,9 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
   switch (P) {
 #define X(p)                                                                                               \
   case p: {                                                                                                \
-    dim3 g(cdiv(a.py, Tile<T, p>::C), a.kx_n);                                                             \
+    const long long ntile = cdiv(a.py, Tile<T, p>::C);                                                     \
+    const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                        \
+    dim3 g(16 * cdiv(npairs, 8));                                                                          \
     return mode == 0 ? go(k_iz<T, p, 0>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1>, g, L, S, W1, a, tw);      \
   }
     FR3D_SIZES(X)

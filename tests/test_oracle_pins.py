@@ -346,14 +346,31 @@ def test_seeded_search():
     t_star = math.log10(delta / (Fn - delta))
     res = discrepancy.seeded(ev, delta, t_star + 0.01)
     assert res["flags"] == 0 and res["n_evals"] == 1
-    for off in (-3.3, 2.7):
-        res = discrepancy.seeded(ev, delta, t_star + off, tol=1e-6)
+    for off in (-3.3, 2.7, 0.4, -0.2):
+        res = discrepancy.seeded(ev, delta, t_star + off, tol=1e-6, acc_lo=1.0, acc_hi=1.0)
         assert res["flags"] == discrepancy.PRED_FALLBACK
         assert res["alpha"] == pytest.approx(10 ** t_star, rel=1e-5)
-        assert res["n_evals"] < 45
-    # bracket walk uses one-decade steps from the seed
-    res = discrepancy.seeded(ev, delta, t_star - 3.3, tol=1e-6)
-    assert [round(t - res["trace"][0][0], 9) for t, *_ in res["trace"][:4]] == [0.0, 1.0, 2.0, 3.0]
+        # regula falsi converges in far fewer points than bisection would need
+        assert res["n_evals"] < 20
+    # the walk doubles its step from the seed: 0.25, 0.5, 1, 2 decades
+    res = discrepancy.seeded(ev, delta, t_star - 3.3, tol=1e-6, acc_lo=1.0, acc_hi=1.0)
+    ts = [t for t, *_ in res["trace"][:5]]
+    assert [round(t - ts[0], 9) for t in ts] == [0.0, 0.25, 0.75, 1.75, 3.75]
+    # no sign change up to the range end
+    ev2, delta2, Fn2 = _identity_problem(0.6)
+    res = discrepancy.seeded(ev2, delta2, -3.0)
+    assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.NOROOT_HIGH and res["alpha"] == 1.0
+
+
+def test_seeded_matches_bisection_answer_quality():
+    # same acceptance band: both searches end inside it
+    ev, delta, Fn = _identity_problem(0.02)
+    for t0 in (-6.0, -1.0, -2.2):
+        r1 = discrepancy.seeded(ev, delta, t0, tol=1e-3, acc_lo=0.999, acc_hi=1.001)
+        r2 = discrepancy.bisection(ev, delta, tol=1e-3)
+        for res in (r1, r2):
+            rr, _ = ev(res["alpha"])
+            assert abs(rr / delta - 1) <= 1e-3
 
 
 # ---------------------------------------------------------------- recovery and V0 (Sec. 2, Sec. 6)
