@@ -212,6 +212,7 @@ def main():
     n = args.n
     ctx = fr3d.Context(0)
     ctx.load_kernel(n, n, n, precision=32)
+    tuning = ctx.apply_tuning()
     ctx.set_lanes(args.lanes)
     modes = args.modes.split(",")
     if "learned" in modes:
@@ -265,6 +266,7 @@ def main():
                                f"delta 1/3/5%), forward transform + {head} alpha search to |r/delta - 1| <= 1e-3 "
                                f"+ recovery of c per solve, {args.lanes} lanes",
                    "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
+                   "tile_shifts": tuning,
                    "modes": results},
         "roofline": roofline,
         "passes": passes,

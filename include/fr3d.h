@@ -216,6 +216,11 @@ fr3d_status fr3d_predictor_train_step(fr3d_ctx* ctx, const float* X_dev, const f
 fr3d_status fr3d_predictor_save(fr3d_ctx* ctx, const char* path);
 fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
 
+/* Tile size of a pass (ids as for timing): shift 0 = a 32 KiB LDS tile of
+ * pencils, 1 = half, 2 = quarter (row passes 0, 1, 4 only); lengths below 64
+ * always use shift 0.  Results do not depend on it; the autotuner picks it. */
+fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
+
 /* Per-pass timing with HIP events on the context's stream (for measurement).
  * Pass ids: 0..2 forward x,y,z; 3..5 inverse z,y,x. */
 fr3d_status fr3d_set_timing(fr3d_ctx* ctx, int32_t enable);

@@ -175,6 +175,7 @@ struct fr3d_ctx {
   std::map<int, void*> tw32, tw64;
   std::vector<Lane> lanes;  // lanes[0] runs on the caller's stream
   int nlanes_wanted = 1;
+  int tile_sh[6] = {0, 0, 0, 0, 0, 0};  // tile-size variant per pass
   // predictor
   bool has_pred = false;
   float* pred_p = nullptr;     // parameters, FP32 master copy
@@ -338,7 +339,7 @@ fr3d_status get_twiddles(fr3d_ctx* c, int P, bool dbl, void** out) {
 // With timing on, each pass kernel is launched with an event pair recorded at
 // its own start and end.
 Launch mkL(fr3d_ctx* c, Lane& L, int pass) {
-  Launch r{L.stream, nullptr, nullptr};
+  Launch r{L.stream, nullptr, nullptr, c->tile_sh[pass]};
   if (!c->timing) return r;
   std::pair<hipEvent_t, hipEvent_t> p;
   if (!c->ev_pool.empty()) { p = c->ev_pool.back(); c->ev_pool.pop_back(); }
@@ -796,7 +797,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
     return st;
   }
   FwdArgs a = fwd_args(c, L0, true);
-  const Launch Lk{L0.stream, nullptr, nullptr};
+  const Launch Lk{L0.stream, nullptr, nullptr, 0};
   hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, Lk);
   if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, Lk);
   if (le == hipSuccess) le = launch_fz<double>(c->pz, 1, Bk, c->oct, a, (const double2*)twz, Lk);
@@ -1065,6 +1066,15 @@ fr3d_status fr3d_get_smax(fr3d_ctx* c, double* smax) {
   if (!c || !smax) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
   *smax = c->smax;
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_set_tile(fr3d_ctx* c, int32_t pass, int32_t shift) {
+  if (!c) return FR3D_E_INVALID;
+  if (pass < 0 || pass > 5) return fail(c, FR3D_E_INVALID, "pass must be in [0, 5]");
+  const int maxsh = (pass == 0 || pass == 1 || pass == 4) ? 2 : 1;
+  if (shift < 0 || shift > maxsh) return fail(c, FR3D_E_INVALID, "tile shift of pass %d must be in [0, %d]", pass, maxsh);
+  c->tile_sh[pass] = shift;
   return FR3D_OK;
 }
 

@@ -23,11 +23,15 @@ namespace fr3d {
 
 constexpr int NT = 256;  // threads per workgroup of every pass
 
-// Pencils per workgroup: a 32 KiB tile (FP32: 4096 elements, FP64: 2048).
+// Pencils per workgroup: a 32 KiB tile (FP32: 4096 elements, FP64: 2048),
+// halved SH times (the tile-size variants the autotuner chooses from).
 template <typename T, int P> struct Tile {
   static constexpr int pow2ceil(int v) { int p = 1; while (p < v) p <<= 1; return p; }
   static constexpr int TE = sizeof(T) == 4 ? 4096 : 2048;
   static constexpr int C = TE / pow2ceil(P) > 0 ? TE / pow2ceil(P) : 1;
+};
+template <typename T, int P, int SH> struct TileC {
+  static constexpr int C = (Tile<T, P>::C >> SH) > 0 ? (Tile<T, P>::C >> SH) : 1;
 };
 
 // Spectral-energy bin of a point (exact integer rule; see the feature oracle):
@@ -82,6 +86,7 @@ struct InvArgs {
 struct Launch {
   hipStream_t s;
   hipEvent_t e0, e1;
+  int sh;  // tile-size variant: 0 = 32 KiB tile, 1 = half, 2 = quarter (row passes)
 };
 
 // Each returns hipSuccess or the launch error; P is the transform length of

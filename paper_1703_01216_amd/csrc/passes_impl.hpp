@@ -35,10 +35,10 @@ __device__ __forceinline__ bool wrap_offset(int a, int n, int p, int& off) {
   return false;
 }
 
-template <typename T, int P, bool GEN>
+template <typename T, int P, bool GEN, int SH>
 __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __restrict__ A, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C;  // complex pencils per tile = C, real rows = 2C
+  constexpr int C = TileC<T, P, SH>::C;  // complex pencils per tile = C, real rows = 2C
   constexpr int LD = P + 1;
   constexpr int N = P / 2;
   __shared__ c2<T> lds[C * LD];
@@ -107,10 +107,10 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
 
 // ============================================================ forward y pass
 // Complex transform along y of every row (kx, z); rows are contiguous.
-template <typename T, int P, bool PRUNE>
+template <typename T, int P, bool PRUNE, int SH>
 __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* __restrict__ B, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C;
+  constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = P + 1;
   constexpr int NIN = PRUNE ? P / 2 : P;
   constexpr int TOT = C * NIN;
@@ -151,10 +151,10 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
 // MODE 0 (data): n inputs, P outputs, fused radial-energy epilogue writing
 // per-workgroup bin partials.  MODE 1 (kernel spectrum): P inputs, only
 // kz <= P/2 and ky <= Py/2 stored (the octant).
-template <typename T, int P, int MODE>
+template <typename T, int P, int MODE, int SH>
 __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* __restrict__ S, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C;
+  constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = C;
   constexpr int NIN = MODE == 0 ? P / 2 : P;
   constexpr int NOUT = MODE == 0 ? P : P / 2 + 1;
@@ -255,10 +255,10 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
   return !(h && tile == t);
 }
 
-template <typename T, int P, int MODE>
+template <typename T, int P, int MODE, int SH>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C;
+  constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = C;
   constexpr int NOUT = P / 2;
   constexpr int TOT = C * P;
@@ -396,10 +396,10 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
 
 // ============================================================ inverse y pass
 // Rows (kx, z) of (u, r) pairs: both transformed along y, y < ny written.
-template <typename T, int P>
+template <typename T, int P, int SH>
 __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* __restrict__ W2, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C / 2 > 0 ? Tile<T, P>::C / 2 : 1;  // rows per tile
+  constexpr int C = TileC<T, P, SH + 1>::C;  // rows per tile (two pencils each)
   constexpr int NC = 2 * C;
   constexpr int LD = P + 1;
   constexpr int NOUT = P / 2;
@@ -448,10 +448,10 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
 // zeta = Re/P^3 on R (MODE 0 and 1) and accumulates ||zeta||^2 and
 // ||r||^2 = sum (Im/P^3)^2 in FP64; the last workgroup sums the partials in
 // a fixed order and advances the alpha search (MODE 0).
-template <typename T, int P, int MODE>
+template <typename T, int P, int MODE, int SH>
 __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __restrict__ out, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = Tile<T, P>::C;
+  constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = C + 1;
   constexpr int NOUT = P / 2;
   constexpr int KXN = P / 2 + 1;
@@ -576,13 +576,24 @@ static inline hipError_t go(K kern, dim3 g, const Launch& L, Args... args) {
   return hipGetLastError();
 }
 
+// Tile variants: SH = 0 (32 KiB tile), 1 (half), 2 (quarter); the smaller
+// tiles are compiled for P >= 64 only (smaller lengths always use SH = 0).
+template <int P> constexpr int eff_sh(int sh) { return P >= 64 ? sh : 0; }
+#define FR3D_SH(p, sh, EXPR0, EXPR1, EXPR2) \
+  (eff_sh<p>(sh) == 2 ? (EXPR2) : eff_sh<p>(sh) == 1 ? (EXPR1) : (EXPR0))
+
 template <typename T>
 hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                         \
-  case p: {                                                                                          \
-    dim3 g(cdiv(a.ny_in, 2 * Tile<T, p>::C), a.nz_in);                                               \
-    return gen ? go(k_fx<T, p, true>, g, L, F, A, a, tw) : go(k_fx<T, p, false>, g, L, F, A, a, tw); \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
+    const int sh = eff_sh<p>(L.sh);                                                                              \
+    const int C = sh == 2 ? TileC<T, p, s2>::C : sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;               \
+    dim3 g(cdiv(a.ny_in, 2 * C), a.nz_in);                                                                       \
+    if (gen) return go(k_fx<T, p, true, 0>, dim3(cdiv(a.ny_in, 2 * TileC<T, p, 0>::C), a.nz_in), L, F, A, a, tw); \
+    return FR3D_SH(p, sh, go(k_fx<T, p, false, 0>, g, L, F, A, a, tw), go(k_fx<T, p, false, s1>, g, L, F, A, a, tw), \
+                   go(k_fx<T, p, false, s2>, g, L, F, A, a, tw));                                                \
   }
     FR3D_SIZES(X)
 #undef X
@@ -595,10 +606,15 @@ template <typename T>
 hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   const long long nrows = (long long)a.kx_n * a.nz_in;
   switch (P) {
-#define X(p)                                                                                             \
-  case p: {                                                                                              \
-    dim3 g(cdiv(nrows, Tile<T, p>::C));                                                                  \
-    return prune ? go(k_fy<T, p, true>, g, L, A, B, a, tw) : go(k_fy<T, p, false>, g, L, A, B, a, tw);   \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
+    const int sh = eff_sh<p>(L.sh);                                                                              \
+    const int C = sh == 2 ? TileC<T, p, s2>::C : sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;               \
+    dim3 g(cdiv(nrows, C));                                                                                      \
+    if (!prune) return go(k_fy<T, p, false, 0>, dim3(cdiv(nrows, TileC<T, p, 0>::C)), L, A, B, a, tw);           \
+    return FR3D_SH(p, sh, go(k_fy<T, p, true, 0>, g, L, A, B, a, tw), go(k_fy<T, p, true, s1>, g, L, A, B, a, tw), \
+                   go(k_fy<T, p, true, s2>, g, L, A, B, a, tw));                                                 \
   }
     FR3D_SIZES(X)
 #undef X
@@ -610,15 +626,20 @@ hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs&
 template <typename T>
 hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                             \
-  case p: {                                                                                              \
-    const int cols = mode == 0 ? a.py : a.py / 2 + 1;                                                    \
-    dim3 g(cdiv(cols, Tile<T, p>::C), a.kx_n);                                                           \
-    if (mode != 0) return go(k_fz<T, p, 1>, g, L, B, S, a, tw);                                          \
-    hipError_t e = go(k_fz<T, p, 0>, g, L, B, S, a, tw);                                                 \
-    if (e != hipSuccess) return e;                                                                       \
-    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                   \
-    return hipGetLastError();                                                                            \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
+    if (mode != 0) {                                                                                             \
+      dim3 g1(cdiv(a.py / 2 + 1, TileC<T, p, 0>::C), a.kx_n);                                                    \
+      return go(k_fz<T, p, 1, 0>, g1, L, B, S, a, tw);                                                           \
+    }                                                                                                            \
+    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
+    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
+    dim3 g(cdiv(a.py, C), a.kx_n);                                                                               \
+    hipError_t e = sh == 1 ? go(k_fz<T, p, 0, s1>, g, L, B, S, a, tw) : go(k_fz<T, p, 0, 0>, g, L, B, S, a, tw);  \
+    if (e != hipSuccess) return e;                                                                               \
+    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                           \
+    return hipGetLastError();                                                                                    \
   }
     FR3D_SIZES(X)
 #undef X
@@ -630,12 +651,16 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
 template <typename T>
 hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                               \
-  case p: {                                                                                                \
-    const long long ntile = cdiv(a.py, Tile<T, p>::C);                                                     \
-    const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                        \
-    dim3 g(16 * cdiv(npairs, 8));                                                                          \
-    return mode == 0 ? go(k_iz<T, p, 0>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1>, g, L, S, W1, a, tw);      \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
+    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
+    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
+    const long long ntile = cdiv(a.py, C);                                                                       \
+    const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
+    dim3 g(16 * cdiv(npairs, 8));                                                                                \
+    if (mode != 0) return sh == 1 ? go(k_iz<T, p, 1, s1>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0>, g, L, S, W1, a, tw); \
+    return sh == 1 ? go(k_iz<T, p, 0, s1>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0>, g, L, S, W1, a, tw);       \
   }
     FR3D_SIZES(X)
 #undef X
@@ -644,16 +669,18 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
   }
 }
 
-template <typename T> constexpr int half_tile(int c) { return c / 2 > 0 ? c / 2 : 1; }
-
 template <typename T>
 hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   const long long nrows = (long long)a.kx_n * a.nz;
   switch (P) {
-#define X(p)                                                  \
-  case p: {                                                   \
-    dim3 g(cdiv(nrows, half_tile<T>(Tile<T, p>::C)));         \
-    return go(k_iy<T, p>, g, L, W1, W2, a, tw);               \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
+    const int sh = eff_sh<p>(L.sh);                                                                              \
+    const int C = sh == 2 ? TileC<T, p, s2 + 1>::C : sh == 1 ? TileC<T, p, s1 + 1>::C : TileC<T, p, 1>::C;       \
+    dim3 g(cdiv(nrows, C));                                                                                      \
+    return FR3D_SH(p, sh, go(k_iy<T, p, 0>, g, L, W1, W2, a, tw), go(k_iy<T, p, s1>, g, L, W1, W2, a, tw),        \
+                   go(k_iy<T, p, s2>, g, L, W1, W2, a, tw));                                                     \
   }
     FR3D_SIZES(X)
 #undef X
@@ -665,14 +692,17 @@ hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const 
 template <typename T>
 hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
-#define X(p)                                                                                               \
-  case p: {                                                                                                \
-    dim3 g(cdiv(a.ny, Tile<T, p>::C), a.nz);                                                               \
-    if (mode != 0) return go(k_ix<T, p, 1>, g, L, W2, out, a, tw);                                        \
-    hipError_t e = go(k_ix<T, p, 0>, g, L, W2, out, a, tw);                                                \
-    if (e != hipSuccess) return e;                                                                         \
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                      \
-    return hipGetLastError();                                                                              \
+#define X(p)                                                                                                     \
+  case p: {                                                                                                      \
+    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
+    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
+    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
+    dim3 g(cdiv(a.ny, C), a.nz);                                                                                 \
+    if (mode != 0) return sh == 1 ? go(k_ix<T, p, 1, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 1, 0>, g, L, W2, out, a, tw); \
+    hipError_t e = sh == 1 ? go(k_ix<T, p, 0, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 0, 0>, g, L, W2, out, a, tw); \
+    if (e != hipSuccess) return e;                                                                               \
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                            \
+    return hipGetLastError();                                                                                    \
   }
     FR3D_SIZES(X)
 #undef X

@@ -28,8 +28,10 @@ EXPORTED = [
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
-    "fr3d_predictor_save", "fr3d_predictor_load",
+    "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
+PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
+TUNING_PATH = os.path.join(HERE, "data", "tuning.json")
 N_PARAMS = 25089
 N_NORM = 132
 
@@ -99,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_predictor_train_step": (I32, [P, P, P, I32, D, P, P]),
         "fr3d_predictor_save": (I32, [P, ctypes.c_char_p]),
         "fr3d_predictor_load": (I32, [P, ctypes.c_char_p]),
+        "fr3d_set_tile": (I32, [P, I32, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -296,6 +299,25 @@ class Context:
 
     def predictor_load(self, path):
         self._chk(self._lib.fr3d_predictor_load(self._ctx, os.fsencode(path)))
+
+    def set_tile(self, pass_id: int, shift: int):
+        self._chk(self._lib.fr3d_set_tile(self._ctx, int(pass_id), int(shift)))
+
+    def tuning_key(self):
+        g = self.geom
+        return f"{2 * g.nx}x{2 * g.ny}x{2 * g.nz}/fp{g.precision}"
+
+    def apply_tuning(self, path: str = TUNING_PATH):
+        """Tile variants from an autotuner cache (JSON {key: {pass name: shift}});
+        returns the applied entry or None when the cache has none for this geometry."""
+        import json
+        if not os.path.exists(path):
+            return None
+        entry = json.load(open(path)).get(self.tuning_key())
+        if entry:
+            for k, v in entry.items():
+                self.set_tile(PASS_NAMES.index(k), int(v))
+        return entry
 
     def set_timing(self, on: bool):
         self._chk(self._lib.fr3d_set_timing(self._ctx, 1 if on else 0))

@@ -285,3 +285,28 @@ def test_workload2_full_size(fr3d, index):
         assert rep["flags"] == 0
         assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + 1e-5
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_tile_variants_same_results(fr3d, precision):
+    # The tile size only changes how many pencils a workgroup holds: spectra
+    # and zeta are bit-identical; the norms differ only in summation order.
+    g = geom(64, 32, 48)
+    d = instance(g, 81, 0.02)
+    c = ctx_for(fr3d, g, precision)
+    Fd = dev(d["F"], precision)
+    outs = []
+    for shifts in ((0, 0, 0, 0, 0, 0), (1, 1, 1, 1, 1, 1), (2, 2, 1, 1, 2, 1)):
+        for p, sh in enumerate(shifts):
+            c.set_tile(p, sh)
+        c.set_data(Fd, d["delta"])
+        spec = host(c.get_data_spectrum())
+        z = torch.empty_like(Fd)
+        rep = c.solve_alpha(3e-5, z)
+        outs.append((spec, host(z), rep))
+    for spec, z, rep in outs[1:]:
+        assert np.array_equal(spec, outs[0][0])
+        assert np.array_equal(z, outs[0][1])
+        assert rep["residual"] == pytest.approx(outs[0][2]["residual"], rel=1e-12)
+    with pytest.raises(fr3d.Fr3dError):
+        c.set_tile(3, 2)
