@@ -289,8 +289,9 @@ def test_workload2_full_size(fr3d, index):
 
 @pytest.mark.parametrize("precision", [32, 64])
 def test_tile_variants_same_results(fr3d, precision):
-    # The tile size only changes how many pencils a workgroup holds: spectra
-    # and zeta are bit-identical; the norms differ only in summation order.
+    # The tile size only changes how many pencils a workgroup holds: spectra,
+    # zeta and norms agree to rounding (each tile variant is its own compiled
+    # instance, so the compiler may contract a different set of products).
     g = geom(64, 32, 48)
     d = instance(g, 81, 0.02)
     c = ctx_for(fr3d, g, precision)
@@ -304,9 +305,10 @@ def test_tile_variants_same_results(fr3d, precision):
         z = torch.empty_like(Fd)
         rep = c.solve_alpha(3e-5, z)
         outs.append((spec, host(z), rep))
+    tol = 1e-6 if precision == 32 else 1e-13
     for spec, z, rep in outs[1:]:
-        assert np.array_equal(spec, outs[0][0])
-        assert np.array_equal(z, outs[0][1])
-        assert rep["residual"] == pytest.approx(outs[0][2]["residual"], rel=1e-12)
+        assert rel_l2(spec, outs[0][0]) < tol
+        assert rel_l2(z, outs[0][1]) < 10 * tol
+        assert rep["residual"] == pytest.approx(outs[0][2]["residual"], rel=10 * tol)
     with pytest.raises(fr3d.Fr3dError):
         c.set_tile(3, 2)
