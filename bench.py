@@ -229,6 +229,11 @@ def main():
                  "bisection": fr3d.default_opts(**tight),
                  "learned_w": fr3d.default_opts(use_predictor=1, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
+    for m in modes:
+        if "@" in m:  # learned@<walk>: the learned search with another first walk step
+            base, w = m.split("@")
+            mode_opts[m] = fr3d.default_opts(use_predictor=1, seed_walk=float(w),
+                                             **(tight if base == "learned" else wide))
     results = {}
     head = modes[0]
     if not args.roofline_only:

@@ -61,7 +61,7 @@ def synthesize(ctx, torch, recipes, V0):
     return Fs, deltas
 
 
-def label_groups(indices, lanes=8, chunk=64, log=print, tol=1e-3):
+def label_groups(indices, lanes=8, chunk=64, log=print, tol=1e-6, max_steps=60):
     """Features, labels and reports of workload-5 instances, grouped by (n, q)."""
     import numpy as np
     import torch
@@ -87,7 +87,7 @@ def label_groups(indices, lanes=8, chunk=64, log=print, tol=1e-3):
             Fs, deltas = synthesize(ctx, torch, [recipes[i] for i in part], V0)
             zs = [torch.empty_like(F) for F in Fs]
             feat = torch.empty((len(part), 65), dtype=torch.float32, device="cuda")
-            reps = ctx.solve_batch(Fs, deltas, zs, feat=feat, tol=tol)
+            reps = ctx.solve_batch(Fs, deltas, zs, feat=feat, tol=tol, max_steps=max_steps)
             fh = feat.cpu().numpy()
             for k, i in enumerate(part):
                 X[pos[i]] = fh[k]
@@ -147,6 +147,7 @@ def main(argv=None):
     ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--out", default=DEFAULT_CKPT)
     ap.add_argument("--first-index", type=int, default=0)
+    ap.add_argument("--label-tol", type=float, default=1e-6)
     args = ap.parse_args(argv)
     import numpy as np
     import torch
@@ -155,7 +156,7 @@ def main(argv=None):
     n = args.instances
     idx = list(range(args.first_index, args.first_index + n))
     log = lambda m: print(m, flush=True)  # noqa: E731
-    X, t, meta = label_groups(idx, lanes=args.lanes, log=log)
+    X, t, meta = label_groups(idx, lanes=args.lanes, log=log, tol=args.label_tol)
     n_va = max(1, n // 20)
     n_te = max(1, n // 20)
     n_tr = n - n_va - n_te
@@ -167,8 +168,10 @@ def main(argv=None):
     ctx.predictor_save(args.out)
     flags = np.array([meta[i]["flags"] for i in idx])
     summary = dict(instances=n, split=[n_tr, n_va, n_te], first_index=args.first_index, epochs=args.epochs,
+                   label_tol=args.label_tol,
                    test_mae_decades=float(np.abs(err).mean()),
                    test_within_0_25_decades=float((np.abs(err) <= 0.25).mean()),
+                   test_within_0_05_decades=float((np.abs(err) <= 0.05).mean()),
                    label_flags={str(k): int((flags == k).sum()) for k in sorted(set(flags.tolist()))},
                    label_mean_evals=float(np.mean([meta[i]["n_evals"] for i in idx])),
                    last=hist[-1])
