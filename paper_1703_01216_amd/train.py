@@ -7,7 +7,7 @@ cubic grid of 64, 96 or 128 cells, source parameter q in {0..3} with its own
 kernel, noise level U[0.5%, 5%]) is synthesised through the library's own
 forward operator: zeta = xi V0 on R, F = A zeta on Y, plus seeded noise scaled
 to delta.  Its label is log10 alpha* of the discrepancy search (bisection to
-|r/delta - 1| <= 1e-3) and its features are the 65 spectral features of F;
+|r/delta - 1| <= 1e-6, i.e. the root) and its features are the 65 spectral features of F;
 both come from the batch solver.  The network is then trained with the
 library's BF16-MFMA kernels (Adam, mean squared error on standardised
 log10 alpha) and saved as a checkpoint.  All of this runs through the C-ABI;
