@@ -312,3 +312,26 @@ def test_tile_variants_same_results(fr3d, precision):
         assert rep["residual"] == pytest.approx(outs[0][2]["residual"], rel=10 * tol)
     with pytest.raises(fr3d.Fr3dError):
         c.set_tile(3, 2)
+
+
+def test_workload1_fp64_against_direct_quadrature(fr3d):
+    # 32^3 grids padded to 64^3, FP64 end to end, alpha = 1e-4: the data come
+    # from the oracle's direct O(n^6) quadrature of the operator; the device's
+    # forward operator matches that sum and its estimate matches the oracle's.
+    from paper_1703_01216_amd import inputs
+    from oracle import synth
+    inst = inputs.workload_instance(1, 0)
+    g = geom(32, 32, 32)
+    d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"], direct=True)
+    c = ctx_for(fr3d, g, 64)
+    zt = dev(d["zeta"], 64)
+    AF = torch.empty_like(zt)
+    c.apply_operator(zt, AF)
+    assert rel_l2(host(AF), d["AF"]) < 1e-13
+    Fd = dev(d["F"], 64)
+    c.set_data(Fd, d["delta"])
+    z = torch.empty_like(Fd)
+    rep = c.solve_alpha(1e-4, z)
+    ref = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), d["F"], 1e-4)
+    assert rel_l2(host(z), ref["zeta"]) < 1e-11
+    assert rep["residual"] == pytest.approx(ref["r_norm"], rel=1e-11)

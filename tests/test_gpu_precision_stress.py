@@ -1,0 +1,70 @@
+"""Precision stress (256^3 grid padded to 512^3, 1 GiB per FP32 complex
+volume): smooth background plus 20 sharp inclusions with contrast up to 0.9,
+delta = 0.5%.  The FP32 path, the FP64 GPU path and the CPU FP64 oracle are
+compared on the same data (synthesised by the oracle): zeta at the same alpha
+and the discrepancy reached at the device's alpha."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import synth, tikhonov
+from oracle.geometry import sample_kernel
+
+from gpu_helpers import geom, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fr3d():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_01216_amd import fr3d as m
+    return m
+
+
+def test_workload4_fp32_fp64_oracle(fr3d):
+    from paper_1703_01216_amd import inputs
+    t0 = time.time()
+    inst = inputs.workload_instance(4, 0)
+    g = geom(256, 256, 256)
+    d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"])
+    khat = np.fft.fftn(sample_kernel(g))
+    print(f"oracle synthesis {time.time() - t0:.1f}s", flush=True)
+    out = {}
+    for prec in (64, 32):
+        c = fr3d.Context()
+        c.load_kernel(256, 256, 256, precision=prec)
+        dt = torch.float64 if prec == 64 else torch.float32
+        F = torch.tensor(d["F"], dtype=dt, device="cuda")
+        c.set_data(F, d["delta"])
+        z = torch.empty_like(F)
+        rep = c.solve_discrepancy(z)
+        out[prec] = (rep, z.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64))
+        if prec == 64:
+            z32 = None
+        c.close()
+        del F, z
+        torch.cuda.empty_cache()
+    rep64, z64, F64 = out[64]
+    rep32, z32, F32 = out[32]
+    # FP64 GPU vs oracle at the FP64 alpha
+    o64 = tikhonov.solve_spectral(g, khat, F64, rep64["alpha"])
+    e64 = rel_l2(z64, o64["zeta"])
+    # FP32 GPU vs oracle at the FP32 alpha (on the FP32-rounded data)
+    o32 = tikhonov.solve_spectral(g, khat, F32, rep32["alpha"])
+    e32 = rel_l2(z32, o32["zeta"])
+    d32 = abs(o32["r_norm"] / d["delta"] - 1)
+    print(f"workload 4: fp64 alpha={rep64['alpha']:.6e} flags={rep64['flags']} evals={rep64['n_evals']} "
+          f"rel_l2 vs oracle={e64:.2e}; fp32 alpha={rep32['alpha']:.6e} flags={rep32['flags']} "
+          f"evals={rep32['n_evals']} rel_l2 vs oracle={e32:.2e} oracle r/delta-1 at fp32 alpha={d32:.2e}; "
+          f"total {time.time() - t0:.1f}s", flush=True)
+    assert e64 < 1e-10
+    assert e32 < 1e-5
+    assert rep64["flags"] == rep32["flags"]
+    if rep32["flags"] == 0:
+        assert d32 <= 1e-3 + 1e-5
+    else:
+        assert rep32["alpha"] == rep64["alpha"]
