@@ -159,6 +159,18 @@ fr3d_status fr3d_solve_batch(fr3d_ctx* ctx, int32_t n, const void* const* F_devs
                              void* const* zeta_devs, const fr3d_dp_opts* opts, const void* V0_dev, double c0,
                              void* const* c_devs, float* feat_dev, fr3d_report* reps);
 
+/* The same solve for items of different geometries (Sec. 6 model: grid sizes
+ * and source sets differ between surveys): item i runs on ctxs[i], a context
+ * whose kernel is loaded for that item's grid (nz*ny*nx of that context),
+ * with V0s[i] its V0 when c_devs is not NULL.  Every lane of every distinct
+ * context is scheduled together, so instances of all geometries are in
+ * flight at once.  With use_predictor each context uses its own loaded
+ * predictor.  A context must not appear in two concurrent calls.  Errors are
+ * reported on ctxs[0] (fr3d_last_error).  n = 0 returns FR3D_OK. */
+fr3d_status fr3d_solve_group(int32_t n, fr3d_ctx* const* ctxs, const void* const* F_devs, const double* deltas,
+                             void* const* zeta_devs, const fr3d_dp_opts* opts, const void* const* V0_devs,
+                             double c0, void* const* c_devs, fr3d_report* reps);
+
 /* Algorithm 1 step 4: xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2) on R; where
  * 1/c0^2 - xi < 1e-6/c0^2 the argument is clamped and the cell counted in
  * *n_clamped (synchronises).  c0 > 0.  zeta, V0, c: nz*ny*nx device arrays. */

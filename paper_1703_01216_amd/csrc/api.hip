@@ -20,6 +20,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -855,54 +856,66 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
   return run_search(c, max_evals, zeta, rep);
 }
 
-// Batch scheduler: instance i goes to the next free lane, which runs
-// set_data, the search and (optionally) recovery on its own stream.  Each lane
-// advances one evaluation at a time; the host polls the lanes' completion
-// events and enqueues the next step of whichever lane is ready, so the lanes'
-// work overlaps on the device and no evaluation is launched after its search
-// has finished.
-fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const double* deltas, void* const* zetas,
-                             const fr3d_dp_opts* o, const void* V0, double c0, void* const* c_out,
-                             float* feat_out, fr3d_report* reps) {
-  if (!c) return FR3D_E_INVALID;
-  if (!need(c, true, false)) return FR3D_E_STATE;
-  if (n < 0 || (n > 0 && (!F || !deltas || !zetas || !reps))) return fail(c, FR3D_E_INVALID, "null batch arrays");
-  if (c_out && (!V0 || !(c0 > 0) || !std::isfinite(c0))) return fail(c, FR3D_E_INVALID, "recovery needs V0 and c0 > 0");
-  for (int i = 0; i < n; ++i) {
-    if (!F[i] || !zetas[i] || (c_out && !c_out[i])) return fail(c, FR3D_E_INVALID, "null array in batch item %d", i);
-    if (!(deltas[i] >= 0) || !std::isfinite(deltas[i])) return fail(c, FR3D_E_INVALID, "bad delta in batch item %d", i);
-  }
-  fr3d_dp_opts d;
-  fr3d_status s = check_opts(c, o, &d);
-  if (s) return s;
-  if ((s = ensure_lanes(c))) return s;
-  const int nl = std::max(1, std::min((int)c->lanes.size(), c->nlanes_wanted));
-  // order: the caller's stream before every lane, every lane before the caller's stream
-  hipEvent_t fence;
-  HIPCHK(c, hipEventCreateWithFlags(&fence, hipEventDisableTiming));
-  HIPCHK(c, hipEventRecord(fence, c->lanes[0].stream));
-  for (int l = 1; l < nl; ++l) HIPCHK(c, hipStreamWaitEvent(c->lanes[l].stream, fence, 0));
+}  // extern "C"
+
+namespace {
+
+// Scheduler over slots (a slot = a context and one of its lanes).  Item i
+// runs set_data, the search and (optionally) recovery on one slot whose
+// context is ctx_of[i]; each slot advances one evaluation at a time, and the
+// host polls the slots' completion events and enqueues the next step of
+// whichever slot is ready, so the slots' work overlaps on the device and no
+// evaluation is launched after its search has finished.
+struct Slot {
+  fr3d_ctx* c;
+  int lane;
+};
+
+struct Items {
+  int n;
+  fr3d_ctx* const* ctx_of;  // per item, or null: every item on ctx0
+  fr3d_ctx* ctx0;
+  const void* const* F;
+  const double* deltas;
+  void* const* zetas;
+  const void* const* V0;  // per item (null: no recovery)
+  double c0;
+  void* const* c_out;
+  float* feat_out;
+  fr3d_report* reps;
+};
+
+fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_dp_opts& d) {
+  const int ns = (int)slots.size();
   enum { IDLE, SEARCH, RECOVER };
-  std::vector<int> item(nl, -1), state(nl, IDLE), launched(nl, 0), limit(nl, 0);
-  int next = 0, done = 0;
-  s = FR3D_OK;
-  while (done < n && s == FR3D_OK) {
+  std::vector<int> item(ns, -1), state(ns, IDLE), launched(ns, 0), limit(ns, 0);
+  std::vector<char> started(it.n, 0);
+  int done = 0, scan = 0;
+  fr3d_status s = FR3D_OK;
+  fr3d_ctx* bad = nullptr;
+  auto ctx_of = [&](int i) { return it.ctx_of ? it.ctx_of[i] : it.ctx0; };
+  while (done < it.n && s == FR3D_OK) {
     bool progressed = false;
-    for (int l = 0; l < nl && s == FR3D_OK; ++l) {
-      Lane& L = c->lanes[l];
+    for (int l = 0; l < ns && s == FR3D_OK; ++l) {
+      fr3d_ctx* c = slots[l].c;
+      Lane& L = c->lanes[slots[l].lane];
       if (state[l] == IDLE) {
-        if (next >= n) continue;
-        const int i = next++;
+        int i = -1;
+        for (int k = scan; k < it.n; ++k)
+          if (!started[k] && ctx_of(k) == c) { i = k; break; }
+        if (i < 0) continue;
+        started[i] = 1;
+        while (scan < it.n && started[scan]) ++scan;
         item[l] = i;
-        if ((s = set_data_lane(c, L, F[i], deltas[i]))) break;
-        if (feat_out &&
-            hipMemcpyAsync(feat_out + (size_t)i * 65, L.feat, 65 * sizeof(float), hipMemcpyDeviceToDevice, L.stream) !=
-                hipSuccess) {
+        bad = c;
+        if ((s = set_data_lane(c, L, it.F[i], it.deltas[i]))) break;
+        if (it.feat_out && hipMemcpyAsync(it.feat_out + (size_t)i * 65, L.feat, 65 * sizeof(float),
+                                          hipMemcpyDeviceToDevice, L.stream) != hipSuccess) {
           s = fail(c, FR3D_E_DEVICE, "feature copy");
           break;
         }
         if ((s = start_search(c, L, d, &limit[l]))) break;
-        if ((s = eval_lane(c, L, zetas[i]))) break;
+        if ((s = eval_lane(c, L, it.zetas[i]))) break;
         launched[l] = 1;
         if ((s = post_ctrl(c, L))) break;
         state[l] = SEARCH;
@@ -911,40 +924,131 @@ fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const
       }
       const hipError_t q = hipEventQuery(L.ev);
       if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess) { s = fail(c, FR3D_E_DEVICE, "lane %d: %s", l, hipGetErrorString(q)); break; }
+      bad = c;
+      if (q != hipSuccess) { s = fail(c, FR3D_E_DEVICE, "lane %d: %s", slots[l].lane, hipGetErrorString(q)); break; }
       progressed = true;
       const int i = item[l];
       if (state[l] == SEARCH) {
         if (L.ctrl_host->active && launched[l] < limit[l]) {
-          if ((s = eval_lane(c, L, zetas[i]))) break;
+          if ((s = eval_lane(c, L, it.zetas[i]))) break;
           launched[l] += 1;
           if ((s = post_ctrl(c, L))) break;
           continue;
         }
         if (L.ctrl_host->active) { s = fail(c, FR3D_E_DEVICE, "search of item %d did not finish", i); break; }
-        fill_report(*L.ctrl_host, &reps[i]);
+        fill_report(*L.ctrl_host, &it.reps[i]);
         if (c->timing) tcollect(c, L, L.ctrl_host->n_evals);
-        if (c_out) {
-          if ((s = launch_recover(c, L, zetas[i], V0, c0, c_out[i], true))) break;
+        if (it.c_out) {
+          if ((s = launch_recover(c, L, it.zetas[i], it.V0[i], it.c0, it.c_out[i], true))) break;
           if (hipEventRecord(L.ev, L.stream) != hipSuccess) { s = fail(c, FR3D_E_DEVICE, "event record"); break; }
           state[l] = RECOVER;
           continue;
         }
       } else {
-        reps[i].n_clamped = (int64_t)L.scal_host[0];
+        it.reps[i].n_clamped = (int64_t)L.scal_host[0];
       }
       state[l] = IDLE;
       done += 1;
     }
     if (!progressed && s == FR3D_OK) std::this_thread::yield();
   }
-  for (int l = 1; l < nl; ++l) {
-    (void)hipEventRecord(fence, c->lanes[l].stream);
-    (void)hipStreamWaitEvent(c->lanes[0].stream, fence, 0);
+  if (s != FR3D_OK && bad && it.ctx0 && bad != it.ctx0) it.ctx0->err = bad->err;
+  return s;
+}
+
+// Orders every lane in use of c after (begin) or before (end) c's lane 0.
+fr3d_status fence_lanes(fr3d_ctx* c, int nl, bool begin) {
+  hipEvent_t e;
+  HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (begin) {
+    HIPCHK(c, hipEventRecord(e, c->lanes[0].stream));
+    for (int l = 1; l < nl; ++l) HIPCHK(c, hipStreamWaitEvent(c->lanes[l].stream, e, 0));
+  } else {
+    for (int l = 1; l < nl; ++l) {
+      HIPCHK(c, hipEventRecord(e, c->lanes[l].stream));
+      HIPCHK(c, hipStreamWaitEvent(c->lanes[0].stream, e, 0));
+    }
   }
+  (void)hipEventDestroy(e);
+  return FR3D_OK;
+}
+
+fr3d_status check_item(fr3d_ctx* c, int i, const void* F, double delta, void* zeta, bool rec, const void* V0,
+                       void* cout) {
+  if (!F || !zeta || (rec && (!cout || !V0))) return fail(c, FR3D_E_INVALID, "null array in batch item %d", i);
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(c, FR3D_E_INVALID, "bad delta in batch item %d", i);
+  return FR3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const double* deltas, void* const* zetas,
+                             const fr3d_dp_opts* o, const void* V0, double c0, void* const* c_out,
+                             float* feat_out, fr3d_report* reps) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, false)) return FR3D_E_STATE;
+  if (n < 0 || (n > 0 && (!F || !deltas || !zetas || !reps))) return fail(c, FR3D_E_INVALID, "null batch arrays");
+  if (c_out && (!V0 || !(c0 > 0) || !std::isfinite(c0))) return fail(c, FR3D_E_INVALID, "recovery needs V0 and c0 > 0");
+  fr3d_status s;
+  for (int i = 0; i < n; ++i)
+    if ((s = check_item(c, i, F[i], deltas[i], zetas[i], c_out != nullptr, V0, c_out ? c_out[i] : nullptr))) return s;
+  fr3d_dp_opts d;
+  if ((s = check_opts(c, o, &d))) return s;
+  if ((s = ensure_lanes(c))) return s;
+  const int nl = std::max(1, std::min((int)c->lanes.size(), c->nlanes_wanted));
+  std::vector<Slot> slots;
+  for (int l = 0; l < nl; ++l) slots.push_back({c, l});
+  std::vector<const void*> v0s(c_out ? n : 0, V0);
+  Items it{n, nullptr, c, F, deltas, zetas, c_out ? v0s.data() : nullptr, c0, c_out, feat_out, reps};
+  if ((s = fence_lanes(c, nl, true))) return s;
+  s = run_schedule(slots, it, d);
+  fence_lanes(c, nl, false);
   if (s != FR3D_OK)
     for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
-  (void)hipEventDestroy(fence);
+  return s;
+}
+
+// Items of different geometries (grid sizes, kernels) in one scheduler: item
+// i runs on ctxs[i]; every lane in use of every distinct context is a slot.
+fr3d_status fr3d_solve_group(int32_t n, fr3d_ctx* const* ctxs, const void* const* F, const double* deltas,
+                             void* const* zetas, const fr3d_dp_opts* o, const void* const* V0s, double c0,
+                             void* const* c_out, fr3d_report* reps) {
+  if (n < 0 || (n > 0 && (!ctxs || !ctxs[0]))) return FR3D_E_INVALID;
+  if (n == 0) return FR3D_OK;
+  fr3d_ctx* c0x = ctxs[0];
+  if (!F || !deltas || !zetas || !reps) return fail(c0x, FR3D_E_INVALID, "null batch arrays");
+  if (c_out && (!V0s || !(c0 > 0) || !std::isfinite(c0))) return fail(c0x, FR3D_E_INVALID, "recovery needs V0 and c0 > 0");
+  std::vector<fr3d_ctx*> distinct;
+  fr3d_status s;
+  for (int i = 0; i < n; ++i) {
+    fr3d_ctx* c = ctxs[i];
+    if (!c) return fail(c0x, FR3D_E_INVALID, "null context in item %d", i);
+    if (!need(c, true, false)) { c0x->err = c->err; return FR3D_E_STATE; }
+    if ((s = check_item(c0x, i, F[i], deltas[i], zetas[i], c_out != nullptr, c_out ? V0s[i] : nullptr,
+                        c_out ? c_out[i] : nullptr)))
+      return s;
+    if (std::find(distinct.begin(), distinct.end(), c) == distinct.end()) distinct.push_back(c);
+  }
+  fr3d_dp_opts d;
+  for (fr3d_ctx* c : distinct)
+    if ((s = check_opts(c, o, &d))) { c0x->err = c->err; return s; }
+  std::vector<Slot> slots;
+  std::vector<int> nls;
+  for (fr3d_ctx* c : distinct) {
+    if ((s = ensure_lanes(c))) { c0x->err = c->err; return s; }
+    const int nl = std::max(1, std::min((int)c->lanes.size(), c->nlanes_wanted));
+    nls.push_back(nl);
+    if ((s = fence_lanes(c, nl, true))) { c0x->err = c->err; return s; }
+    for (int l = 0; l < nl; ++l) slots.push_back({c, l});
+  }
+  Items it{n, ctxs, c0x, F, deltas, zetas, V0s, c0, c_out, nullptr, reps};
+  s = run_schedule(slots, it, d);
+  for (size_t k = 0; k < distinct.size(); ++k) fence_lanes(distinct[k], nls[k], false);
+  if (s != FR3D_OK)
+    for (fr3d_ctx* c : distinct)
+      for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
   return s;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -95,6 +95,9 @@ def load_library(path: str = LIB_PATH):
         "fr3d_set_lanes": (I32, [P, I32]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
+        "fr3d_solve_group": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
+                                   ctypes.POINTER(DpOpts), ctypes.POINTER(P), D, ctypes.POINTER(P),
+                                   ctypes.POINTER(Report)]),
         "fr3d_predictor_set": (I32, [P, ctypes.POINTER(ctypes.c_float), I64, ctypes.POINTER(ctypes.c_float)]),
         "fr3d_predictor_get": (I32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
         "fr3d_predictor_forward": (I32, [P, P, I32, P]),
@@ -327,3 +330,29 @@ class Context:
         n = ctypes.c_int64()
         self._chk(self._lib.fr3d_get_timing(self._ctx, int(pass_id), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def solve_group(ctxs, F_list, deltas, zetas, opts: DpOpts | None = None, V0_list=None, c0=1.0, c_list=None, **kw):
+    """Discrepancy solves of items of different geometries: item i on ctxs[i]
+    (fr3d_solve_group).  Returns one report dict per item."""
+    n = len(F_list)
+    if len(ctxs) != n or len(deltas) != n or len(zetas) != n:
+        raise ValueError("group lists must have equal lengths")
+    if c_list is not None and (V0_list is None or len(c_list) != n or len(V0_list) != n):
+        raise ValueError("recovery needs V0_list and c_list of the group's length")
+    if n == 0:
+        return []
+    o = opts if opts is not None else default_opts(**kw)
+    PA = ctypes.c_void_p * n
+    Ca_ = PA(*[c._ctx.value for c in ctxs])
+    Fa = PA(*[c._arr(f, "F").value for c, f in zip(ctxs, F_list)])
+    Za = PA(*[c._arr(z, "zeta").value for c, z in zip(ctxs, zetas)])
+    Da = (ctypes.c_double * n)(*[float(d) for d in deltas])
+    reps = (Report * n)()
+    Va = PA(*[c._arr(v, "V0").value for c, v in zip(ctxs, V0_list)]) if c_list is not None else None
+    Oa = PA(*[c._arr(x, "c").value for c, x in zip(ctxs, c_list)]) if c_list is not None else None
+    L = lib()
+    s = L.fr3d_solve_group(n, Ca_, Fa, Da, Za, ctypes.byref(o), Va, float(c0), Oa, reps)
+    if s != OK:
+        raise Fr3dError(s, L.fr3d_last_error(ctxs[0]._ctx).decode())
+    return [reps[i].as_dict() for i in range(n)]
