@@ -29,6 +29,18 @@ Seeded search (a predicted t0 from the alpha predictor; not in the paper):
   that survives two steps in a row is halved), at most max_steps points;
   otherwise alpha = 10^b, MAXITER.  PRED_FALLBACK is set whenever the first
   point is not accepted.
+
+K-candidate search (K alphas per step, log-spaced in the current bracket; not
+in the paper -- the batched form of the same rule):
+  step 1 evaluates t_j = lo + j (hi - lo)/(K - 1), j = 0..K-1 (both range ends);
+  later steps evaluate the K interior points t_j = a + (j + 1)(b - a)/(K + 1).
+  After a step: the candidate with the smallest |r/T - 1| among those with
+  |r/T - 1| <= tol (the lowest index on ties) is accepted.  Otherwise, in
+  step 1, rho(hi) < 0 -> NOROOT_HIGH at hi and rho(lo) > 0 -> NOROOT_LOW at lo;
+  then b is the first point (in increasing t, the old b last) with rho >= 0 and
+  a the point before it (the old a first).  After max_steps steps the answer
+  is b, MAXITER.  The answer is evaluated once more on its own (it is where
+  zeta is written), so n_evals = K * steps + 1.
 """
 from __future__ import annotations
 
@@ -147,3 +159,43 @@ def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=
     if ev.last_t != b:
         ev(b)
     return out(b, flags | MAXITER)
+
+
+def kary(evaluate, delta, K=16, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, tau=1.0, h_op=0.0, mu=0.0):
+    """K-candidate search (module docstring).  Returns dict(alpha, t, flags,
+    n_evals, trace, steps)."""
+    if K < 2:
+        raise ValueError("K >= 2")
+    ev = _Counter(evaluate, delta, tau, h_op, mu)
+
+    def finish(t, flags, steps):
+        ev(t)
+        return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace, steps=steps)
+
+    a = b = None
+    for step in range(max_steps):
+        if step == 0:
+            ts = [lo + j * (hi - lo) / (K - 1) for j in range(K)]
+        else:
+            ts = [a + (j + 1) * (b - a) / (K + 1) for j in range(K)]
+        res = [ev(t) for t in ts]
+        best = None
+        for j, (rho, ratio, r, zn) in enumerate(res):
+            d = abs(ratio - 1.0)
+            if d <= tol and (best is None or d < best[0]):
+                best = (d, j)
+        if best is not None:
+            return finish(ts[best[1]], 0, step + 1)
+        rhos = [x[0] for x in res]
+        if step == 0:
+            if rhos[-1] < 0:
+                return finish(hi, NOROOT_HIGH, 1)
+            if rhos[0] > 0:
+                return finish(lo, NOROOT_LOW, 1)
+            pts, signs = ts, rhos
+        else:
+            pts = [a] + ts + [b]
+            signs = [-1.0] + rhos + [0.0]          # rho(a) < 0 <= rho(b)
+        jb = next(j for j, v in enumerate(signs) if v >= 0)
+        a, b = pts[jb - 1], pts[jb]
+    return finish(b, MAXITER, max_steps)

@@ -373,6 +373,58 @@ def test_seeded_matches_bisection_answer_quality():
             assert abs(rr / delta - 1) <= 1e-3
 
 
+@pytest.mark.parametrize("K", [2, 5, 16])
+@pytest.mark.parametrize("frac", [0.01, 0.05, 0.3])
+def test_kary_reaches_closed_form_root(K, frac):
+    ev, delta, Fn = _identity_problem(frac)
+    a_star = delta / (Fn - delta)
+    t_star = math.log10(a_star)
+    res = discrepancy.kary(ev, delta, K=K, tol=1e-6)
+    assert res["flags"] == 0
+    assert res["alpha"] == pytest.approx(a_star, rel=1e-5)
+    assert res["n_evals"] == K * res["steps"] + 1 == len(res["trace"])
+    ts = [t for t, *_ in res["trace"]]
+    # step 1: K points from lo to hi inclusive
+    assert ts[0] == -8.0 and ts[K - 1] == 0.0
+    assert np.allclose(np.diff(ts[:K]), 8.0 / (K - 1))
+    # every later step: K equally spaced interior points of a bracket around t*
+    # whose width shrinks by K + 1 per step
+    width = 8.0 / (K - 1)
+    for s in range(1, res["steps"]):
+        pts = ts[s * K:(s + 1) * K]
+        h = width / (K + 1)
+        a = pts[0] - h
+        assert np.allclose(np.diff(pts), h) and a - 1e-12 <= t_star <= a + width + 1e-12
+        width = h
+    # the answer is evaluated last, on its own
+    assert ts[-1] == res["t"]
+
+
+def test_kary_flags_and_best_candidate():
+    ev, delta, Fn = _identity_problem(0.6)
+    res = discrepancy.kary(ev, delta, K=16)
+    assert res["flags"] == discrepancy.NOROOT_HIGH and res["alpha"] == 1.0 and res["n_evals"] == 17
+    ev, delta, Fn = _identity_problem(1e-12)
+    res = discrepancy.kary(ev, delta, K=16)
+    assert res["flags"] == discrepancy.NOROOT_LOW and res["alpha"] == 1e-8 and res["n_evals"] == 17
+    ev, delta, Fn = _identity_problem(0.05)
+    t_star = math.log10(delta / (Fn - delta))
+    res = discrepancy.kary(ev, delta, K=4, tol=0.0, max_steps=3)
+    assert res["flags"] == discrepancy.MAXITER and res["n_evals"] == 13
+    # b is the bracket's upper end: rho(b) >= 0 and b - a = 8/3/5/5 around t*
+    assert res["t"] >= t_star and res["t"] - 8.0 / 3 / 25 <= t_star + 1e-12
+
+    # several candidates inside the tolerance: the one closest to the target wins
+    g = {3: 5e-4, 5: -2e-4, 9: 3e-4}
+
+    def ev2(alpha):
+        t = math.log10(alpha)
+        j = round((t + 8.0) * 15 / 8.0)
+        return 1.0 + g.get(j, (0.5 if j > 5 else -0.5)), 0.0
+    res = discrepancy.kary(ev2, 1.0, K=16, tol=1e-3)
+    assert res["flags"] == 0 and res["t"] == -8.0 + 5 * 8.0 / 15 and res["n_evals"] == 17
+
+
 # ---------------------------------------------------------------- recovery and V0 (Sec. 2, Sec. 6)
 
 def test_model_example_v0_closed_form():
