@@ -84,6 +84,7 @@ typedef struct {
   double tau, h_op, mu;                  /* generalised principle, default 1, 0, 0 */
   int32_t use_predictor;                 /* 1: seed the search with the alpha predictor */
   double seed_walk;                      /* first walk step from the seed in decades, default 0.25 */
+  int32_t candidates;                    /* K = 2..16: K-candidate search (K alphas per step); 0: off */
 } fr3d_dp_opts;
 
 typedef struct {
@@ -140,7 +141,14 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
  * use_predictor: start from the predicted alpha (accepted inside [accept_lo,
  * accept_hi] or within tol), walk toward the sign change with doubling steps
  * from seed_walk decades, then Illinois regula falsi on r/T - 1 inside the
- * bracket.  Fills *rep (synchronises). */
+ * bracket.  With candidates = K (2..16, not with use_predictor, max_steps >= 1):
+ * each step evaluates K alphas in one set of launches, the first step at K
+ * points from lo to hi, later steps at the K interior points of the current
+ * bracket (log-spaced); the candidate closest to the target within tol is
+ * accepted, else the bracket narrows to the two points around the sign change
+ * of rho (NOROOT_* as above after the first step, MAXITER after max_steps
+ * steps with the answer b); the answer is evaluated once more on its own to
+ * write zeta (n_evals = K steps + 1).  Fills *rep (synchronises). */
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
                                    fr3d_report* rep);
 

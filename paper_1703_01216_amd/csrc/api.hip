@@ -34,7 +34,10 @@ using namespace fr3d;
 // ============================================================ small kernels
 namespace {
 
-__global__ void k_ctrl_init(Ctrl* c, Ctrl v) { *c = v; }
+__global__ void k_ctrl_init(Ctrl* c, Ctrl v) {
+  *c = v;
+  if (v.state == ST_KARY) ctrl_kary_points(c);  // first step's candidates
+}
 
 // Recovery (Algorithm 1, step 4): xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2)
 // with the argument clamped at 1e-6/c0^2; per-block counts of clamped cells.
@@ -156,6 +159,10 @@ struct Lane {
   double* scal = nullptr;       // small FP64 scratch
   double* scal_host = nullptr;  // pinned
   uint32_t* ticket = nullptr;
+  void* kwork = nullptr;        // K-candidate workspaces: K slices of W1, then K of W2
+  double2* knorm = nullptr;     // K-candidate norm partials
+  int kcap = 0;                 // candidates the K-candidate workspaces hold
+  int kmax = 0;                 // K of the lane's current search (0: not a K-candidate search)
   hipEvent_t ev = nullptr;      // completion marker polled by the batch scheduler
   bool has_data = false;
   double delta = 0;
@@ -237,6 +244,10 @@ void free_lane_geometry(Lane& L) {
   dfree(L.work);
   dfree(L.bins_part);
   dfree(L.norm_part);
+  dfree(L.kwork);
+  dfree(L.knorm);
+  L.kcap = 0;
+  L.kmax = 0;
   L.has_data = false;
 }
 
@@ -459,6 +470,32 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     return st;
   Bufs<T> b = bufs<T>(c, L);
   InvArgs a = inv_args(c, L, mode == 0);
+  if (mode == 0 && L.kmax > 0) {
+    // K-candidate step (runs only while the search is in that state)
+    const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny, nB = (size_t)c->kxn * c->g.nz * c->py;
+    InvArgs ak = a;
+    ak.kmode = 1;
+    ak.kmax = L.kmax;
+    ak.w1_stride = (long long)nB;
+    ak.w2_stride = (long long)nA;
+    ak.norm_stride = (long long)c->norm_part_n;
+    ak.norm_part = L.knorm;
+    // candidates per z-pass workgroup: all K unless the grid would be small
+    const long long tiles = (long long)c->kxn * std::max<long long>(1, (long long)c->py * c->pz / (c->esz == 8 ? 2048 : 4096));
+    int kb = L.kmax;
+    while (kb > 1 && tiles * ((L.kmax + kb - 1) / kb) < 2048) kb = (kb + 1) / 2;
+    ak.kb = kb;
+    c4<T>* W1k = (c4<T>*)L.kwork;
+    c4<T>* W2k = W1k + (size_t)L.kmax * nB;
+    const Launch none{L.stream, nullptr, nullptr, 0};
+    Launch lz = none, ly = none, lx = none;
+    lz.sh = c->tile_sh[3];
+    ly.sh = c->tile_sh[4];
+    lx.sh = c->tile_sh[5];
+    LCHK(c, launch_iz<T>(c->pz, 0, b.S, W1k, ak, (const c2<T>*)twz, lz));
+    LCHK(c, launch_iy<T>(c->py, W1k, W2k, ak, (const c2<T>*)twy, ly));
+    LCHK(c, launch_ix<T>(c->px, 0, W2k, (T*)nullptr, ak, (const c2<T>*)twx, lx));
+  }
   LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
   LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, L, 4)));
   LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, L, 5)));
@@ -503,7 +540,21 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
       !(d->seed_walk > 0) || !std::isfinite(d->seed_walk))
     return fail(c, FR3D_E_INVALID, "bad search options");
+  if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
+    return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
   if (d->use_predictor && !c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  return FR3D_OK;
+}
+
+fr3d_status ensure_kwork(fr3d_ctx* c, Lane& L, int K) {
+  if (L.kcap >= K) return FR3D_OK;
+  dfree(L.kwork);
+  dfree(L.knorm);
+  L.kcap = 0;
+  const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny, nB = (size_t)c->kxn * c->g.nz * c->py;
+  HIPCHK(c, hipMalloc(&L.kwork, (size_t)K * (nA + nB) * 4 * c->esz));
+  HIPCHK(c, hipMalloc(&L.knorm, (size_t)K * c->norm_part_n * sizeof(double2)));
+  L.kcap = K;
   return FR3D_OK;
 }
 
@@ -524,9 +575,20 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_e
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
+  L.kmax = 0;
+  if (d.candidates) {
+    fr3d_status s = ensure_kwork(c, L, d.candidates);
+    if (s) return s;
+    L.kmax = d.candidates;
+    v.state = ST_KARY;
+    v.kmax = d.candidates;
+    v.steps = 0;
+  }
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, L.stream, L.ctrl, v);
   LCHK(c, hipGetLastError());
-  if (d.use_predictor) {
+  if (d.candidates) {
+    *max_evals = d.max_steps;  // each evaluation call: one K-candidate step, then the answer once found
+  } else if (d.use_predictor) {
     LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream));
     // seed + doubling walk across the range + regula falsi + final re-evaluation
     int walk = 0;
@@ -539,6 +601,7 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_e
 }
 
 fr3d_status fixed_search(fr3d_ctx* c, Lane& L, double alpha) {
+  L.kmax = 0;
   Ctrl v = ctrl_base(c, L);
   v.state = ST_FIXED;
   v.t = std::log10(alpha);
@@ -681,6 +744,7 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->mu = 0.0;
   o->use_predictor = 0;
   o->seed_walk = 0.25;
+  o->candidates = 0;
 }
 
 const char* fr3d_status_string(fr3d_status s) {

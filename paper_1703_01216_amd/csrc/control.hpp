@@ -23,6 +23,14 @@
 // sign change with steps walk, 2 walk, 4 walk, ... (NOROOT at a range end),
 // then regula falsi on g = r/T - 1 inside the bracket with the Illinois
 // modification (the value kept at an end that survives two steps is halved).
+// K-candidate search: each step evaluates K alphas at once (the pass kernels
+// take the candidate from the grid), step 1 at K points from lo to hi, later
+// steps at the K interior points of the bracket (spaced (b - a)/(K + 1)).
+// The candidate closest to the target among those within tol is accepted;
+// otherwise (step 1) NOROOT_HIGH / NOROOT_LOW as in the plain search, and the
+// bracket becomes [point before, first point with rho >= 0].  After max_steps
+// steps the answer is b (MAXITER).  The answer is then evaluated once more
+// on its own, which writes zeta and the final norms.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,7 +49,11 @@ enum : int32_t {
   ST_WALK = 7,    // walking from the seed toward the sign change
   ST_FALSI = 8,   // regula falsi inside the bracket
   ST_DONE = 9,
+  ST_KARY = 10,   // evaluating K candidates
+  ST_KFINAL = 11, // evaluating the answer of the K-candidate search
 };
+
+constexpr int KMAX = 16;  // candidates per step of the K-candidate search
 
 enum : int32_t { F_NOROOT_HIGH = 1, F_NOROOT_LOW = 2, F_MAXITER = 4, F_NAN = 8, F_PRED_FALLBACK = 16 };
 
@@ -59,6 +71,10 @@ struct Ctrl {
   double ga, gb;     // r/T - 1 at the bracket ends (seeded search)
   double prev_t, prev_g, wstep;
   int32_t side, up;
+  // K-candidate search
+  int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer
+  double ct[KMAX];          // log10 alpha of each candidate
+  double ca[KMAX];          // filter alpha of each candidate
 };
 
 __device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {
@@ -70,6 +86,69 @@ __device__ __forceinline__ void ctrl_finish(Ctrl* c, int32_t flags) {
   c->flags |= flags;
   c->state = ST_DONE;
   c->active = 0;
+}
+
+// Candidates of the next step of the K-candidate search (steps done so far
+// in c->steps; bracket [a, b] after the first step).
+__device__ inline void ctrl_kary_points(Ctrl* c) {
+  const int K = c->kmax;
+  for (int j = 0; j < K; ++j) {
+    const double t = c->steps == 0 ? c->lo + j * (c->hi - c->lo) / (K - 1) : c->a + (j + 1) * (c->b - c->a) / (K + 1);
+    c->ct[j] = t;
+    c->ca[j] = pow(10.0, t) * c->a_scale;
+  }
+  c->kc = K;
+}
+
+__device__ inline void ctrl_kary_answer(Ctrl* c, double t, int32_t flags) {
+  c->pend = flags;
+  c->kc = 0;
+  c->state = ST_KFINAL;
+  ctrl_set_t(c, t);
+}
+
+// Advance after a K-candidate step with ||r||^2 = r2[j], ||zeta||^2 = z2[j].
+__device__ inline void ctrl_advance_k(Ctrl* c, const double* r2, const double* z2) {
+  const int K = c->kc;
+  c->n_evals += K;
+  double rho[KMAX];
+  int best = -1;
+  double bd = 0.0;
+  for (int j = 0; j < K; ++j) {
+    if (!isfinite(r2[j]) || !isfinite(z2[j])) {
+      c->r2 = r2[j];
+      c->z2 = z2[j];
+      c->t = c->ct[j];
+      ctrl_finish(c, F_NAN);
+      return;
+    }
+    const double r = sqrt(r2[j]), zn = sqrt(z2[j]);
+    const double g = c->tau * c->delta + c->h_op * zn;
+    const double tgt2 = g * g + c->mu * c->mu;
+    rho[j] = r2[j] - tgt2;
+    const double ratio = tgt2 > 0 ? r / sqrt(tgt2) : INFINITY;
+    const double d = fabs(ratio - 1.0);
+    if (d <= c->tol && (best < 0 || d < bd)) { best = j; bd = d; }
+  }
+  const int step = c->steps;
+  c->steps = step + 1;
+  if (best >= 0) { ctrl_kary_answer(c, c->ct[best], 0); return; }
+  int jb = 0;
+  if (step == 0) {
+    if (rho[K - 1] < 0) { ctrl_kary_answer(c, c->hi, F_NOROOT_HIGH); return; }
+    if (rho[0] > 0) { ctrl_kary_answer(c, c->lo, F_NOROOT_LOW); return; }
+    while (rho[jb] < 0) ++jb;  // jb >= 1: rho(lo) <= 0 and rho(lo) = 0 was accepted
+    c->a = c->ct[jb - 1];
+    c->b = c->ct[jb];
+  } else {
+    while (jb < K && rho[jb] < 0) ++jb;
+    const double na = jb == 0 ? c->a : c->ct[jb - 1];
+    const double nb = jb == K ? c->b : c->ct[jb];
+    c->a = na;
+    c->b = nb;
+  }
+  if (c->steps >= c->max_steps) { ctrl_kary_answer(c, c->b, F_MAXITER); return; }
+  ctrl_kary_points(c);
 }
 
 // Advance after an evaluation at c->t with ||r||^2 = r2 and ||zeta||^2 = z2.
@@ -117,6 +196,9 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
       return;
     case ST_FINAL:
       ctrl_finish(c, F_MAXITER);
+      return;
+    case ST_KFINAL:
+      ctrl_finish(c, c->pend);
       return;
     case ST_SEED:
     case ST_WALK: {

@@ -78,7 +78,23 @@ struct InvArgs {
   const double2* oct;
   Ctrl* ctrl;               // null for the forward operator (no search)
   double2* norm_part;       // [x-pass workgroups] (||r||^2, ||zeta||^2) partials
+  // K-candidate step (kmode = 1): candidate j filters with ctrl->ca[j] and
+  // works in its own slices W1 + j w1_stride, W2 + j w2_stride and
+  // norm_part + j norm_stride; zeta is not written.  The passes of a
+  // K-candidate step run only while the search is in that state, the passes
+  // of a single evaluation only while it is not.
+  int kmode;
+  int kmax;                 // K (grid extent over candidates)
+  int kb;                   // candidates per z-pass workgroup
+  long long w1_stride, w2_stride, norm_stride;
 };
+
+// Whether an inverse-pass kernel of this launch has nothing to do.
+__device__ __forceinline__ bool inv_idle(const InvArgs& a) {
+  if (!a.ctrl) return false;
+  if (!a.ctrl->active) return true;
+  return (a.ctrl->state == ST_KARY) != (a.kmode != 0);
+}
 
 // ------------------------------------------------------------------ host launchers
 // Stream and, when timing, the event pair recorded at the pass kernel's start
@@ -99,7 +115,9 @@ hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs&
 // mode 1: kernel (full input, octant output)
 template <typename T>
 hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a, const c2<T>* tw, const Launch& L);
-// mode 0: Tikhonov filter (u^, r^); 1: multiply by k^ (forward operator)
+// mode 0: Tikhonov filter (u^, r^); 1: multiply by k^ (forward operator).
+// With a.kmode the z, y and x passes cover a.kmax candidates (a grid
+// dimension) and the x pass is followed by the K-way norm kernel.
 template <typename T>
 hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>

@@ -255,7 +255,7 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
   return !(h && tile == t);
 }
 
-template <typename T, int P, int MODE, int SH>
+template <typename T, int P, int MODE, int SH, bool KM>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
   constexpr int C = TileC<T, P, SH>::C;
@@ -268,19 +268,25 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   constexpr bool PAIRED = C <= NT && NT % C == 0 && (P / 2) % (NT / C) == 0;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
-  if (a.ctrl && !a.ctrl->active) return;
+  if (inv_idle(a)) return;
+  // candidates [cb, ce) of a K-candidate step, else the single evaluation
+  int cb = 0, ce = 1;
+  if constexpr (KM) {
+    cb = blockIdx.y * a.kb;
+    ce = min(cb + a.kb, a.ctrl->kc);
+    if (cb >= ce) return;
+  }
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
   int kx, tile;
   if (!xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)) return;
-  const double aa = MODE == 0 ? a.ctrl->alpha_abs : 0.0;
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
   const c2<T>* src = S + (size_t)kx * P * py;
   const double2* oc = a.oct + (size_t)kx * oz * oy;
   // filter of one point: u and r from f^ and the (possibly conjugated) k^
-  auto filt = [&](c2<T> f, double2 kk, c2<T>& u, c2<T>& r) {
+  auto filt = [&](double aa, c2<T> f, double2 kk, c2<T>& u, c2<T>& r) {
     const double fx = (double)f.x, fy = (double)f.y;
     if constexpr (MODE == 0) {
       const double s = kk.x * kk.x + kk.y * kk.y;
@@ -294,17 +300,18 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       r = mk<T>(0, 0);
     }
   };
-  c2<T> r[PE::n];
+  // loads: kept in registers across the candidates
+  constexpr int TPC = PAIRED ? NT / C : 1;         // threads per column
+  constexpr int UPT = PAIRED ? (P / 2) / TPC : 1;  // row pairs per thread
+  constexpr int NF = PAIRED ? UPT : PE::n;
+  c2<T> f0[NF], f1[PAIRED ? UPT : 1];
+  double2 k[NF];
+  double2 kmid = make_double2(0.0, 0.0);
   if constexpr (PAIRED) {
-    constexpr int TPC = NT / C;          // threads per column
-    constexpr int UPT = (P / 2) / TPC;   // row pairs per thread
     const int col = tid % C, j = tid / C;
     const int ky = ky0 + col;
     const bool okc = ky < py;
     const int my = ky <= py / 2 ? ky : py - ky;
-    c2<T> f0[UPT], f1[UPT];
-    double2 k[UPT];
-    double2 kmid = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int p = j + TPC * i;  // rows p and P-p (p = 0: rows 0 and P/2)
@@ -314,23 +321,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       k[i] = okc ? oc[(size_t)p * oy + my] : make_double2(0.0, 0.0);
     }
     if (j == 0 && okc) kmid = oc[(size_t)(P / 2) * oy + my];
-    for (int m = tid; m < P; m += NT) tw[m] = twg[m];
-#pragma unroll
-    for (int i = 0; i < UPT; ++i) {
-      const int p = j + TPC * i;
-      const int r1 = p == 0 ? P / 2 : P - p;
-      c2<T> u0, u1;
-      filt(f0[i], k[i], u0, r[2 * i]);
-      double2 k1 = k[i];
-      if (p == 0) k1 = kmid;
-      else k1.y = -k1.y;  // row P-p > P/2: conj
-      filt(f1[i], k1, u1, r[2 * i + 1]);
-      lds[p * LD + col] = u0;
-      lds[r1 * LD + col] = u1;
-    }
   } else {
-    c2<T> f[PE::n];
-    double2 k[PE::n];
 #pragma unroll
     for (int i = 0; i < PE::n; ++i) {
       const int e = tid + i * NT;
@@ -338,59 +329,79 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const bool ok = PE::ok(e) && ky < py;
       const int mz = kz <= P / 2 ? kz : P - kz;
       const int my = ky <= py / 2 ? ky : py - ky;
-      f[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
+      f0[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
       k[i] = ok ? oc[(size_t)mz * oy + my] : make_double2(0.0, 0.0);
     }
-    for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+  }
+  for (int m = tid; m < P; m += NT) tw[m] = twg[m];
+  for (int cand = cb; cand < ce; ++cand) {
+    const double aa = MODE == 0 ? (KM ? a.ctrl->ca[cand] : a.ctrl->alpha_abs) : 0.0;
+    if (KM && cand > cb) __syncthreads();  // the previous candidate's stores have read the tile
+    c2<T> r[PE::n];
+    if constexpr (PAIRED) {
+      const int col = tid % C, j = tid / C;
 #pragma unroll
-    for (int i = 0; i < PE::n; ++i) {
+      for (int i = 0; i < UPT; ++i) {
+        const int p = j + TPC * i;
+        const int r1 = p == 0 ? P / 2 : P - p;
+        c2<T> u0, u1;
+        filt(aa, f0[i], k[i], u0, r[2 * i]);
+        double2 k1 = k[i];
+        if (p == 0) k1 = kmid;
+        else k1.y = -k1.y;  // row P-p > P/2: conj
+        filt(aa, f1[i], k1, u1, r[2 * i + 1]);
+        lds[p * LD + col] = u0;
+        lds[r1 * LD + col] = u1;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PE::n; ++i) {
+        const int e = tid + i * NT;
+        double2 kk = k[i];
+        if (e / C > P / 2) kk.y = -kk.y;
+        c2<T> u;
+        filt(aa, f0[i], kk, u, r[i]);
+        if (PE::ok(e)) lds[e] = u;
+      }
+    }
+    __syncthreads();
+    tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+    c2<T> uo[PO::n];
+#pragma unroll
+    for (int i = 0; i < PO::n; ++i) {
       const int e = tid + i * NT;
-      double2 kk = k[i];
-      if (e / C > P / 2) kk.y = -kk.y;
-      c2<T> u;
-      filt(f[i], kk, u, r[i]);
-      if (PE::ok(e)) lds[e] = u;
+      uo[i] = PO::ok(e) ? lds[e] : mk<T>(0, 0);
     }
-  }
-  __syncthreads();
-  tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
-  c2<T> uo[PO::n];
+    __syncthreads();
+    if constexpr (PAIRED) {
+      const int col = tid % C, j = tid / C;
 #pragma unroll
-  for (int i = 0; i < PO::n; ++i) {
-    const int e = tid + i * NT;
-    uo[i] = PO::ok(e) ? lds[e] : mk<T>(0, 0);
-  }
-  __syncthreads();
-  if constexpr (PAIRED) {
-    constexpr int TPC = NT / C;
-    constexpr int UPT = (P / 2) / TPC;
-    const int col = tid % C, j = tid / C;
+      for (int i = 0; i < UPT; ++i) {
+        const int p = j + TPC * i;
+        const int r1 = p == 0 ? P / 2 : P - p;
+        lds[p * LD + col] = r[2 * i];
+        lds[r1 * LD + col] = r[2 * i + 1];
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < UPT; ++i) {
-      const int p = j + TPC * i;
-      const int r1 = p == 0 ? P / 2 : P - p;
-      lds[p * LD + col] = r[2 * i];
-      lds[r1 * LD + col] = r[2 * i + 1];
+      for (int i = 0; i < PE::n; ++i) {
+        const int e = tid + i * NT;
+        if (PE::ok(e)) lds[e] = r[i];
+      }
     }
-  } else {
+    __syncthreads();
+    if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+    c4<T>* dst = W1 + (KM ? (size_t)cand * a.w1_stride : 0) + (size_t)kx * NOUT * py;
 #pragma unroll
-    for (int i = 0; i < PE::n; ++i) {
+    for (int i = 0; i < PO::n; ++i) {
       const int e = tid + i * NT;
-      if (PE::ok(e)) lds[e] = r[i];
+      const int z = e / C, ky = ky0 + e % C;
+      if (!PO::ok(e) || ky >= py) continue;
+      const c2<T> w = lds[e];
+      c4<T> v;
+      v.x = uo[i].x; v.y = uo[i].y; v.z = w.x; v.w = w.y;
+      dst[(size_t)z * py + ky] = v;
     }
-  }
-  __syncthreads();
-  if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
-  c4<T>* dst = W1 + (size_t)kx * NOUT * py;
-#pragma unroll
-  for (int i = 0; i < PO::n; ++i) {
-    const int e = tid + i * NT;
-    const int z = e / C, ky = ky0 + e % C;
-    if (!PO::ok(e) || ky >= py) continue;
-    const c2<T> w = lds[e];
-    c4<T> v;
-    v.x = uo[i].x; v.y = uo[i].y; v.z = w.x; v.w = w.y;
-    dst[(size_t)z * py + ky] = v;
   }
 }
 
@@ -407,7 +418,11 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
   using PE = Per<TOT>;
   __shared__ c2<T> lds[NC * LD];
   __shared__ c2<T> tw[P];
-  if (a.ctrl && !a.ctrl->active) return;
+  if (inv_idle(a)) return;
+  const int cand = a.kmode ? (int)blockIdx.y : 0;  // candidate of a K-candidate step
+  if (a.kmode && cand >= a.ctrl->kc) return;
+  W1 += (size_t)cand * a.w1_stride;
+  W2 += (size_t)cand * a.w2_stride;
   const int tid = threadIdx.x;
   const long long nrows = (long long)a.kx_n * a.nz;
   const long long row0 = (long long)blockIdx.x * C;
@@ -460,7 +475,10 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double red[NT / 64];
-  if (a.ctrl && !a.ctrl->active) return;
+  if (inv_idle(a)) return;
+  const int cand = a.kmode ? (int)blockIdx.z : 0;  // candidate of a K-candidate step
+  if (a.kmode && cand >= a.ctrl->kc) return;
+  W2 += (size_t)cand * a.w2_stride;
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
   const int y0 = blockIdx.x * C;
@@ -493,7 +511,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
     const int col = e / NOUT, x = e % NOUT;
     const c2<T> u = lds[x * LD + col];
     const T zeta = u.x * sc, res = u.y * sc;
-    dst[e] = zeta;
+    if (!a.kmode) dst[e] = zeta;
     zz += (double)zeta * zeta;
     rr += (double)res * res;
   }
@@ -501,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     const double sz = block_sum<NT>(zz, red);
     const double sr = block_sum<NT>(rr, red);
-    if (tid == 0) a.norm_part[bid] = make_double2(sr, sz);
+    if (tid == 0) a.norm_part[(size_t)cand * a.norm_stride + bid] = make_double2(sr, sz);
   }
 }
 
@@ -509,7 +527,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
 // then one step of the alpha search.
 static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
   __shared__ double red[NT / 64];
-  if (!a.ctrl->active) return;
+  if (inv_idle(a)) return;
   double pr = 0.0, pz = 0.0;
   for (int k = threadIdx.x; k < nblk; k += NT) {
     const double2 v = a.norm_part[k];
@@ -519,6 +537,30 @@ static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
   const double tr = block_sum<NT>(pr, red);
   const double tz = block_sum<NT>(pz, red);
   if (threadIdx.x == 0) ctrl_advance(a.ctrl, tr, tz);
+}
+
+// The same for the kc candidates of a K-candidate step: wave w sums the
+// partials of candidates w, w + 4, ... in a fixed order, then one step of
+// the K-candidate search.
+static __global__ __launch_bounds__(NT) void k_norm_final_k(InvArgs a, int nblk) {
+  __shared__ double r2[KMAX], z2[KMAX];
+  if (inv_idle(a)) return;
+  const int kc = a.ctrl->kc;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int j = w; j < kc; j += NT / 64) {
+    const double2* part = a.norm_part + (size_t)j * a.norm_stride;
+    double pr = 0.0, pz = 0.0;
+    for (int k = lane; k < nblk; k += 64) {
+      const double2 v = part[k];
+      pr += v.x;
+      pz += v.y;
+    }
+    pr = wave_sum<double>(pr);
+    pz = wave_sum<double>(pz);
+    if (lane == 0) { r2[j] = pr; z2[j] = pz; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ctrl_advance_k(a.ctrl, r2, z2);
 }
 
 // Radial energies and predictor features from the z pass's per-workgroup bin
@@ -659,8 +701,13 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
     const long long ntile = cdiv(a.py, C);                                                                       \
     const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
     dim3 g(16 * cdiv(npairs, 8));                                                                                \
-    if (mode != 0) return sh == 1 ? go(k_iz<T, p, 1, s1>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0>, g, L, S, W1, a, tw); \
-    return sh == 1 ? go(k_iz<T, p, 0, s1>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0>, g, L, S, W1, a, tw);       \
+    if (mode != 0)                                                                                               \
+      return sh == 1 ? go(k_iz<T, p, 1, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0, false>, g, L, S, W1, a, tw); \
+    if (a.kmode) {                                                                                               \
+      g.y = cdiv(a.kmax, a.kb);                                                                                  \
+      return sh == 1 ? go(k_iz<T, p, 0, s1, true>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0, true>, g, L, S, W1, a, tw); \
+    }                                                                                                            \
+    return sh == 1 ? go(k_iz<T, p, 0, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0, false>, g, L, S, W1, a, tw); \
   }
     FR3D_SIZES(X)
 #undef X
@@ -678,7 +725,7 @@ hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const 
     constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
     const int sh = eff_sh<p>(L.sh);                                                                              \
     const int C = sh == 2 ? TileC<T, p, s2 + 1>::C : sh == 1 ? TileC<T, p, s1 + 1>::C : TileC<T, p, 1>::C;       \
-    dim3 g(cdiv(nrows, C));                                                                                      \
+    dim3 g(cdiv(nrows, C), a.kmode ? a.kmax : 1);                                                               \
     return FR3D_SH(p, sh, go(k_iy<T, p, 0>, g, L, W1, W2, a, tw), go(k_iy<T, p, s1>, g, L, W1, W2, a, tw),        \
                    go(k_iy<T, p, s2>, g, L, W1, W2, a, tw));                                                     \
   }
@@ -697,11 +744,12 @@ hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a,
     constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
     const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
     const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
-    dim3 g(cdiv(a.ny, C), a.nz);                                                                                 \
+    dim3 g(cdiv(a.ny, C), a.nz, a.kmode ? a.kmax : 1);                                                           \
     if (mode != 0) return sh == 1 ? go(k_ix<T, p, 1, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 1, 0>, g, L, W2, out, a, tw); \
     hipError_t e = sh == 1 ? go(k_ix<T, p, 0, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 0, 0>, g, L, W2, out, a, tw); \
     if (e != hipSuccess) return e;                                                                               \
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                            \
+    if (a.kmode) hipLaunchKernelGGL(k_norm_final_k, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));             \
+    else hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                       \
     return hipGetLastError();                                                                                    \
   }
     FR3D_SIZES(X)

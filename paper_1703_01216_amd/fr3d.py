@@ -47,7 +47,8 @@ class DpOpts(ctypes.Structure):
                 ("max_steps", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("accept_lo", ctypes.c_double), ("accept_hi", ctypes.c_double),
                 ("tau", ctypes.c_double), ("h_op", ctypes.c_double), ("mu", ctypes.c_double),
-                ("use_predictor", ctypes.c_int32), ("seed_walk", ctypes.c_double)]
+                ("use_predictor", ctypes.c_int32), ("seed_walk", ctypes.c_double),
+                ("candidates", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -180,6 +181,8 @@ class Context:
     def _arr(self, t, name):
         if t is None:
             raise ValueError(f"{name} is None")
+        if self.geom is None:
+            raise ValueError("no kernel loaded on this context")
         if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {self.dtype} cuda tensor of shape {self.shape}")
         return ctypes.c_void_p(t.data_ptr())

@@ -1,0 +1,196 @@
+"""GPU checks of the batched forms of the alpha search, through the C-ABI.
+
+* K-candidate search (K alphas per launch set): the device takes the oracle
+  rule's decisions on the FP64 path (same flags, evaluation count and alpha)
+  and writes the oracle's zeta at the answer.
+* Group solve: items of different grid sizes and source sets, scheduled
+  together over several contexts, equal their single-context solves bit for
+  bit, with and without the K-candidate search and recovery.
+* Workload 3 recipe at full size (uneven per-axis sizes from {64, 96, 128,
+  192}, the four source sets q, 16 candidates per step, FP32): every item ends
+  inside the tolerance or with a flag the oracle confirms at the range end,
+  and one sampled item's zeta is checked against the FP64 oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import discrepancy, tikhonov
+from oracle.geometry import sample_kernel
+from paper_1703_01216_amd import inputs
+
+from gpu_helpers import geom, instance, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fr3d():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_01216_amd import fr3d as m
+    return m
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("K,delta_rel,kw", [
+    (16, 0.02, {}),
+    (5, 0.01, {}),
+    (2, 0.05, {}),
+    (16, 0.03, {"tol": 0.0, "max_steps": 2}),     # MAXITER: answer b
+    (16, 0.9, {}),                                 # no root below hi
+    (8, 1e-9, {}),                                 # no root above lo
+])
+def test_kary_matches_rule_fp64(fr3d, K, delta_rel, kw):
+    g = geom(16, 12, 8)
+    d = instance(g, 81, delta_rel)
+    say(f"[kary fp64] K={K} delta_rel={delta_rel} {kw}")
+    c = fr3d.Context()
+    c.load_kernel(16, 12, 8, precision=64)
+    F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    rep = c.solve_discrepancy(z, candidates=K, **kw)
+    khat = np.fft.fftn(sample_kernel(g))
+
+    def ev(a):
+        o = tikhonov.solve_spectral(g, khat, d["F"], a)
+        return o["r_norm"], o["zeta_norm"]
+    ref = discrepancy.kary(ev, d["delta"], K=K, **kw)
+    assert rep["flags"] == ref["flags"]
+    assert rep["n_evals"] == ref["n_evals"]
+    assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    o = tikhonov.solve_spectral(g, khat, d["F"], ref["alpha"])
+    assert rel_l2(host(z), o["zeta"]) < 1e-11
+    assert rep["residual"] == pytest.approx(o["r_norm"], rel=1e-11)
+    if ref["flags"] == 0:
+        assert abs(rep["residual"] / d["delta"] - 1) <= kw.get("tol", 1e-3) + 1e-9
+
+
+def test_kary_options_rejected(fr3d):
+    c = fr3d.Context()
+    c.load_kernel(8, 8, 8, precision=32)
+    F = torch.ones((8, 8, 8), dtype=torch.float32, device="cuda")
+    c.set_data(F, 0.1)
+    z = torch.empty_like(F)
+    for kw in ({"candidates": 1}, {"candidates": 17}, {"candidates": 4, "max_steps": 0}):
+        with pytest.raises(fr3d.Fr3dError) as ei:
+            c.solve_discrepancy(z, **kw)
+        assert ei.value.status == fr3d.E_INVALID
+
+
+GROUP = [((16, 24, 32), 0), ((24, 16, 16), 1), ((32, 32, 24), 2), ((16, 24, 32), 3), ((24, 16, 16), 1)]
+
+
+@pytest.mark.parametrize("K", [0, 16])
+def test_group_equals_single(fr3d, K):
+    say(f"[group] K={K}")
+    ctxs, Fs, deltas, V0s, keyed = [], [], [], [], {}
+    for i, (shape, q) in enumerate(GROUP):
+        nz, ny, nx = shape
+        if (shape, q) not in keyed:
+            c = fr3d.Context()
+            c.load_kernel(nx, ny, nz, q=q, precision=32)
+            c.set_lanes(2)
+            V = torch.empty(shape, dtype=torch.float32, device="cuda")
+            c.source_potential(V)
+            keyed[(shape, q)] = (c, V)
+        c, V = keyed[(shape, q)]
+        d = instance(geom(nx, ny, nz, q=q), 90 + i, (0.01, 0.03, 0.05)[i % 3])
+        ctxs.append(c)
+        V0s.append(V)
+        Fs.append(torch.tensor(d["F"], dtype=torch.float32, device="cuda"))
+        deltas.append(d["delta"])
+    single = []
+    for c, F, dl, V in zip(ctxs, Fs, deltas, V0s):
+        z = torch.empty_like(F)
+        c.set_data(F, dl)
+        rep = c.solve_discrepancy(z, candidates=K)
+        cc = torch.empty_like(F)
+        rep["n_clamped"] = c.recover_c(z, V, 1.0, cc)
+        single.append((rep, z, cc))
+    zs = [torch.empty_like(F) for F in Fs]
+    cs = [torch.empty_like(F) for F in Fs]
+    reps = fr3d.solve_group(ctxs, Fs, deltas, zs, V0_list=V0s, c0=1.0, c_list=cs, candidates=K)
+    torch.cuda.synchronize()
+    for (r1, z1, c1), r2, z2, c2 in zip(single, reps, zs, cs):
+        assert np.array_equal(host(z1), host(z2))
+        assert np.array_equal(host(c1), host(c2))
+        for k in ("alpha", "residual", "zeta_norm", "n_evals", "flags", "n_clamped"):
+            assert r1[k] == r2[k]
+    assert fr3d.solve_group([], [], [], []) == []
+
+
+def test_group_errors(fr3d):
+    c = fr3d.Context()
+    c.load_kernel(8, 8, 8, precision=32)
+    F = torch.ones((8, 8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(fr3d.Fr3dError) as ei:
+        fr3d.solve_group([c], [F], [-1.0], [torch.empty_like(F)])
+    assert ei.value.status == fr3d.E_INVALID
+    c2 = fr3d.Context()  # no kernel loaded
+    with pytest.raises(ValueError):
+        fr3d.solve_group([c, c2], [F, F], [0.1, 0.1], [torch.empty_like(F)] * 2)
+
+
+def test_workload3_full_size(fr3d):
+    """Two instances of the workload-3 recipe, each under all four source sets."""
+    items, ctxs, Fs, deltas, zs = [], [], [], [], []
+    for i in range(2):
+        r = inputs.workload_instance(3, i)
+        shape = r["shape"]
+        nz, ny, nx = shape
+        for q in r["q"]:
+            c = fr3d.Context()
+            c.load_kernel(nx, ny, nz, q=q, precision=32)
+            c.apply_tuning()
+            V = torch.empty(shape, dtype=torch.float32, device="cuda")
+            c.source_potential(V)
+            xi = torch.tensor(r["xi"], dtype=torch.float32, device="cuda")
+            F = torch.empty_like(xi)
+            c.apply_operator(xi * V, F)
+            e = torch.tensor(r["noise"], dtype=torch.float32, device="cuda")
+            dl = c.add_noise(F, e, r["delta_rel"])
+            items.append((i, shape, q, r))
+            ctxs.append(c)
+            Fs.append(F)
+            deltas.append(dl)
+            zs.append(torch.empty_like(F))
+            say(f"[workload3] instance {i} shape {shape} q {q} delta_rel {r['delta_rel']:.4f}")
+    reps = fr3d.solve_group(ctxs, Fs, deltas, zs, candidates=16)
+    torch.cuda.synchronize()
+    for (i, shape, q, r), rep, dl in zip(items, reps, deltas):
+        say(f"[workload3] {i} {shape} q={q}: alpha {rep['alpha']:.4e} r/delta {rep['residual'] / dl:.6f} "
+            f"flags {rep['flags']} evals {rep['n_evals']}")
+        if rep["flags"] == 0:
+            assert abs(rep["residual"] / dl - 1) <= 1e-3
+            assert (rep["n_evals"] - 1) % 16 == 0
+        else:
+            # a range end: the residual there is on the flagged side of delta
+            assert rep["flags"] in (discrepancy.NOROOT_LOW, discrepancy.NOROOT_HIGH)
+            if rep["flags"] == discrepancy.NOROOT_LOW:
+                assert rep["alpha"] == pytest.approx(1e-8) and rep["residual"] > dl
+            else:
+                assert rep["alpha"] == 1.0 and rep["residual"] < dl
+    # sampled item against the FP64 oracle at the device's alpha
+    k = 0
+    i, shape, q, r = items[k]
+    nz, ny, nx = shape
+    g = geom(nx, ny, nz, q=q)
+    say(f"[workload3] oracle check of item {k}: {shape} q={q}")
+    khat = np.fft.fftn(sample_kernel(g))
+    o = tikhonov.solve_spectral(g, khat, host(Fs[k]), reps[k]["alpha"])
+    assert rel_l2(host(zs[k]), o["zeta"]) < 1e-5
+    assert reps[k]["residual"] == pytest.approx(o["r_norm"], rel=1e-5)
+    assert math.isfinite(reps[k]["zeta_norm"])
