@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
     ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-lane kernel-timing section (for profiler runs)")
@@ -214,6 +215,7 @@ def main():
     ctx.load_kernel(n, n, n, precision=32)
     tuning = ctx.apply_tuning()
     ctx.set_lanes(args.lanes)
+    ctx.set_graphs(bool(args.graphs))
     modes = args.modes.split(",")
     if "learned" in modes:
         if not os.path.exists(args.predictor):
@@ -230,6 +232,8 @@ def main():
                  "learned_w": fr3d.default_opts(use_predictor=1, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
     for m in modes:
+        if m.startswith("kary"):  # kary<K>: the K-candidate search
+            mode_opts[m] = fr3d.default_opts(candidates=int(m[4:]), **tight)
         if "@" in m:  # learned@<walk>: the learned search with another first walk step
             base, w = m.split("@")
             mode_opts[m] = fr3d.default_opts(use_predictor=1, seed_walk=float(w),
@@ -271,6 +275,7 @@ def main():
                                f"delta 1/3/5%), forward transform + {head} alpha search to |r/delta - 1| <= 1e-3 "
                                f"+ recovery of c per solve, {args.lanes} lanes",
                    "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
+                   "graphs": bool(args.graphs),
                    "tile_shifts": tuning,
                    "modes": results},
         "roofline": roofline,

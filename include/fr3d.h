@@ -241,6 +241,15 @@ fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
  * always use shift 0.  Results do not depend on it; the autotuner picks it. */
 fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
 
+/* With enable = 1, each lane captures its evaluation's launch sequence (the
+ * z, y and x passes and the norm kernel, for K-candidate searches both the
+ * K-candidate step and the single evaluation) into a HIP graph once and
+ * replays it for every later evaluation; the search state and the zeta
+ * pointer live in the lane's control block, so one graph serves every item.
+ * Results are identical either way.  Ignored while timing is on.  A graph
+ * is re-captured after a change of geometry, tile sizes or K. */
+fr3d_status fr3d_set_graphs(fr3d_ctx* ctx, int32_t enable);
+
 /* Per-pass timing with HIP events on the context's stream (for measurement).
  * Pass ids: 0..2 forward x,y,z; 3..5 inverse z,y,x. */
 fr3d_status fr3d_set_timing(fr3d_ctx* ctx, int32_t enable);

@@ -163,6 +163,9 @@ struct Lane {
   double2* knorm = nullptr;     // K-candidate norm partials
   int kcap = 0;                 // candidates the K-candidate workspaces hold
   int kmax = 0;                 // K of the lane's current search (0: not a K-candidate search)
+  hipGraphExec_t gexec = nullptr;  // captured evaluation (valid for gkmax and gsh)
+  int gkmax = -1;
+  int gsh[6] = {0, 0, 0, 0, 0, 0};
   hipEvent_t ev = nullptr;      // completion marker polled by the batch scheduler
   bool has_data = false;
   double delta = 0;
@@ -197,6 +200,8 @@ struct fr3d_ctx {
   long long pred_step = 0;
   // timing
   bool timing = false;
+  bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
+  hipStream_t cap_stream = nullptr; // stream the graphs are captured on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double acc_ms[6] = {0, 0, 0, 0, 0, 0};
   long long cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -248,6 +253,9 @@ void free_lane_geometry(Lane& L) {
   dfree(L.knorm);
   L.kcap = 0;
   L.kmax = 0;
+  if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+  L.gexec = nullptr;
+  L.gkmax = -1;
   L.has_data = false;
 }
 
@@ -510,8 +518,37 @@ fr3d_status set_data_lane(fr3d_ctx* c, Lane& L, const void* F, double delta) {
   return FR3D_OK;
 }
 
-fr3d_status eval_lane(fr3d_ctx* c, Lane& L, void* zeta) {
-  return c->esz == 8 ? inverse<double>(c, L, 0, (double*)zeta) : inverse<float>(c, L, 0, (float*)zeta);
+fr3d_status enqueue_eval(fr3d_ctx* c, Lane& L) {
+  return c->esz == 8 ? inverse<double>(c, L, 0, (double*)nullptr) : inverse<float>(c, L, 0, (float*)nullptr);
+}
+
+// One evaluation of the lane's search (zeta goes where its control block
+// says).  With graphs on, the launch sequence is captured once per lane
+// (kernels only: every argument is fixed for the lane's geometry, the search
+// state lives in the control block) and replayed.
+fr3d_status eval_lane(fr3d_ctx* c, Lane& L) {
+  if (!c->graphs || c->timing) return enqueue_eval(c, L);
+  if (!L.gexec || L.gkmax != L.kmax || std::memcmp(L.gsh, c->tile_sh, sizeof(L.gsh))) {
+    if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+    L.gexec = nullptr;
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipStream_t keep = L.stream;
+    L.stream = c->cap_stream;
+    fr3d_status s = enqueue_eval(c, L);
+    L.stream = keep;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (s) { if (g) (void)hipGraphDestroy(g); return s; }
+    if (e != hipSuccess || !g) return fail(c, FR3D_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&L.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) { L.gexec = nullptr; return fail(c, FR3D_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e2)); }
+    L.gkmax = L.kmax;
+    std::memcpy(L.gsh, c->tile_sh, sizeof(L.gsh));
+  }
+  HIPCHK(c, hipGraphLaunch(L.gexec, L.stream));
+  return FR3D_OK;
 }
 
 Ctrl ctrl_base(fr3d_ctx* c, Lane& L) {
@@ -560,8 +597,9 @@ fr3d_status ensure_kwork(fr3d_ctx* c, Lane& L, int K) {
 
 // Initial control block of a search with options d; with the predictor the
 // first point is written on the device by the network's forward pass.
-fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_evals) {
+fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta, int* max_evals) {
   Ctrl v = ctrl_base(c, L);
+  v.out = zeta;
   v.lo = d.log10_alpha_lo;
   v.hi = d.log10_alpha_hi;
   v.max_steps = d.max_steps;
@@ -600,9 +638,10 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, int* max_e
   return FR3D_OK;
 }
 
-fr3d_status fixed_search(fr3d_ctx* c, Lane& L, double alpha) {
+fr3d_status fixed_search(fr3d_ctx* c, Lane& L, double alpha, void* zeta) {
   L.kmax = 0;
   Ctrl v = ctrl_base(c, L);
+  v.out = zeta;
   v.state = ST_FIXED;
   v.t = std::log10(alpha);
   v.alpha_abs = alpha * v.a_scale;
@@ -634,7 +673,7 @@ int env_int(const char* name, int dflt) {
 }
 
 // Single search on lane 0, chunks of evaluations between host reads.
-fr3d_status run_search(fr3d_ctx* c, int max_evals, void* zeta, fr3d_report* rep) {
+fr3d_status run_search(fr3d_ctx* c, int max_evals, fr3d_report* rep) {
   Lane& L = c->lanes[0];
   const int chunk = std::max(1, env_int("FR3D_EVAL_CHUNK", 4));
   int launched = 0;
@@ -642,7 +681,7 @@ fr3d_status run_search(fr3d_ctx* c, int max_evals, void* zeta, fr3d_report* rep)
   for (;;) {
     const int k = std::min(chunk, max_evals - launched);
     for (int i = 0; i < k; ++i)
-      if ((s = eval_lane(c, L, zeta))) return s;
+      if ((s = eval_lane(c, L))) return s;
     launched += k;
     if ((s = post_ctrl(c, L))) return s;
     HIPCHK(c, hipEventSynchronize(L.ev));
@@ -792,6 +831,7 @@ fr3d_status fr3d_destroy(fr3d_ctx* c) {
     free_lane(L);
   }
   for (auto& e : c->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dfree(c->pred_p);
   dfree(c->pred_m);
   dfree(c->pred_v);
@@ -903,9 +943,9 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* c, double alpha, void* zeta, fr3d_report*
   if (!need(c, true, true)) return FR3D_E_STATE;
   if (!zeta) return fail(c, FR3D_E_INVALID, "zeta is null");
   if (!(alpha > 0) || !std::isfinite(alpha)) return fail(c, FR3D_E_INVALID, "alpha must be finite and > 0");
-  fr3d_status s = fixed_search(c, c->lanes[0], alpha);
+  fr3d_status s = fixed_search(c, c->lanes[0], alpha, zeta);
   if (s) return s;
-  return run_search(c, 1, zeta, rep);
+  return run_search(c, 1, rep);
 }
 
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zeta, fr3d_report* rep) {
@@ -916,8 +956,8 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
   fr3d_status s = check_opts(c, o, &d);
   if (s) return s;
   int max_evals = 0;
-  if ((s = start_search(c, c->lanes[0], d, &max_evals))) return s;
-  return run_search(c, max_evals, zeta, rep);
+  if ((s = start_search(c, c->lanes[0], d, zeta, &max_evals))) return s;
+  return run_search(c, max_evals, rep);
 }
 
 }  // extern "C"
@@ -978,8 +1018,8 @@ fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_d
           s = fail(c, FR3D_E_DEVICE, "feature copy");
           break;
         }
-        if ((s = start_search(c, L, d, &limit[l]))) break;
-        if ((s = eval_lane(c, L, it.zetas[i]))) break;
+        if ((s = start_search(c, L, d, it.zetas[i], &limit[l]))) break;
+        if ((s = eval_lane(c, L))) break;
         launched[l] = 1;
         if ((s = post_ctrl(c, L))) break;
         state[l] = SEARCH;
@@ -994,7 +1034,7 @@ fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_d
       const int i = item[l];
       if (state[l] == SEARCH) {
         if (L.ctrl_host->active && launched[l] < limit[l]) {
-          if ((s = eval_lane(c, L, it.zetas[i]))) break;
+          if ((s = eval_lane(c, L))) break;
           launched[l] += 1;
           if ((s = post_ctrl(c, L))) break;
           continue;
@@ -1243,6 +1283,12 @@ fr3d_status fr3d_set_tile(fr3d_ctx* c, int32_t pass, int32_t shift) {
   const int maxsh = (pass == 0 || pass == 1 || pass == 4) ? 2 : 1;
   if (shift < 0 || shift > maxsh) return fail(c, FR3D_E_INVALID, "tile shift of pass %d must be in [0, %d]", pass, maxsh);
   c->tile_sh[pass] = shift;
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_set_graphs(fr3d_ctx* c, int32_t enable) {
+  if (!c) return FR3D_E_INVALID;
+  c->graphs = enable != 0;
   return FR3D_OK;
 }
 

@@ -75,6 +75,7 @@ struct Ctrl {
   int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer
   double ct[KMAX];          // log10 alpha of each candidate
   double ca[KMAX];          // filter alpha of each candidate
+  void* out;                // zeta of the search (device, nz*ny*nx), written by the x pass
 };
 
 __device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {

@@ -505,6 +505,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
   const T sc = (T)a.scale;
   double zz = 0.0, rr = 0.0;
+  if (a.ctrl) out = (T*)a.ctrl->out;  // a search writes the zeta its control block names
   T* dst = out + ((size_t)z * ny + y0) * NOUT;
   const int rows = min(C, ny - y0);
   for (int e = tid; e < rows * NOUT; e += NT) {

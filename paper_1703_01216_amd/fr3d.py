@@ -26,7 +26,7 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_status_string": (ctypes.c_char_p, [I32]),
         "fr3d_last_error": (ctypes.c_char_p, [P]),
         "fr3d_set_lanes": (I32, [P, I32]),
+        "fr3d_set_graphs": (I32, [P, I32]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
         "fr3d_solve_group": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
@@ -252,6 +253,9 @@ class Context:
         d = ctypes.c_double()
         self._chk(self._lib.fr3d_get_smax(self._ctx, ctypes.byref(d)))
         return d.value
+
+    def set_graphs(self, on: bool):
+        self._chk(self._lib.fr3d_set_graphs(self._ctx, 1 if on else 0))
 
     def set_lanes(self, lanes: int):
         self._chk(self._lib.fr3d_set_lanes(self._ctx, int(lanes)))

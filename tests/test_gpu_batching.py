@@ -194,3 +194,47 @@ def test_workload3_full_size(fr3d):
     assert rel_l2(host(zs[k]), o["zeta"]) < 1e-5
     assert reps[k]["residual"] == pytest.approx(o["r_norm"], rel=1e-5)
     assert math.isfinite(reps[k]["zeta_norm"])
+
+
+@pytest.mark.parametrize("K,pred", [(0, False), (16, False), (0, True)])
+def test_graph_replays_equal_eager(fr3d, K, pred):
+    """The captured evaluation, replayed many times with eager work and
+    synchronisations between replays, gives the eager results bit for bit."""
+    import os
+    say(f"[graphs] K={K} predictor={pred}")
+    g = geom(16, 24, 32)
+    items = [instance(g, 120 + i, (0.01, 0.03, 0.05)[i % 3]) for i in range(5)]
+    Fs = [torch.tensor(d["F"], dtype=torch.float32, device="cuda") for d in items]
+    deltas = [d["delta"] for d in items]
+    c = fr3d.Context()
+    c.load_kernel(16, 24, 32, precision=32)
+    kw = {"candidates": K}
+    if pred:
+        c.predictor_load(os.path.join(os.path.dirname(fr3d.__file__), "data", "predictor.bin"))
+        kw = {"use_predictor": 1}
+    c.set_lanes(3)
+    ref_z = [torch.empty_like(F) for F in Fs]
+    ref = c.solve_batch(Fs, deltas, ref_z, **kw)
+    single = []
+    for F, dl in zip(Fs, deltas):
+        z = torch.empty_like(F)
+        c.set_data(F, dl)
+        single.append((c.solve_discrepancy(z, **kw), z))
+    c.set_graphs(True)
+    for rnd in range(3):
+        zs = [torch.empty_like(F) for F in Fs]
+        reps = c.solve_batch(Fs, deltas, zs, **kw)
+        torch.cuda.synchronize()
+        for r1, z1, r2, z2 in zip(ref, ref_z, reps, zs):
+            assert np.array_equal(host(z1), host(z2)), rnd
+            for k in ("alpha", "residual", "zeta_norm", "n_evals", "flags"):
+                assert r1[k] == r2[k]
+        for (r1, z1), F, dl in zip(single, Fs, deltas):
+            _ = (F * 2.0).sum().item()   # eager work between replays
+            z = torch.empty_like(F)
+            c.set_data(F, dl)
+            r2 = c.solve_discrepancy(z, **kw)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(z1), host(z)), rnd
+            assert r1["alpha"] == r2["alpha"] and r1["n_evals"] == r2["n_evals"]
+    c.set_graphs(False)
