@@ -107,6 +107,57 @@ def cpu_baseline(n, mean_evals, n_sample_evals=3):
                       f"the GPU learned path's mean {mean_evals:.2f} evaluations per solve"}
 
 
+def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, modes=("kary16", "bisection")):
+    """Batched solves of the uneven-size workload: n_inst instances (each axis
+    from {64, 96, 128, 192}), each under the four source sets q (one context
+    and stream per (shape, q)), all scheduled together by the group solver;
+    K-candidate search (16 alphas per step) and bisection, both to 1e-3."""
+    from paper_1703_01216_amd import inputs
+    tight = dict(tol=1e-3, accept_lo=1 - 1e-3, accept_hi=1 + 1e-3)
+    ctxs, Fs, deltas, shapes = [], [], [], []
+    for i in range(n_inst):
+        r = inputs.workload_params(3, i)
+        shape = r["shape"]
+        nz, ny, nx = shape
+        for q in r["q"]:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                c = fr3d.Context(0, stream=st)
+                c.load_kernel(nx, ny, nz, q=q, precision=32)
+                c.apply_tuning()
+                c.set_graphs(graphs)
+                V = torch.empty(shape, dtype=torch.float32, device="cuda")
+                c.source_potential(V)
+                xi = inputs.xi_torch(shape, r["inclusions"])
+                F = torch.empty_like(xi)
+                c.apply_operator(xi * V, F)
+                e = inputs.noise_torch(shape, r["seed"])
+                deltas.append(c.add_noise(F, e, r["delta_rel"]))
+            ctxs.append(c)
+            Fs.append(F)
+            shapes.append(shape)
+    torch.cuda.synchronize()
+    out = {"instances": n_inst, "items": len(Fs), "shapes": sorted(set(shapes)), "graphs": graphs}
+    for m in modes:
+        o = fr3d.default_opts(candidates=int(m[4:]), **tight) if m.startswith("kary") else fr3d.default_opts(**tight)
+        zs = [torch.empty_like(F) for F in Fs]
+        for _ in range(warmup):
+            fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evals = []
+        for _ in range(steps):
+            reps = fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
+            evals += [r["n_evals"] for r in reps]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[m] = {"solves_per_s": len(Fs) * steps / el, "mean_evals": sum(evals) / len(evals),
+                  "alpha_evals_per_s": sum(evals) / el}
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     """Plain device-to-device copy of a 1 GiB buffer (read + write = 2 GiB per
     copy): the practical HBM ceiling and the calibration kernel for counters."""
@@ -190,7 +241,8 @@ def main():
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
-    ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w")
+    ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w,kary16")
+    ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-lane kernel-timing section (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -291,6 +343,11 @@ def main():
     if "learned_w" in results and "bisection_w" in results:
         out["config"]["speedup_learned_vs_bisection_tol_0.1"] = (
             results["learned_w"]["solves_per_s"] / results["bisection_w"]["solves_per_s"])
+    if args.w3 > 0:
+        del Fs, V0
+        torch.cuda.empty_cache()
+        out["config"]["workload3"] = workload3_section(torch, fr3d, n_inst=args.w3, graphs=bool(args.graphs))
+        print(f"[bench] workload3: {out['config']['workload3']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, H["mean_evals"])
     print(json.dumps(out))

@@ -127,13 +127,20 @@ def noise(shape, seed):
 
 
 def workload_params(cfg: int, index: int):
-    """Recipe of workload 5's training/inference instances without evaluating
-    any field: dict(shape, inclusions, delta_rel, q, seed).  Grid extent
-    n ~ U{64, 96, 128} (cubic), q ~ U{0..3}, delta_rel ~ U[0.5%, 5%]."""
-    if cfg != 5:
-        raise ValueError("parameter-only recipes exist for workload 5")
+    """Recipe of a workload-3 or workload-5 instance without evaluating any
+    field: dict(shape, inclusions, delta_rel, q, seed), the same draws as
+    workload_instance.  Workload 5: grid extent n ~ U{64, 96, 128} (cubic),
+    q ~ U{0..3}, delta_rel ~ U[0.5%, 5%].  Workload 3: each axis ~ U{64, 96,
+    128, 192}, q = all of 0..3, delta_rel ~ U[0.5%, 5%]."""
+    if cfg not in (3, 5):
+        raise ValueError("parameter-only recipes exist for workloads 3 and 5")
     seed = instance_seed(cfg, index)
     g = rng(seed + 13)
+    if cfg == 3:
+        shape = tuple(int(g.choice((64, 96, 128, 192))) for _ in range(3))
+        delta_rel = float(g.uniform(0.005, 0.05))
+        return dict(shape=shape, inclusions=inclusion_params(shape, seed), delta_rel=delta_rel, q=[0, 1, 2, 3],
+                    seed=seed)
     m = int(g.choice((64, 96, 128)))
     shape = (m, m, m)
     delta_rel = float(g.uniform(0.005, 0.05))
