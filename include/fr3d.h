@@ -237,8 +237,10 @@ fr3d_status fr3d_predictor_save(fr3d_ctx* ctx, const char* path);
 fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
 
 /* Tile size of a pass (ids as for timing): shift 0 = a 32 KiB LDS tile of
- * pencils, 1 = half, 2 = quarter (row passes 0, 1, 4 only); lengths below 64
- * always use shift 0.  Results do not depend on it; the autotuner picks it. */
+ * pencils, 1 = half, 2 = quarter (row passes 0, 1, 4); for the inverse z
+ * pass (3) shift 2 is the half tile of ky columns with u^ and r^ transformed
+ * together as one 32 KiB tile.  Lengths below 64 always use shift 0.
+ * Results do not depend on it beyond rounding; the autotuner picks it. */
 fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
 
 /* With enable = 1, each lane captures its evaluation's launch sequence (the

@@ -5,7 +5,9 @@
 For each padded geometry and precision, every pass is timed (HIP events at
 the kernel's own start and end) with each of its tile variants -- a 32 KiB
 LDS tile of pencils, half of it, and for the row passes a quarter -- while
-the other passes keep their default, and the fastest variant is kept.  The
+the other passes keep their default, and the fastest variant is kept (the
+inverse z pass also has a joint variant: half the ky columns with u^ and r^
+transformed together).  The
 result is a JSON cache {"<Px>x<Py>x<Pz>/fp<precision>": {pass: shift}} that
 fr3d.Context.apply_tuning() applies; results do not depend on the choice.
 """
@@ -23,7 +25,7 @@ if ROOT not in sys.path:
 
 from paper_1703_01216_amd import fr3d  # noqa: E402
 
-SHIFTS = {"fwd_x": (0, 1, 2), "fwd_y": (0, 1, 2), "fwd_z": (0, 1), "inv_z": (0, 1), "inv_y": (0, 1, 2), "inv_x": (0, 1)}
+SHIFTS = {"fwd_x": (0, 1, 2), "fwd_y": (0, 1, 2), "fwd_z": (0, 1), "inv_z": (0, 1, 2), "inv_y": (0, 1, 2), "inv_x": (0, 1)}
 
 
 def tune_geometry(n, precision=32, reps=20, log=print):

@@ -258,8 +258,11 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
 template <typename T, int P, int MODE, int SH, bool KM>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
-  constexpr int C = TileC<T, P, SH>::C;
-  constexpr int LD = C;
+  // SH = 2 (joint variant, Tikhonov mode): C ky columns of the half tile, u^
+  // and r^ side by side as 2C pencils, transformed together.
+  constexpr bool JOINT = SH == 2 && MODE == 0;
+  constexpr int C = TileC<T, P, JOINT ? 1 : SH>::C;
+  constexpr int LD = JOINT ? 2 * C : C;
   constexpr int NOUT = P / 2;
   constexpr int TOT = C * P;
   constexpr int TOTO = C * NOUT;
@@ -352,6 +355,10 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         filt(aa, f1[i], k1, u1, r[2 * i + 1]);
         lds[p * LD + col] = u0;
         lds[r1 * LD + col] = u1;
+        if constexpr (JOINT) {
+          lds[p * LD + C + col] = r[2 * i];
+          lds[r1 * LD + C + col] = r[2 * i + 1];
+        }
       }
     } else {
 #pragma unroll
@@ -361,10 +368,28 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         if (e / C > P / 2) kk.y = -kk.y;
         c2<T> u;
         filt(aa, f0[i], kk, u, r[i]);
-        if (PE::ok(e)) lds[e] = u;
+        if (PE::ok(e)) {
+          lds[(e / C) * LD + e % C] = u;
+          if constexpr (JOINT) lds[(e / C) * LD + C + e % C] = r[i];
+        }
       }
     }
     __syncthreads();
+    if constexpr (JOINT) {
+      tile_fft<T, P, 2 * C, LD, NT, true, +1>(lds, tw, tid);
+      c4<T>* dst = W1 + (KM ? (size_t)cand * a.w1_stride : 0) + (size_t)kx * NOUT * py;
+#pragma unroll
+      for (int i = 0; i < PO::n; ++i) {
+        const int e = tid + i * NT;
+        const int z = e / C, col = e % C, ky = ky0 + col;
+        if (!PO::ok(e) || ky >= py) continue;
+        const c2<T> u = lds[z * LD + col], w = lds[z * LD + C + col];
+        c4<T> v;
+        v.x = u.x; v.y = u.y; v.z = w.x; v.w = w.y;
+        dst[(size_t)z * py + ky] = v;
+      }
+      continue;
+    }
     tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
     c2<T> uo[PO::n];
 #pragma unroll
@@ -696,9 +721,10 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
-    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
-    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
+    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
+    const int sh0 = eff_sh<p>(L.sh);                                                                             \
+    const int sh = mode != 0 ? (sh0 >= 1 ? 1 : 0) : sh0;  /* 2 = joint u/r variant (filter mode only) */        \
+    const int C = sh >= 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
     const long long ntile = cdiv(a.py, C);                                                                       \
     const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
     dim3 g(16 * cdiv(npairs, 8));                                                                                \
@@ -706,9 +732,11 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
       return sh == 1 ? go(k_iz<T, p, 1, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0, false>, g, L, S, W1, a, tw); \
     if (a.kmode) {                                                                                               \
       g.y = cdiv(a.kmax, a.kb);                                                                                  \
-      return sh == 1 ? go(k_iz<T, p, 0, s1, true>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0, true>, g, L, S, W1, a, tw); \
+      return FR3D_SH(p, sh, go(k_iz<T, p, 0, 0, true>, g, L, S, W1, a, tw), go(k_iz<T, p, 0, s1, true>, g, L, S, W1, a, tw), \
+                     go(k_iz<T, p, 0, s2, true>, g, L, S, W1, a, tw));                                           \
     }                                                                                                            \
-    return sh == 1 ? go(k_iz<T, p, 0, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 0, 0, false>, g, L, S, W1, a, tw); \
+    return FR3D_SH(p, sh, go(k_iz<T, p, 0, 0, false>, g, L, S, W1, a, tw), go(k_iz<T, p, 0, s1, false>, g, L, S, W1, a, tw), \
+                   go(k_iz<T, p, 0, s2, false>, g, L, S, W1, a, tw));                                            \
   }
     FR3D_SIZES(X)
 #undef X

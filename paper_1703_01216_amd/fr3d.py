@@ -319,15 +319,27 @@ class Context:
 
     def apply_tuning(self, path: str = TUNING_PATH):
         """Tile variants from an autotuner cache (JSON {key: {pass name: shift}});
-        returns the applied entry or None when the cache has none for this geometry."""
+        returns the applied entry or None when the cache has nothing for this
+        geometry.  Without an entry for this exact padded box, each pass takes
+        its variant from the cube whose side is that pass's transform length
+        (the pass kernels are compiled per length)."""
         import json
         if not os.path.exists(path):
             return None
-        entry = json.load(open(path)).get(self.tuning_key())
-        if entry:
-            for k, v in entry.items():
-                self.set_tile(PASS_NAMES.index(k), int(v))
-        return entry
+        cache = json.load(open(path))
+        entry = cache.get(self.tuning_key())
+        if not entry:
+            g = self.geom
+            axis = {"fwd_x": 2 * g.nx, "inv_x": 2 * g.nx, "fwd_y": 2 * g.ny, "inv_y": 2 * g.ny,
+                    "fwd_z": 2 * g.nz, "inv_z": 2 * g.nz}
+            entry = {}
+            for name, P in axis.items():
+                cube = cache.get(f"{P}x{P}x{P}/fp{g.precision}")
+                if cube and name in cube:
+                    entry[name] = cube[name]
+        for k, v in entry.items():
+            self.set_tile(PASS_NAMES.index(k), int(v))
+        return entry or None
 
     def set_timing(self, on: bool):
         self._chk(self._lib.fr3d_set_timing(self._ctx, 1 if on else 0))

@@ -297,7 +297,7 @@ def test_tile_variants_same_results(fr3d, precision):
     c = ctx_for(fr3d, g, precision)
     Fd = dev(d["F"], precision)
     outs = []
-    for shifts in ((0, 0, 0, 0, 0, 0), (1, 1, 1, 1, 1, 1), (2, 2, 1, 1, 2, 1)):
+    for shifts in ((0, 0, 0, 0, 0, 0), (1, 1, 1, 1, 1, 1), (2, 2, 1, 2, 2, 1)):
         for p, sh in enumerate(shifts):
             c.set_tile(p, sh)
         c.set_data(Fd, d["delta"])
@@ -311,7 +311,9 @@ def test_tile_variants_same_results(fr3d, precision):
         assert rel_l2(z, outs[0][1]) < 10 * tol
         assert rep["residual"] == pytest.approx(outs[0][2]["residual"], rel=10 * tol)
     with pytest.raises(fr3d.Fr3dError):
-        c.set_tile(3, 2)
+        c.set_tile(3, 3)
+    with pytest.raises(fr3d.Fr3dError):
+        c.set_tile(5, 2)
 
 
 def test_workload1_fp64_against_direct_quadrature(fr3d):
