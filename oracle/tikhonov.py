@@ -20,6 +20,19 @@ any h).  With ``relative=True`` the given alpha is scaled by max |k^|^2
 with C assembled as a matrix and a Cholesky factorisation -- no transform.
 ``solve_spectral`` is the same minimiser through the DFT, where C is diagonal:
 u^ = conj(k^) f^ / (|k^|^2 + alpha_abs).
+
+Other regularising algorithms (Sec. 5 names standard and iterated Tikhonov
+and truncated SVD as the ones applied to the per-frequency systems), on the
+same circulant embedding, with s = |k^|^2 and q = alpha/(s + alpha):
+
+* iterated Tikhonov of order m: u_0 = 0, u_j = argmin ||C u - f||^2 +
+  alpha ||u - u_{j-1}||^2, j = 1..m; spectrally u^ = conj(k^) f^ (1 - q^m)/s
+  = conj(k^) f^ sum_{j<m} q^j / (s + alpha), residual -q^m f^ (m = 1 is
+  Tikhonov).  ``dense_iterated`` runs the m normal-equation solves.
+* truncated SVD with cut alpha: the singular values of C are |k^|, so the
+  modes with s >= alpha are inverted, u^ = conj(k^) f^ / s, and the others
+  dropped; residual 0 on kept modes and -f^ on dropped ones.
+  ``dense_tsvd`` uses the SVD of the assembled matrix.
 """
 from __future__ import annotations
 
@@ -29,6 +42,8 @@ import scipy.linalg
 from .geometry import Geom
 from .operator import pad
 
+TIKHONOV, ITERATED, TSVD = 0, 1, 2
+
 
 def kernel_spectrum(k):
     """k^ = DFT3(k) (FP64), s = |k^|^2 and s_max."""
@@ -37,11 +52,23 @@ def kernel_spectrum(k):
     return khat, s, float(s.max())
 
 
-def spectral_filter(khat, fhat, alpha_abs: float):
+def spectral_filter(khat, fhat, alpha_abs: float, method: int = TIKHONOV, order: int = 1):
     """Minimiser and residual spectra on the whole box for box data with spectrum f^:
-    u^ = conj(k^) f^ / (s + a) and (C u - f)^ = k^ u^ - f^ = -a f^ / (s + a)."""
+    Tikhonov u^ = conj(k^) f^ / (s + a) and (C u - f)^ = k^ u^ - f^ = -a f^ / (s + a);
+    iterated Tikhonov and truncated SVD as in the module docstring."""
     s = (khat * khat.conj()).real
-    return khat.conj() * fhat / (s + alpha_abs), -alpha_abs * fhat / (s + alpha_abs)
+    a = alpha_abs
+    if method == TIKHONOV:
+        return khat.conj() * fhat / (s + a), -a * fhat / (s + a)
+    if method == ITERATED:
+        q = a / (s + a)
+        g = sum(q ** j for j in range(order)) / (s + a)
+        return khat.conj() * fhat * g, -(q ** order) * fhat
+    if method == TSVD:
+        keep = s >= a
+        inv = np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)
+        return khat.conj() * fhat * inv, np.where(keep, 0.0, -1.0) * fhat
+    raise ValueError(f"unknown method {method}")
 
 
 def alpha_abs(khat, alpha: float, relative: bool) -> float:
@@ -55,11 +82,13 @@ def solve_box(khat, f_box, alpha: float, relative: bool = False):
     return np.fft.ifftn(uhat), np.fft.ifftn(rhat)
 
 
-def solve_spectral(g: Geom, khat, F, alpha: float, relative: bool = False):
-    """Tikhonov estimate at alpha; returns zeta on R, r on Y and their norms."""
+def solve_spectral(g: Geom, khat, F, alpha: float, relative: bool = False, method: int = TIKHONOV,
+                   order: int = 1):
+    """Regularised estimate at alpha (Tikhonov unless ``method`` says otherwise);
+    returns zeta on R, r on Y and their norms."""
     a = alpha_abs(khat, alpha, relative)
     fhat = np.fft.fftn(pad(g, np.asarray(F, dtype=np.float64)))
-    uhat, rhat = spectral_filter(khat, fhat, a)
+    uhat, rhat = spectral_filter(khat, fhat, a, method, order)
     zpad = np.fft.ifftn(uhat)
     rpad = np.fft.ifftn(rhat)
     n = g.shape
@@ -98,3 +127,32 @@ def dense_tikhonov(g: Geom, k, F, alpha_abs: float):
     u = u.reshape(k.shape)
     n = g.shape
     return dict(zeta_pad=u, zeta=u[: n[0], : n[1], : n[2]], r=res[: n[0], : n[1], : n[2]], r_full=res)
+
+
+def _restrict(g: Geom, C, u, f, k):
+    res = (C @ u - f).reshape(k.shape)
+    u = u.reshape(k.shape)
+    n = g.shape
+    return dict(zeta_pad=u, zeta=u[: n[0], : n[1], : n[2]], r=res[: n[0], : n[1], : n[2]], r_full=res)
+
+
+def dense_iterated(g: Geom, k, F, alpha_abs: float, order: int):
+    """Iterated Tikhonov by its definition: ``order`` normal-equation solves
+    (C^T C + alpha I) u_j = C^T f + alpha u_{j-1} from u_0 = 0, explicit matrix."""
+    C = circulant_matrix(k)
+    f = pad(g, np.asarray(F, dtype=np.float64)).ravel()
+    fac = scipy.linalg.cho_factor(C.T @ C + alpha_abs * np.eye(C.shape[0]))
+    u = np.zeros_like(f)
+    for _ in range(order):
+        u = scipy.linalg.cho_solve(fac, C.T @ f + alpha_abs * u)
+    return _restrict(g, C, u, f, k)
+
+
+def dense_tsvd(g: Geom, k, F, cut: float):
+    """Truncated SVD of the explicit matrix: singular triplets with sigma^2 >= cut."""
+    C = circulant_matrix(k)
+    f = pad(g, np.asarray(F, dtype=np.float64)).ravel()
+    U, S, Vt = np.linalg.svd(C)
+    keep = S * S >= cut
+    u = Vt[keep].T @ ((U[:, keep].T @ f) / S[keep])
+    return _restrict(g, C, u, f, k)

@@ -214,6 +214,53 @@ def test_dense_normal_equations_equal_spectral(shape, alpha):
     assert sp["imag_max"] < 1e-12 * np.abs(sp["zeta"]).max()
 
 
+@pytest.mark.parametrize("order", [1, 2, 5])
+@pytest.mark.parametrize("shape,alpha", [((4, 4, 4), 1e-2), ((3, 4, 6), 1e-4)])
+def test_iterated_tikhonov_equals_repeated_normal_equations(shape, alpha, order):
+    # Sec. 5: iterated Tikhonov, by its definition (order solves of the
+    # normal equations, each regularised toward the previous iterate).
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz)
+    k = sample_kernel(g)
+    khat = np.fft.fftn(k)
+    F = inputs.rng(17).standard_normal(shape)
+    sp = tikhonov.solve_spectral(g, khat, F, alpha, method=tikhonov.ITERATED, order=order)
+    de = tikhonov.dense_iterated(g, k, F, alpha, order)
+    assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-9 * np.linalg.norm(de["zeta"])
+    assert np.linalg.norm(sp["r"] - de["r"]) < 1e-9 * np.linalg.norm(de["r"])
+    if order == 1:
+        t = tikhonov.solve_spectral(g, khat, F, alpha)
+        assert np.allclose(sp["zeta"], t["zeta"], rtol=0, atol=1e-13 * np.abs(t["zeta"]).max())
+    # more iterations fit the data more closely
+    if order > 1:
+        prev = tikhonov.solve_spectral(g, khat, F, alpha, method=tikhonov.ITERATED, order=order - 1)
+        assert sp["r_full"] < prev["r_full"]
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (3, 4, 6)])
+def test_spectral_tsvd_equals_dense_svd(shape):
+    # Sec. 5: truncated SVD; the singular values of the circulant matrix are |k^|.
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz)
+    k = sample_kernel(g)
+    khat = np.fft.fftn(k)
+    s = np.sort(np.abs(khat).ravel() ** 2)
+    F = inputs.rng(18).standard_normal(shape)
+    C = tikhonov.circulant_matrix(k)
+    sv = np.linalg.svd(C, compute_uv=False)
+    assert np.allclose(np.sort(sv ** 2), s, rtol=1e-10, atol=1e-12 * s[-1])
+    for frac in (0.05, 0.3, 0.7):
+        # a cut half-way between two distinct values of s
+        i = int(frac * len(s))
+        while s[i + 1] - s[i] < 1e-6 * s[-1]:
+            i += 1
+        cut = 0.5 * (s[i] + s[i + 1])
+        sp = tikhonov.solve_spectral(g, khat, F, cut, method=tikhonov.TSVD)
+        de = tikhonov.dense_tsvd(g, k, F, cut)
+        assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-9 * np.linalg.norm(de["zeta"])
+        assert np.linalg.norm(sp["r"] - de["r"]) < 1e-9 * max(np.linalg.norm(de["r"]), 1e-30)
+
+
 @pytest.mark.parametrize("alpha", [1e-10, 1e-7, 1e-4])
 def test_near_exact_recovery_of_band_limited_zeta(alpha):
     # Circulant model, full-box data f = C zeta with zeta^ supported where
