@@ -243,6 +243,17 @@ fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
  * Results do not depend on it beyond rounding; the autotuner picks it. */
 fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
 
+/* Regularising filter of every later evaluation (Sec. 5 names Tikhonov,
+ * iterated Tikhonov and truncated SVD as the algorithms applied): kind 0 =
+ * Tikhonov (default), 1 = iterated Tikhonov of the given order (1..64; the
+ * minimiser of ||A u - F||^2 + alpha ||u - u_prev||^2 applied `order` times
+ * from 0), 2 = truncated SVD of the embedded operator with cut alpha
+ * (spectral modes with |k^|^2 >= alpha inverted, the others dropped).
+ * alpha keeps the units of geom.alpha_relative; the discrepancy searches
+ * apply unchanged (r grows with alpha for all three).  Waits for the
+ * context's streams.  E_INVALID on a bad kind or order. */
+fr3d_status fr3d_set_filter(fr3d_ctx* ctx, int32_t kind, int32_t order);
+
 /* With enable = 1, each lane captures its evaluation's launch sequence (the
  * z, y and x passes and the norm kernel, for K-candidate searches both the
  * K-candidate step and the single evaluation) into a HIP graph once and

@@ -200,6 +200,7 @@ struct fr3d_ctx {
   long long pred_step = 0;
   // timing
   bool timing = false;
+  int filt = 0, forder = 1;          // regularising filter and its order
   bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
   hipStream_t cap_stream = nullptr; // stream the graphs are captured on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -451,6 +452,8 @@ InvArgs inv_args(fr3d_ctx* c, Lane& L, bool search) {
   a.oct = c->oct;
   a.ctrl = search ? L.ctrl : nullptr;
   a.norm_part = L.norm_part;
+  a.filt = c->filt;
+  a.order = c->forder;
   return a;
 }
 
@@ -497,7 +500,7 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     c4<T>* W2k = W1k + (size_t)L.kmax * nB;
     const Launch none{L.stream, nullptr, nullptr, 0};
     Launch lz = none, ly = none, lx = none;
-    lz.sh = c->tile_sh[3];
+    lz.sh = 2;  // joint u/r tile: its loop over candidates keeps the fewest registers live
     ly.sh = c->tile_sh[4];
     lx.sh = c->tile_sh[5];
     LCHK(c, launch_iz<T>(c->pz, 0, b.S, W1k, ak, (const c2<T>*)twz, lz));
@@ -1283,6 +1286,21 @@ fr3d_status fr3d_set_tile(fr3d_ctx* c, int32_t pass, int32_t shift) {
   const int maxsh = (pass == 0 || pass == 1 || pass == 3 || pass == 4) ? 2 : 1;
   if (shift < 0 || shift > maxsh) return fail(c, FR3D_E_INVALID, "tile shift of pass %d must be in [0, %d]", pass, maxsh);
   c->tile_sh[pass] = shift;
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_set_filter(fr3d_ctx* c, int32_t kind, int32_t order) {
+  if (!c) return FR3D_E_INVALID;
+  if (kind < 0 || kind > 2) return fail(c, FR3D_E_INVALID, "filter kind must be 0, 1 or 2");
+  if (kind == 1 && (order < 1 || order > 64)) return fail(c, FR3D_E_INVALID, "iterated Tikhonov order must be in [1, 64]");
+  for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
+  c->filt = kind;
+  c->forder = kind == 1 ? order : 1;
+  // captured evaluations hold the old filter in their arguments
+  for (auto& L : c->lanes) {
+    if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+    L.gexec = nullptr;
+  }
   return FR3D_OK;
 }
 

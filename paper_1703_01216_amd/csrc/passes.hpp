@@ -83,6 +83,8 @@ struct InvArgs {
   // norm_part + j norm_stride; zeta is not written.  The passes of a
   // K-candidate step run only while the search is in that state, the passes
   // of a single evaluation only while it is not.
+  int filt;                 // regularising filter: 0 Tikhonov, 1 iterated Tikhonov, 2 truncated SVD
+  int order;                // order of iterated Tikhonov (>= 1)
   int kmode;
   int kmax;                 // K (grid extent over candidates)
   int kb;                   // candidates per z-pass workgroup

@@ -233,7 +233,11 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 // ============================================================ inverse z pass
 // Reads f^ for C ky-columns of one kx plane and all kz, forms per point (FP64
 // coefficients from the octant of k^, rounded to T):
-//   MODE 0: u^ = conj(k^) f^ / (s + a),  r^ = -a f^ / (s + a)   (Tikhonov, s = |k^|^2)
+//   MODE 0: u^ = conj(k^) f^ g(s),  r^ = -e(s) f^   with s = |k^|^2 and the
+//           regularising filter (Sec. 4-5):
+//             Tikhonov           g = 1/(s + a),                 e = a/(s + a)
+//             iterated, order m  g = sum_{j<m} q^j / (s + a),   e = q^m,  q = a/(s + a)
+//             truncated SVD      g = 1/s, e = 0 if s >= a;      g = 0, e = 1 otherwise
 //   MODE 1: u^ = k^ f^,  r^ = 0                                  (forward operator)
 // transforms u^ and then r^ along z in the same LDS tile and writes z < nz
 // as (u, r) pairs.
@@ -293,10 +297,26 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     const double fx = (double)f.x, fy = (double)f.y;
     if constexpr (MODE == 0) {
       const double s = kk.x * kk.x + kk.y * kk.y;
-      const double d = 1.0 / (s + aa);
-      const double cx = kk.x * d, cy = -kk.y * d;  // conj(k^) / (s + a)
+      double gu, cr;
+      if (a.filt == 0) {
+        gu = 1.0 / (s + aa);
+        cr = -aa * gu;
+      } else if (a.filt == 1) {
+        const double d = 1.0 / (s + aa), q = aa * d;
+        double qp = 1.0, sum = 1.0;
+        for (int j = 1; j < a.order; ++j) {
+          qp *= q;
+          sum += qp;
+        }
+        gu = d * sum;
+        cr = -(qp * q);
+      } else {
+        const bool keep = s >= aa;
+        gu = keep ? 1.0 / s : 0.0;
+        cr = keep ? 0.0 : -1.0;
+      }
+      const double cx = kk.x * gu, cy = -kk.y * gu;  // conj(k^) g
       u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
-      const double cr = -aa * d;
       r = mk<T>((T)(fx * cr), (T)(fy * cr));
     } else {
       u = mk<T>((T)(fx * kk.x - fy * kk.y), (T)(fx * kk.y + fy * kk.x));

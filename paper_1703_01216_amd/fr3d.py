@@ -26,7 +26,7 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_last_error": (ctypes.c_char_p, [P]),
         "fr3d_set_lanes": (I32, [P, I32]),
         "fr3d_set_graphs": (I32, [P, I32]),
+        "fr3d_set_filter": (I32, [P, I32, I32]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
         "fr3d_solve_group": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
@@ -253,6 +254,10 @@ class Context:
         d = ctypes.c_double()
         self._chk(self._lib.fr3d_get_smax(self._ctx, ctypes.byref(d)))
         return d.value
+
+    def set_filter(self, kind: int, order: int = 1):
+        """0 Tikhonov, 1 iterated Tikhonov of the given order, 2 truncated SVD."""
+        self._chk(self._lib.fr3d_set_filter(self._ctx, int(kind), int(order)))
 
     def set_graphs(self, on: bool):
         self._chk(self._lib.fr3d_set_graphs(self._ctx, 1 if on else 0))
