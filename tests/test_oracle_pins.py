@@ -594,3 +594,61 @@ def test_adam_first_step():
 def test_mlp_param_count():
     p = mlp.init_params(0)
     assert sum(v.size for v in p.values()) == 25089
+
+
+# ---------------------------------------------------------------- Algorithm 1 with per-frequency z-systems (Sec. 5)
+
+from oracle import layered  # noqa: E402
+
+
+@pytest.mark.parametrize("shape,kind", [((4, 3, 5), 0), ((3, 4, 4), 1), ((6, 6, 2), 0)])
+def test_layered_forward_equals_direct_quadrature(shape, kind):
+    # Eq. (14)'s systems, assembled from the lateral transform of the kernel,
+    # reproduce the direct quadrature sum of Eq. (8) exactly (no wrap in z).
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz, kind=kind)
+    kt = layered.lateral_kernel_spectrum(g)
+    assert np.abs(kt.imag).max() < 1e-12 * np.abs(kt).max()   # K even in x and y
+    z = inputs.rng(21).standard_normal(shape)
+    assert np.allclose(layered.forward_layered(g, kt, z), forward_direct(g, z), rtol=0,
+                       atol=1e-12 * np.abs(forward_direct(g, z)).max())
+
+
+@pytest.mark.parametrize("method", [tikhonov.TIKHONOV, tikhonov.TSVD])
+@pytest.mark.parametrize("shape", [(2, 2, 3), (3, 2, 2)])
+def test_layered_solve_equals_assembled_operator(shape, method):
+    # The per-frequency regularisation is the regularisation of the whole
+    # (laterally embedded, z-exact) operator: normal equations / SVD of the
+    # explicit matrix give the same estimate and residual.
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz)
+    kt = layered.lateral_kernel_spectrum(g)
+    F = inputs.rng(22).standard_normal(shape)
+    S = np.linalg.svd(layered.assembled_operator(g), compute_uv=False)
+    lam = np.unique(np.round(S * S, 12))
+    alpha = 1e-3 if method == tikhonov.TIKHONOV else 0.5 * (lam[len(lam) // 2] + lam[len(lam) // 2 + 1])
+    sp = layered.solve_layered(g, kt, F, alpha, method)
+    de = layered.dense_layered(g, F, alpha, method)
+    assert np.linalg.norm(sp["zeta"] - de["zeta"]) < 1e-9 * np.linalg.norm(de["zeta"])
+    assert np.linalg.norm(sp["r"] - de["r"]) < 1e-9 * np.linalg.norm(de["r"])
+    assert sp["imag_max"] < 1e-10 * np.abs(sp["zeta"]).max()
+    # singular values of the assembled operator = those of all per-frequency systems
+    Sf = np.sort(sp["singular_values"].ravel())
+    assert np.allclose(np.sort(S)[-len(Sf):], Sf, rtol=1e-9, atol=1e-12 * S.max())
+
+
+def test_layered_filters_and_monotone_residual():
+    g = Geom(8, 8, 6)
+    kt = layered.lateral_kernel_spectrum(g)
+    F = inputs.rng(23).standard_normal(g.shape)
+    prev = -1.0
+    for a in (1e-6, 1e-4, 1e-2, 1.0):
+        o = layered.solve_layered(g, kt, F, a)
+        assert o["r_norm"] > prev
+        prev = o["r_norm"]
+    # iterated Tikhonov of order 1 = Tikhonov; higher order fits more closely
+    o1 = layered.solve_layered(g, kt, F, 1e-3)
+    i1 = layered.solve_layered(g, kt, F, 1e-3, tikhonov.ITERATED, 1)
+    i3 = layered.solve_layered(g, kt, F, 1e-3, tikhonov.ITERATED, 3)
+    assert np.allclose(o1["zeta"], i1["zeta"], rtol=0, atol=1e-12 * np.abs(o1["zeta"]).max())
+    assert i3["r_norm"] < o1["r_norm"]
