@@ -124,6 +124,26 @@ fr3d_status fr3d_set_lanes(fr3d_ctx* ctx, int32_t lanes);
  * set earlier. */
 fr3d_status fr3d_load_kernel(fr3d_ctx* ctx, const fr3d_geom* geom);
 
+/* Algorithm 1 as run in Sec. 5: load the geometry for the lateral 2D
+ * transform and per-frequency dense z-systems of Eq. (14) instead of the 3D
+ * embedding.  Lateral axes are zero-padded to 2n (the exact discrete lateral
+ * convolution); z is not embedded: for every lateral frequency the real
+ * nz x nz matrix A[i][j] = k~(kx, ky; i - j) couples R's layer j with Y's
+ * layer i, k~ being the lateral transform of the kernel samples at the z
+ * offset (D + i - j) h (K is even in x and y, so A is real and shared by
+ * ky and Py - ky).  Each A is factorised once here (one-sided Jacobi SVD in
+ * FP64).  Afterwards set_data, solve_alpha, solve_discrepancy (plain and
+ * K-candidate searches), solve_batch / solve_group, recover_c,
+ * apply_operator (F^ = A zeta^ per frequency) and the filters of
+ * fr3d_set_filter work on this form; one alpha for all frequencies, the
+ * discrepancy on Y's whole footprint.  Not available in this form:
+ * predictor features (use_predictor, get_features, batch features) and the
+ * 3D octant (FR3D_E_STATE).  get_data_spectrum returns the lateral spectrum,
+ * complex T [Px/2+1][nz][Py].  Limits: 1 <= nz <= 60, 2 nx and 2 ny
+ * compiled lengths; nz needs no transform length.  geom as for
+ * fr3d_load_kernel (alpha_relative scales by the largest s^2). */
+fr3d_status fr3d_load_layered(fr3d_ctx* ctx, const fr3d_geom* geom);
+
 /* Set the data F on Y (nz*ny*nx values, device) and the noise level delta >= 0
  * (absolute, ||F - A zeta|| <= delta).  Runs the zero-padded forward
  * transform (Algorithm 1 step 1 for the data) and its radial energy

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfr3d.so")
 
-SOURCES = ["api.hip", "passes_f32.hip", "passes_f64.hip", "mlp.hip"]
+SOURCES = ["api.hip", "passes_f32.hip", "passes_f64.hip", "mlp.hip", "layered.hip"]
 ARCH = "gfx950"
 
 

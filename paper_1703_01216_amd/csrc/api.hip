@@ -26,6 +26,7 @@
 
 #include "../../include/fr3d.h"
 #include "control.hpp"
+#include "layered.hpp"
 #include "mlp.hpp"
 #include "passes.hpp"
 
@@ -182,6 +183,9 @@ struct fr3d_ctx {
   size_t esz = 4;
   double smax = 0;
   double2* oct = nullptr;
+  // per-frequency z-systems (Algorithm 1 as in Sec. 5) instead of the 3D embedding
+  bool layered = false;
+  double *lay_kt = nullptr, *lay_V = nullptr, *lay_lam = nullptr;
   size_t spec_bytes = 0, work_bytes = 0, bins_part_n = 0, norm_part_n = 0;
   std::map<int, void*> tw32, tw64;
   std::vector<Lane> lanes;  // lanes[0] runs on the caller's stream
@@ -303,6 +307,10 @@ fr3d_status alloc_lane_geometry(fr3d_ctx* c, Lane& L) {
 
 void free_geometry(fr3d_ctx* c) {
   dfree(c->oct);
+  dfree(c->lay_kt);
+  dfree(c->lay_V);
+  dfree(c->lay_lam);
+  c->layered = false;
   for (auto& kv : c->tw32) (void)hipFree(kv.second);
   for (auto& kv : c->tw64) (void)hipFree(kv.second);
   c->tw32.clear();
@@ -448,7 +456,8 @@ InvArgs inv_args(fr3d_ctx* c, Lane& L, bool search) {
   InvArgs a{};
   a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
   a.kx_n = c->kxn; a.py = c->py; a.pz = c->pz;
-  a.scale = 1.0 / ((double)c->px * c->py * c->pz);
+  // the per-frequency path inverts a lateral (2D) transform only
+  a.scale = c->layered ? 1.0 / ((double)c->px * c->py) : 1.0 / ((double)c->px * c->py * c->pz);
   a.oct = c->oct;
   a.ctrl = search ? L.ctrl : nullptr;
   a.norm_part = L.norm_part;
@@ -467,9 +476,25 @@ template <typename T> fr3d_status forward_data(fr3d_ctx* c, Lane& L, const T* F)
   Bufs<T> b = bufs<T>(c, L);
   FwdArgs a = fwd_args(c, L, false);
   LCHK(c, launch_fx<T>(c->px, false, F, b.A, a, (const c2<T>*)twx, mkL(c, L, 0)));
+  if (c->layered) {  // lateral transform only: [Kx][nz][Py] into the spectrum buffer
+    LCHK(c, launch_fy<T>(c->py, true, b.A, b.S, a, (const c2<T>*)twy, mkL(c, L, 1)));
+    return FR3D_OK;
+  }
   LCHK(c, launch_fy<T>(c->py, true, b.A, b.B, a, (const c2<T>*)twy, mkL(c, L, 1)));
   LCHK(c, launch_fz<T>(c->pz, 0, b.B, b.S, a, (const c2<T>*)twz, mkL(c, L, 2)));
   return FR3D_OK;
+}
+
+LayArgs lay_args(fr3d_ctx* c) {
+  LayArgs la{};
+  la.M = c->g.nz;
+  la.kxn = c->kxn;
+  la.py = c->py;
+  la.pyh = c->py / 2 + 1;
+  la.kt = c->lay_kt;
+  la.V = c->lay_V;
+  la.lam = c->lay_lam;
+  return la;
 }
 
 template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out) {
@@ -503,11 +528,13 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     lz.sh = 2;  // joint u/r tile: its loop over candidates keeps the fewest registers live
     ly.sh = c->tile_sh[4];
     lx.sh = c->tile_sh[5];
-    LCHK(c, launch_iz<T>(c->pz, 0, b.S, W1k, ak, (const c2<T>*)twz, lz));
+    if (c->layered) LCHK(c, launch_lay_filter<T>(0, b.S, W1k, lay_args(c), ak, lz));
+    else LCHK(c, launch_iz<T>(c->pz, 0, b.S, W1k, ak, (const c2<T>*)twz, lz));
     LCHK(c, launch_iy<T>(c->py, W1k, W2k, ak, (const c2<T>*)twy, ly));
     LCHK(c, launch_ix<T>(c->px, 0, W2k, (T*)nullptr, ak, (const c2<T>*)twx, lx));
   }
-  LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
+  if (c->layered) LCHK(c, launch_lay_filter<T>(mode, b.S, b.W1, lay_args(c), a, mkL(c, L, 3)));
+  else LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
   LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, L, 4)));
   LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, L, 5)));
   return FR3D_OK;
@@ -583,6 +610,8 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
   if (d->use_predictor && !c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  if (d->use_predictor && c->layered)
+    return fail(c, FR3D_E_STATE, "the predictor's features come from the 3D spectrum (not with per-frequency systems)");
   return FR3D_OK;
 }
 
@@ -933,6 +962,75 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   return FR3D_OK;
 }
 
+fr3d_status fr3d_load_layered(fr3d_ctx* c, const fr3d_geom* g) {
+  if (!c) return FR3D_E_INVALID;
+  if (!g) return fail(c, FR3D_E_INVALID, "geom is null");
+  if (g->nx < 2 || g->ny < 2 || g->nz < 1) return fail(c, FR3D_E_INVALID, "need nx, ny >= 2 and nz >= 1");
+  if (g->nz > LAY_MMAX) return fail(c, FR3D_E_INVALID, "nz must be <= %d for the per-frequency systems", LAY_MMAX);
+  if (!supported_length(2 * g->nx) || !supported_length(2 * g->ny))
+    return fail(c, FR3D_E_INVALID, "2n per lateral axis must be one of the compiled lengths (2^a 3^b, <= 512)");
+  if (!(g->h > 0) || !std::isfinite(g->h)) return fail(c, FR3D_E_INVALID, "h must be finite and > 0");
+  if (g->kind != 0 && g->kind != 1) return fail(c, FR3D_E_INVALID, "kind must be 0 or 1");
+  if (g->precision != 32 && g->precision != 64) return fail(c, FR3D_E_INVALID, "precision must be 32 or 64");
+  if (!std::isfinite(g->D)) return fail(c, FR3D_E_INVALID, "D must be finite");
+  if (g->alpha_relative != 0 && g->alpha_relative != 1) return fail(c, FR3D_E_INVALID, "alpha_relative must be 0 or 1");
+  const double D = g->D > 0 ? g->D : (double)gap_default(g->nz, g->q);
+  if (D < g->nz) return fail(c, FR3D_E_INVALID, "D must be >= nz (R and Y disjoint)");
+  HIPCHK(c, hipSetDevice(c->device));
+  for (auto& L : c->lanes) HIPCHK(c, L.stream ? hipStreamSynchronize(L.stream) : hipDeviceSynchronize());
+  free_geometry(c);
+  c->g = *g;
+  c->D = D;
+  c->px = 2 * g->nx; c->py = 2 * g->ny; c->pz = 2 * g->nz;
+  c->kxn = c->px / 2 + 1;
+  c->esz = g->precision == 64 ? 8 : 4;
+  const size_t kxn = c->kxn, M = g->nz, Lz = 2 * M - 1, pyh = c->py / 2 + 1, nf = kxn * pyh;
+  const size_t nA = kxn * g->nz * g->ny, nB = kxn * g->nz * c->py;
+  c->spec_bytes = nB * 2 * c->esz;         // lateral spectrum [Kx][nz][Py]
+  c->work_bytes = (nA + nB) * 4 * c->esz;  // W1 + W2 (pairs) cover A
+  c->bins_part_n = (size_t)kxn * c->py;
+  c->norm_part_n = (size_t)g->nz * g->ny;
+  HIPCHK(c, hipMalloc(&c->lay_kt, nf * Lz * sizeof(double)));
+  HIPCHK(c, hipMalloc(&c->lay_V, nf * M * M * sizeof(double)));
+  HIPCHK(c, hipMalloc(&c->lay_lam, nf * M * sizeof(double)));
+  c->layered = true;
+  fr3d_status st;
+  for (auto& L : c->lanes)
+    if ((st = alloc_lane_geometry(c, L))) return st;
+  Lane& L0 = c->lanes[0];
+  // lateral transform of the kernel at the 2 nz - 1 z offsets (FP64), then the SVDs
+  const size_t nk = kxn * Lz * c->py;
+  double2 *Ak = nullptr, *Bk = nullptr;
+  HIPCHK(c, hipMalloc(&Ak, nk * sizeof(double2)));
+  hipError_t e2 = hipMalloc(&Bk, nk * sizeof(double2));
+  if (e2 != hipSuccess) { (void)hipFree(Ak); return fail(c, FR3D_E_NOMEM, "kernel transform workspace: %s", hipGetErrorString(e2)); }
+  void *twx, *twy;
+  if ((st = get_twiddles(c, c->px, true, &twx)) || (st = get_twiddles(c, c->py, true, &twy))) {
+    (void)hipFree(Ak); (void)hipFree(Bk);
+    return st;
+  }
+  FwdArgs a = fwd_args(c, L0, true);
+  a.nz_in = (int)Lz;
+  a.zlin = 1;
+  const Launch Lk{L0.stream, nullptr, nullptr, 0};
+  LayArgs la = lay_args(c);
+  hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, Lk);
+  if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, Lk);
+  if (le == hipSuccess) le = launch_lay_svd(Bk, la, c->lay_kt, c->lay_V, c->lay_lam, L0.stream);
+  if (le == hipSuccess) le = launch_lay_max(c->lay_lam, (long long)(nf * M), (double*)Ak, L0.scal, L0.stream);
+  if (le == hipSuccess) le = hipMemcpyAsync(L0.scal_host, L0.scal, sizeof(double), hipMemcpyDeviceToHost, L0.stream);
+  if (le == hipSuccess) le = hipStreamSynchronize(L0.stream);
+  (void)hipFree(Ak);
+  (void)hipFree(Bk);
+  if (le != hipSuccess) return fail(c, FR3D_E_DEVICE, "per-frequency systems: %s", hipGetErrorString(le));
+  c->smax = L0.scal_host[0];
+  if (!(c->smax > 0) || !std::isfinite(c->smax)) return fail(c, FR3D_E_DEVICE, "kernel has no energy");
+  const bool dbl = c->esz == 8;
+  if ((st = get_twiddles(c, c->px, dbl, &twx)) || (st = get_twiddles(c, c->py, dbl, &twy))) return st;
+  c->has_kernel = true;
+  return FR3D_OK;
+}
+
 fr3d_status fr3d_set_data(fr3d_ctx* c, const void* F, double delta) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
@@ -1098,6 +1196,7 @@ fr3d_status fr3d_solve_batch(fr3d_ctx* c, int32_t n, const void* const* F, const
   if (!need(c, true, false)) return FR3D_E_STATE;
   if (n < 0 || (n > 0 && (!F || !deltas || !zetas || !reps))) return fail(c, FR3D_E_INVALID, "null batch arrays");
   if (c_out && (!V0 || !(c0 > 0) || !std::isfinite(c0))) return fail(c, FR3D_E_INVALID, "recovery needs V0 and c0 > 0");
+  if (feat_out && c->layered) return fail(c, FR3D_E_STATE, "no features with per-frequency systems");
   fr3d_status s;
   for (int i = 0; i < n; ++i)
     if ((s = check_item(c, i, F[i], deltas[i], zetas[i], c_out != nullptr, V0, c_out ? c_out[i] : nullptr))) return s;
@@ -1250,6 +1349,7 @@ fr3d_status fr3d_add_noise(fr3d_ctx* c, void* F, const void* e, double delta_rel
 fr3d_status fr3d_get_octant(fr3d_ctx* c, void* out, int64_t bytes) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
+  if (c->layered) return fail(c, FR3D_E_STATE, "no 3D kernel spectrum with per-frequency systems");
   const size_t n = (size_t)c->kxn * (c->pz / 2 + 1) * (c->py / 2 + 1) * sizeof(double2);
   if (!out || bytes < (int64_t)n) return fail(c, FR3D_E_INVALID, "need %zu bytes", n);
   HIPCHK(c, hipMemcpyAsync(out, c->oct, n, hipMemcpyDeviceToDevice, c->lanes[0].stream));
@@ -1267,6 +1367,7 @@ fr3d_status fr3d_get_data_spectrum(fr3d_ctx* c, void* out, int64_t bytes) {
 fr3d_status fr3d_get_features(fr3d_ctx* c, float* feat, double* energy) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, true)) return FR3D_E_STATE;
+  if (c->layered) return fail(c, FR3D_E_STATE, "features come from the 3D spectrum (not with per-frequency systems)");
   Lane& L = c->lanes[0];
   if (feat) HIPCHK(c, hipMemcpyAsync(feat, L.feat, 65 * sizeof(float), hipMemcpyDeviceToDevice, L.stream));
   if (energy) HIPCHK(c, hipMemcpyAsync(energy, L.energy, 64 * sizeof(double), hipMemcpyDeviceToDevice, L.stream));

@@ -62,6 +62,7 @@ struct FwdArgs {
   double h, D;
   int nx, ny, nz;     // cell counts
   int kind;
+  int zlin;           // generator mode: plane z samples the z offset z - (nz - 1) (no wrap)
   // energy epilogue
   BinGeom bg;
   double* bins_part;  // [64][z-pass workgroups]

@@ -80,8 +80,8 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       const int yb = y0 + r;
       double v = 0.0;
       int ox, oy, oz;
-      if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) &&
-          wrap_offset(z, a.nz, a.pz, oz)) {
+      const bool zok = a.zlin ? (oz = z - (a.nz - 1), true) : wrap_offset(z, a.nz, a.pz, oz);
+      if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) && zok) {
         v = a.h * a.h * a.h * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.h);
       }
       ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = (T)v;

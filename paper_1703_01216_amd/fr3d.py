@@ -26,7 +26,7 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_set_lanes": (I32, [P, I32]),
         "fr3d_set_graphs": (I32, [P, I32]),
         "fr3d_set_filter": (I32, [P, I32, I32]),
+        "fr3d_load_layered": (I32, [P, ctypes.POINTER(Geom)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
         "fr3d_solve_group": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
@@ -197,6 +198,12 @@ class Context:
     def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0):
         g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative)
         self._chk(self._lib.fr3d_load_kernel(self._ctx, ctypes.byref(g)))
+        self.geom = g
+
+    def load_layered(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0):
+        """Per-frequency z-systems (Algorithm 1 as run in Sec. 5) instead of the 3D embedding."""
+        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative)
+        self._chk(self._lib.fr3d_load_layered(self._ctx, ctypes.byref(g)))
         self.geom = g
 
     def set_data(self, F, delta):
