@@ -158,6 +158,48 @@ def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, mo
     return out
 
 
+def layered_section(torch, fr3d, n=256, nz=51, reps=3):
+    """Algorithm 1 with per-frequency z-systems at the size the paper times
+    (Sec. 6: lateral grid N = 512, M = M' = 51 layers): n x n x nz cells, the
+    lateral axes padded to 2n = 512.  Times the setup (lateral kernel
+    transform + one SVD per distinct system) and whole solves (data
+    transform, discrepancy search to 1e-3 over alpha in [1e-12, 1], inverse)
+    with TSVD -- the paper's best method -- and with Tikhonov; 5% noise."""
+    from paper_1703_01216_amd import inputs
+    shape = (nz, n, n)
+    c = fr3d.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.load_layered(n, n, nz, precision=32)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    V = torch.empty(shape, dtype=torch.float32, device="cuda")
+    c.source_potential(V)
+    seed = inputs.instance_seed(2, 0)
+    xi = inputs.xi_torch(shape, inputs.inclusion_params(shape, seed))
+    F = torch.empty_like(xi)
+    c.apply_operator(xi * V, F)
+    delta = c.add_noise(F, inputs.noise_torch(shape, seed), 0.05)
+    z = torch.empty_like(F)
+    out = {"grid": list(shape), "lateral_padded": 2 * n, "setup_ms": setup * 1e3,
+           "paper": "MATLAB, one core: N = 512, M = M' = 51 solved in under 10 minutes (Sec. 6)"}
+    for name, (kind, order) in (("tsvd", (2, 1)), ("tikhonov", (0, 1))):
+        c.set_filter(kind, order)
+        c.set_data(F, delta)
+        c.solve_discrepancy(z, tol=1e-3, log10_alpha_lo=-12.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.set_data(F, delta)
+            rep = c.solve_discrepancy(z, tol=1e-3, log10_alpha_lo=-12.0)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        out[name] = {"solve_ms": el * 1e3, "n_evals": rep["n_evals"], "flags": rep["flags"],
+                     "alpha": rep["alpha"], "r_over_delta": rep["residual"] / delta}
+    c.close()
+    return out
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     """Plain device-to-device copy of a 1 GiB buffer (read + write = 2 GiB per
     copy): the practical HBM ceiling and the calibration kernel for counters."""
@@ -243,6 +285,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
     ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w,kary16")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
+    ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-lane kernel-timing section (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -348,6 +391,9 @@ def main():
         torch.cuda.empty_cache()
         out["config"]["workload3"] = workload3_section(torch, fr3d, n_inst=args.w3, graphs=bool(args.graphs))
         print(f"[bench] workload3: {out['config']['workload3']}", file=sys.stderr, flush=True)
+    if args.layered:
+        out["config"]["layered"] = layered_section(torch, fr3d)
+        print(f"[bench] layered: {out['config']['layered']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, H["mean_evals"])
     print(json.dumps(out))

@@ -8,7 +8,8 @@ namespace fr3d {
 
 namespace {
 
-constexpr int LNT = 256;  // threads per workgroup
+constexpr int LNT = 256;   // threads per workgroup of the per-evaluation kernels
+constexpr int SNT = 1024;  // threads of the SVD kernel: 16 waves share a round's column pairs
 
 // Round-robin ("circle") pairing of n2 (even) columns: in round r, column 0
 // meets c(0) and column c(p) meets c(n2 - 1 - p), with c(k) = 1 + (k + r) mod (n2 - 1).
@@ -27,23 +28,23 @@ __device__ __forceinline__ void rr_pair(int r, int p, int n2, int& i, int& j) {
 // one-sided Jacobi (Hestenes) rotations on pairs of columns until every pair
 // is orthogonal to 1e-15 relative (at most 40 sweeps); the rotated columns'
 // squared norms are s_k^2 and the accumulated rotations are V.
-__global__ __launch_bounds__(LNT) void k_lay_svd(const double2* __restrict__ Bk, LayArgs la, double* __restrict__ kt,
+__global__ __launch_bounds__(SNT) void k_lay_svd(const double2* __restrict__ Bk, LayArgs la, double* __restrict__ kt,
                                                   double* __restrict__ V, double* __restrict__ lam) {
   __shared__ double As[LAY_MMAX * LAY_MMAX];  // column j at j*M
   __shared__ double Vs[LAY_MMAX * LAY_MMAX];  // column k at k*M
   __shared__ double ktv[2 * LAY_MMAX];
-  __shared__ double offw[LNT / 64];
+  __shared__ double offw[SNT / 64];
   const int M = la.M, L = 2 * M - 1;
   const int f = blockIdx.x;
   const int kx = f / la.pyh, my = f % la.pyh;
   const int tid = threadIdx.x, w = tid / 64, lane = tid % 64;
-  for (int l = tid; l < L; l += LNT) {
+  for (int l = tid; l < L; l += SNT) {
     const double v = Bk[((size_t)kx * L + l) * la.py + my].x;
     ktv[l] = v;
     kt[(size_t)f * L + l] = v;
   }
   __syncthreads();
-  for (int e = tid; e < M * M; e += LNT) {
+  for (int e = tid; e < M * M; e += SNT) {
     const int i = e % M, j = e / M;
     As[e] = ktv[i - j + M - 1];
     Vs[e] = i == j ? 1.0 : 0.0;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(LNT) void k_lay_svd(const double2* __restrict__ Bk,
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0;
     for (int r = 0; r < n2 - 1; ++r) {
-      for (int p = w; p < n2 / 2; p += LNT / 64) {
+      for (int p = w; p < n2 / 2; p += SNT / 64) {
         int i, j;
         rr_pair(r, p, n2, i, j);
         if (i >= M || j >= M) continue;  // the dummy column of an odd M
@@ -82,17 +83,17 @@ __global__ __launch_bounds__(LNT) void k_lay_svd(const double2* __restrict__ Bk,
     if (lane == 0) offw[w] = off;
     __syncthreads();
     double mx = 0.0;
-    for (int k = 0; k < LNT / 64; ++k) mx = fmax(mx, offw[k]);
+    for (int k = 0; k < SNT / 64; ++k) mx = fmax(mx, offw[k]);
     __syncthreads();
     if (mx <= tol) break;
   }
-  for (int k = w; k < M; k += LNT / 64) {
+  for (int k = w; k < M; k += SNT / 64) {
     const double a = lane < M ? As[k * M + lane] : 0.0;
     const double s2 = wave_sum<double>(a * a);
     if (lane == 0) lam[(size_t)f * M + k] = s2;
   }
   double* Vf = V + (size_t)f * M * M;
-  for (int e = tid; e < M * M; e += LNT) {
+  for (int e = tid; e < M * M; e += SNT) {
     const int i = e / M, k = e % M;
     Vf[e] = Vs[k * M + i];
   }
@@ -137,8 +138,21 @@ __global__ __launch_bounds__(LNT) void k_lay_filter(const c2<T>* __restrict__ B,
   const int tid = threadIdx.x;
   for (int l = tid; l < L; l += LNT) ktv[l] = la.kt[(size_t)f * L + l];
   if constexpr (MODE == 0) {
+    // all of the system's V in flight at once (up to 15 loads per thread), then to LDS
+    constexpr int NV = (LAY_MMAX * LAY_MMAX + LNT - 1) / LNT;
     const double* Vf = la.V + (size_t)f * M * M;
-    for (int e = tid; e < M * M; e += LNT) Vs[e] = Vf[e];
+    const int MM = M * M;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = tid + k * LNT;
+      v[k] = e < MM ? Vf[e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = tid + k * LNT;
+      if (e < MM) Vs[e] = v[k];
+    }
     for (int k = tid; k < M; k += LNT) ls[k] = la.lam[(size_t)f * M + k];
   }
   for (int e = tid; e < nky * M; e += LNT) {
@@ -256,7 +270,7 @@ hipError_t go_lay(K kern, dim3 g, const Launch& L, Args... args) {
 
 hipError_t launch_lay_svd(const double2* Bk, const LayArgs& la, double* kt, double* V, double* lam, hipStream_t s) {
   if (la.M < 1 || la.M > LAY_MMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lay_svd, dim3((unsigned)(la.kxn * la.pyh)), dim3(LNT), 0, s, Bk, la, kt, V, lam);
+  hipLaunchKernelGGL(k_lay_svd, dim3((unsigned)(la.kxn * la.pyh)), dim3(SNT), 0, s, Bk, la, kt, V, lam);
   return hipGetLastError();
 }
 
