@@ -914,7 +914,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   const size_t nA = kxn * g->nz * g->ny, nB = kxn * g->nz * c->py;
   c->spec_bytes = nS * 2 * c->esz;
   c->work_bytes = (nA + nB) * 4 * c->esz;  // W1 + W2 (pairs) cover A + B
-  c->bins_part_n = (size_t)kxn * c->py;    // >= workgroups of the z pass
+  c->bins_part_n = (size_t)kxn * c->py + 64;  // >= workgroups of the z pass (tile pairs, padded grid)
   c->norm_part_n = (size_t)g->nz * g->ny;  // >= workgroups of the x pass
   const size_t noct = kxn * (c->pz / 2 + 1) * (c->py / 2 + 1);
   HIPCHK(c, hipMalloc(&c->oct, noct * sizeof(double2)));

@@ -164,9 +164,26 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   __shared__ c2<T> tw[P];
   __shared__ double bins[64];
   const int tid = threadIdx.x;
-  const int kx = blockIdx.y;
-  const int ky0 = blockIdx.x * C;
   const int py = a.py;
+  int kx, tile;
+  if constexpr (MODE == 0) {
+    // tiles 2t and 2t+1 share the 128 B lines of B's rows: they run as
+    // workgroups w and w + 8, i.e. on the same XCD (round robin over 8), so
+    // the second read of a line hits that XCD's L2
+    const int ntile = (py + C - 1) / C, npr = (ntile + 1) / 2;
+    const int w = blockIdx.x, sidx = w >> 3;
+    const int pidx = (sidx >> 1) * 8 + (w & 7);
+    kx = pidx / npr;
+    tile = 2 * (pidx % npr) + (sidx & 1);
+    if (kx >= a.kx_n || tile >= ntile) {  // padding of the grid: an empty partial
+      if (tid < 64) a.bins_part[(size_t)tid * gridDim.x + blockIdx.x] = 0.0;
+      return;
+    }
+  } else {
+    kx = blockIdx.y;
+    tile = blockIdx.x;
+  }
+  const int ky0 = tile * C;
   const c2<T>* src = B + (size_t)kx * NIN * py;
   c2<T> v[PE::n];
 #pragma unroll
@@ -216,8 +233,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     }
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    const int nblk = gridDim.x * gridDim.y;
+    const int bid = blockIdx.x, nblk = gridDim.x;
     if (tid < 64) a.bins_part[(size_t)tid * nblk + bid] = bins[tid];
   } else {
     const int oy = py / 2 + 1;
@@ -723,10 +739,11 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
     }                                                                                                            \
     const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
     const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
-    dim3 g(cdiv(a.py, C), a.kx_n);                                                                               \
+    const long long npr = (cdiv(a.py, C) + 1) / 2;                                                               \
+    dim3 g(16 * cdiv((long long)a.kx_n * npr, 8));                                                               \
     hipError_t e = sh == 1 ? go(k_fz<T, p, 0, s1>, g, L, B, S, a, tw) : go(k_fz<T, p, 0, 0>, g, L, B, S, a, tw);  \
     if (e != hipSuccess) return e;                                                                               \
-    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                           \
+    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)g.x);                                   \
     return hipGetLastError();                                                                                    \
   }
     FR3D_SIZES(X)
