@@ -57,11 +57,12 @@ typedef enum {
 #define FR3D_PRED_FALLBACK 16 /* predicted alpha rejected; the search continued */
 
 /* Geometry of R and Y (Sec. 3: both are horizontal layers with the same
- * lateral footprint; Sec. 5: uniform grids, midpoint quadrature weight h^3). */
+ * lateral footprint; Sec. 5: uniform grids, midpoint quadrature weight = the
+ * cell volume h^2 hz). */
 typedef struct {
   int32_t nx, ny, nz; /* cells per axis of R (= of Y); each 2n must be 2^a 3^b, n >= 2 */
-  double h;           /* cell edge (> 0) */
-  double D;           /* z-offset of Y above R in cells, >= nz; <= 0 selects the default */
+  double h;           /* lateral cell edge (> 0); also the vertical one unless hz > 0 */
+  double D;           /* z-offset of Y above R in vertical cells, >= nz; <= 0 selects the default */
   int32_t kind;       /* 0: K = dz(1/|x|) (Eq. (6), (8)); 1: K = 1/|x| (Eq. (5)) */
   int32_t q;          /* source parameter: -1 = single-kernel default gap nz + ceil(nz/4);
                          q >= 0: gap (q+1) ceil(nz/8) (each q gives its own kernel) */
@@ -69,8 +70,9 @@ typedef struct {
                          norms and alpha search; 64: all FP64 */
   int32_t alpha_relative; /* 0: alpha is the parameter of the Tikhonov functional
                          ||A zeta - F||^2 + alpha ||zeta||^2 in the L2 norms of Sec. 3
-                         (the h^3 weights of both terms cancel); 1: alpha is relative,
-                         alpha_abs = alpha max|k^|^2 */
+                         (the cell-volume weights of both terms cancel); 1: alpha is
+                         relative, alpha_abs = alpha max|k^|^2 */
+  double hz;          /* vertical cell edge; <= 0: hz = h (thin layers of Sec. 6 use hz < h) */
 } fr3d_geom;
 
 /* Options of the discrepancy search (Sec. 4: Tikhonov with the discrepancy

@@ -8,8 +8,9 @@ Readings of points the paper leaves open (each also listed in the design notes):
   z-centres (D+k+.5)h.  R and Y are disjoint when D >= nz.
 * Default gap: D = nz + ceil(nz/4).  With a source parameter q that varies the
   kernel: D_q = nz + (q+1) ceil(nz/8).
-* Quadrature: midpoint rule with weight h^3 (Sec. 5 names only "quadrature
-  coefficients").
+* Quadrature: midpoint rule with weight the cell volume h^2 hz (Sec. 5 names
+  only "quadrature coefficients"); hz = h unless the layers are thinner
+  (Sec. 6's model example), and D counts vertical cells.
 * Circulant embedding: per axis P = 2n; an offset index a in [0,P) stands for
   the cell offset a (a < n) or a-P (a > P-n); the one slot a = n (P = 2n) that
   no pair of cells reaches is zero.
@@ -34,6 +35,7 @@ class Geom:
     D: float | None = None   # z-offset of Y above R in cells
     kind: int = 0            # 0: dz(1/|x|) (Eq. (6)/(8)); 1: 1/|x| (Eq. (5))
     q: int | None = None     # source parameter; None = single-kernel default gap
+    hz: float | None = None  # vertical cell edge; None = h (D counts vertical cells)
 
     @property
     def shape(self):
@@ -42,6 +44,11 @@ class Geom:
     @property
     def pshape(self):
         return (2 * self.nz, 2 * self.ny, 2 * self.nx)
+
+    @property
+    def hv(self) -> float:
+        """Vertical cell edge."""
+        return float(self.h if self.hz is None else self.hz)
 
     @property
     def d(self) -> float:
@@ -76,16 +83,16 @@ def offset_of_index(a, n, p):
 
 
 def sample_kernel(g: Geom, pshape=None):
-    """Wrapped offset table k[c][b][a] = h^3 K(off(a) h, off(b) h, (D + off(c)) h),
+    """Wrapped offset table k[c][b][a] = h^2 hz K(off(a) h, off(b) h, (D + off(c)) hz),
     zero in slots no pair of cells reaches.  Shape (Pz, Py, Px)."""
     pz, py, px = pshape or g.pshape
     oz, vz = offset_of_index(np.arange(pz), g.nz, pz)
     oy, vy = offset_of_index(np.arange(py), g.ny, py)
     ox, vx = offset_of_index(np.arange(px), g.nx, px)
-    Z = (g.d + oz)[:, None, None] * g.h
+    Z = (g.d + oz)[:, None, None] * g.hv
     Y = oy[None, :, None] * g.h
     X = ox[None, None, :] * g.h
-    k = g.h ** 3 * kernel_fn(g.kind)(X, Y, Z)
+    k = g.h * g.h * g.hv * kernel_fn(g.kind)(X, Y, Z)
     mask = vz[:, None, None] & vy[None, :, None] & vx[None, None, :]
     return np.where(mask, k, 0.0)
 
@@ -98,14 +105,14 @@ def sources(g: Geom):
     pts = []
     for zc in (g.nz + G / 4.0, g.nz + 3.0 * G / 4.0):
         for (x, y) in ((cx, cy), (cx - ax, cy), (cx + ax, cy), (cx, cy - ay), (cx, cy + ay)):
-            pts.append((x * g.h, y * g.h, zc * g.h))
+            pts.append((x * g.h, y * g.h, zc * g.hv))
     return np.array(pts, dtype=np.float64)
 
 
 def v0(g: Geom, A0: float = 1.0):
     """V0 at the centres of R's cells for point sources (Sec. 6):
     V0(x) = -(A0 / 4 pi) sum_l 1/|x - x_l|.  Shape (nz, ny, nx)."""
-    z = (np.arange(g.nz) + 0.5)[:, None, None] * g.h
+    z = (np.arange(g.nz) + 0.5)[:, None, None] * g.hv
     y = (np.arange(g.ny) + 0.5)[None, :, None] * g.h
     x = (np.arange(g.nx) + 0.5)[None, None, :] * g.h
     acc = np.zeros(g.shape)

@@ -10,7 +10,7 @@ Readings (each also listed in the design notes):
   the exact discrete one.  The z axis is not embedded: the system matrix of
   lateral frequency (kx, ky) is A[i][j] = k~(kx, ky; i - j), Y layer i
   (height D + i cells), R layer j (height j cells), where k~(.; dz) is the 2D
-  DFT of the wrapped lateral samples h^3 K(ox h, oy h, (D + dz) h).  M = M' =
+  DFT of the wrapped lateral samples h^2 hz K(ox h, oy h, (D + dz) hz).  M = M' =
   nz.  K is even in x and y, so k~ and every A are real.
 * One alpha for all frequencies, chosen by the discrepancy principle on the
   residual over Y (Sec. 4 rule applied to the whole data set).
@@ -30,13 +30,13 @@ from .tikhonov import ITERATED, TIKHONOV, TSVD
 
 def lateral_kernel_spectrum(g: Geom):
     """k~[l][ky][kx] for l = dz + nz - 1, dz in (-nz, nz): 2D DFT over the
-    wrapped lateral offset table at z offset (D + dz) h, weight h^3."""
+    wrapped lateral offset table at z offset (D + dz) hz, weight h^2 hz."""
     py, px = 2 * g.ny, 2 * g.nx
     ox, vx = offset_of_index(np.arange(px), g.nx, px)
     oy, vy = offset_of_index(np.arange(py), g.ny, py)
     dz = np.arange(-(g.nz - 1), g.nz)
-    K = g.h ** 3 * kernel_fn(g.kind)(ox[None, None, :] * g.h, oy[None, :, None] * g.h,
-                                     (g.d + dz[:, None, None]) * g.h)
+    K = g.h * g.h * g.hv * kernel_fn(g.kind)(ox[None, None, :] * g.h, oy[None, :, None] * g.h,
+                                             (g.d + dz[:, None, None]) * g.hv)
     K = K * (vx[None, None, :] & vy[None, :, None])
     return np.fft.fft2(K, axes=(1, 2))
 
@@ -100,7 +100,7 @@ def forward_layered(g: Geom, kt, zeta):
 def assembled_operator(g: Geom):
     """The laterally embedded, z-exact operator as one explicit matrix from
     R's layers over the padded lateral box to Y's: rows (i, y, x), columns
-    (j, y', x'), entry h^3 K(wrapped offset (x - x', y - y'), (D + i - j) h).
+    (j, y', x'), entry h^2 hz K(wrapped offset (x - x', y - y'), (D + i - j) hz).
     No transform; for tiny grids only."""
     py, px = 2 * g.ny, 2 * g.nx
     n = g.nz * py * px
@@ -119,8 +119,8 @@ def assembled_operator(g: Geom):
                             ox, vx = offset_of_index((x - x2) % px, g.nx, px)
                             if not vx:
                                 continue
-                            C[row, (j * py + y2) * px + x2] = g.h ** 3 * K(float(ox) * g.h, float(oy) * g.h,
-                                                                          (g.d + i - j) * g.h)
+                            C[row, (j * py + y2) * px + x2] = g.h * g.h * g.hv * K(
+                                float(ox) * g.h, float(oy) * g.h, (g.d + i - j) * g.hv)
     return C
 
 

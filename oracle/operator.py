@@ -2,7 +2,7 @@
 
 Oracle (test infrastructure only).
 
-(A zeta)(y) = sum over cells r of R of  h^3 K(x_y - x_r) zeta(r),  y a cell of Y,
+(A zeta)(y) = sum over cells r of R of  h^2 hz K(x_y - x_r) zeta(r),  y a cell of Y,
 the midpoint quadrature of the convolution integral of Eq. (8) with the
 kernel K of Sec. 3.  Two forms:
 
@@ -19,12 +19,12 @@ from .geometry import Geom, kernel_fn, sample_kernel
 
 
 def offset_table(g: Geom):
-    """h^3 K at every cell offset (dz, dy, dx) in (-n, n)^3, indexed [dz+nz-1][dy+ny-1][dx+nx-1]."""
+    """h^2 hz K at every cell offset (dz, dy, dx) in (-n, n)^3, indexed [dz+nz-1][dy+ny-1][dx+nx-1]."""
     dz = np.arange(-(g.nz - 1), g.nz)[:, None, None]
     dy = np.arange(-(g.ny - 1), g.ny)[None, :, None]
     dx = np.arange(-(g.nx - 1), g.nx)[None, None, :]
-    # centre of Y cell minus centre of R cell: ((dx)h, (dy)h, (D + dz)h)
-    return g.h ** 3 * kernel_fn(g.kind)(dx * g.h, dy * g.h, (g.d + dz) * g.h)
+    # centre of Y cell minus centre of R cell: ((dx)h, (dy)h, (D + dz)hz)
+    return g.h * g.h * g.hv * kernel_fn(g.kind)(dx * g.h, dy * g.h, (g.d + dz) * g.hv)
 
 
 def forward_direct(g: Geom, zeta):

@@ -12,8 +12,8 @@ box (the three-axis analogue of the paper's per-frequency systems, Eq. (14)):
     r(alpha)        = (C zeta_pad - E_Y F) restricted to Y's index block,
 
 where alpha_abs is the Tikhonov parameter of the functional in the L2 norms of
-Sec. 3 (midpoint weights h^3 on both sides cancel, so alpha_abs = alpha for
-any h).  With ``relative=True`` the given alpha is scaled by max |k^|^2
+Sec. 3 (the cell-volume weights on both sides cancel, so alpha_abs = alpha
+for any cell size).  With ``relative=True`` the given alpha is scaled by max |k^|^2
 (relative to the squared operator norm of C) instead.
 
 ``dense_tikhonov`` solves the normal equations (C^T C + alpha_abs I) u = C^T E_Y F

@@ -72,11 +72,11 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nblk, int strid
 struct Sources { double x[10], y[10], z[10]; };
 
 template <typename T>
-__global__ void k_v0(T* __restrict__ V0, int nx, int ny, int nz, double h, double A0, Sources s) {
+__global__ void k_v0(T* __restrict__ V0, int nx, int ny, int nz, double h, double hz, double A0, Sources s) {
   const long long n = (long long)nx * ny * nz;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((long long)nx * ny));
-    const double px = (ix + 0.5) * h, py = (iy + 0.5) * h, pz = (iz + 0.5) * h;
+    const double px = (ix + 0.5) * h, py = (iy + 0.5) * h, pz = (iz + 0.5) * hz;
     double acc = 0.0;
     for (int l = 0; l < 10; ++l) {
       const double dx = px - s.x[l], dy = py - s.y[l], dz = pz - s.z[l];
@@ -180,6 +180,7 @@ struct fr3d_ctx {
   fr3d_geom g{};
   int px = 0, py = 0, pz = 0, kxn = 0;
   double D = 0;
+  double hz = 1;  // vertical cell edge
   size_t esz = 4;
   double smax = 0;
   double2* oct = nullptr;
@@ -440,6 +441,7 @@ FwdArgs fwd_args(fr3d_ctx* c, Lane& L, bool kernel) {
   a.py = c->py;
   a.pz = c->pz;
   a.h = c->g.h;
+  a.hz = c->hz;
   a.D = c->D;
   a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
   a.kind = c->g.kind;
@@ -895,6 +897,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   if (!supported_length(2 * g->nx) || !supported_length(2 * g->ny) || !supported_length(2 * g->nz))
     return fail(c, FR3D_E_INVALID, "2n per axis must be one of the compiled lengths (2^a 3^b, <= 512)");
   if (!(g->h > 0) || !std::isfinite(g->h)) return fail(c, FR3D_E_INVALID, "h must be finite and > 0");
+  if (!std::isfinite(g->hz)) return fail(c, FR3D_E_INVALID, "hz must be finite");
   if (g->kind != 0 && g->kind != 1) return fail(c, FR3D_E_INVALID, "kind must be 0 or 1");
   if (g->precision != 32 && g->precision != 64) return fail(c, FR3D_E_INVALID, "precision must be 32 or 64");
   if (!std::isfinite(g->D)) return fail(c, FR3D_E_INVALID, "D must be finite");
@@ -906,6 +909,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   free_geometry(c);
   c->g = *g;
   c->D = D;
+  c->hz = g->hz > 0 ? g->hz : g->h;
   c->px = 2 * g->nx; c->py = 2 * g->ny; c->pz = 2 * g->nz;
   c->kxn = c->px / 2 + 1;
   c->esz = g->precision == 64 ? 8 : 4;
@@ -970,6 +974,7 @@ fr3d_status fr3d_load_layered(fr3d_ctx* c, const fr3d_geom* g) {
   if (!supported_length(2 * g->nx) || !supported_length(2 * g->ny))
     return fail(c, FR3D_E_INVALID, "2n per lateral axis must be one of the compiled lengths (2^a 3^b, <= 512)");
   if (!(g->h > 0) || !std::isfinite(g->h)) return fail(c, FR3D_E_INVALID, "h must be finite and > 0");
+  if (!std::isfinite(g->hz)) return fail(c, FR3D_E_INVALID, "hz must be finite");
   if (g->kind != 0 && g->kind != 1) return fail(c, FR3D_E_INVALID, "kind must be 0 or 1");
   if (g->precision != 32 && g->precision != 64) return fail(c, FR3D_E_INVALID, "precision must be 32 or 64");
   if (!std::isfinite(g->D)) return fail(c, FR3D_E_INVALID, "D must be finite");
@@ -981,6 +986,7 @@ fr3d_status fr3d_load_layered(fr3d_ctx* c, const fr3d_geom* g) {
   free_geometry(c);
   c->g = *g;
   c->D = D;
+  c->hz = g->hz > 0 ? g->hz : g->h;
   c->px = 2 * g->nx; c->py = 2 * g->ny; c->pz = 2 * g->nz;
   c->kxn = c->px / 2 + 1;
   c->esz = g->precision == 64 ? 8 : 4;
@@ -1287,15 +1293,15 @@ fr3d_status fr3d_source_potential(fr3d_ctx* c, double A0, void* V0) {
     for (int l = 0; l < 5; ++l) {
       s.x[5 * k + l] = lx[l] * h;
       s.y[5 * k + l] = ly[l] * h;
-      s.z[5 * k + l] = hz[k] * h;
+      s.z[5 * k + l] = hz[k] * c->hz;
     }
   const long long n = ncells(c);
   Lane& L = c->lanes[0];
   dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 4096));
   if (c->esz == 8)
-    hipLaunchKernelGGL(k_v0<double>, grid, dim3(256), 0, L.stream, (double*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
+    hipLaunchKernelGGL(k_v0<double>, grid, dim3(256), 0, L.stream, (double*)V0, c->g.nx, c->g.ny, c->g.nz, h, c->hz, A0, s);
   else
-    hipLaunchKernelGGL(k_v0<float>, grid, dim3(256), 0, L.stream, (float*)V0, c->g.nx, c->g.ny, c->g.nz, h, A0, s);
+    hipLaunchKernelGGL(k_v0<float>, grid, dim3(256), 0, L.stream, (float*)V0, c->g.nx, c->g.ny, c->g.nz, h, c->hz, A0, s);
   LCHK(c, hipGetLastError());
   return FR3D_OK;
 }

@@ -59,7 +59,7 @@ struct FwdArgs {
   int kx_n;           // Px/2 + 1
   int py, pz;         // padded extents
   // kernel sampling (x pass in generator mode)
-  double h, D;
+  double h, hz, D;    // lateral and vertical cell edges, gap in vertical cells
   int nx, ny, nz;     // cell counts
   int kind;
   int zlin;           // generator mode: plane z samples the z offset z - (nz - 1) (no wrap)

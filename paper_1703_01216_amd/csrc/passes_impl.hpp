@@ -21,8 +21,8 @@ template <int TOTAL> struct Per {
 // (a + i b); after the transform A(k) = (Z(k) + conj Z(P-k))/2 and
 // B(k) = (Z(k) - conj Z(P-k))/(2i).  Data mode reads the n = P/2 valid
 // samples of each row; generator mode samples the kernel's offset table on
-// the fly (Sec. 3 kernel, Sec. 5 midpoint weight h^3; the slot at offset
-// index n is zero).
+// the fly (Sec. 3 kernel, Sec. 5 midpoint weight = cell volume h^2 hz; the
+// slot at offset index n is zero).
 __device__ __forceinline__ double kernel_value(int kind, double x, double y, double z) {
   const double r2 = x * x + y * y + z * z;
   const double rr = sqrt(r2);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       int ox, oy, oz;
       const bool zok = a.zlin ? (oz = z - (a.nz - 1), true) : wrap_offset(z, a.nz, a.pz, oz);
       if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) && zok) {
-        v = a.h * a.h * a.h * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.h);
+        v = a.h * a.h * a.hz * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.hz);
       }
       ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = (T)v;
     }

@@ -39,7 +39,8 @@ N_NORM = 132
 class Geom(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("h", ctypes.c_double), ("D", ctypes.c_double), ("kind", ctypes.c_int32),
-                ("q", ctypes.c_int32), ("precision", ctypes.c_int32), ("alpha_relative", ctypes.c_int32)]
+                ("q", ctypes.c_int32), ("precision", ctypes.c_int32), ("alpha_relative", ctypes.c_int32),
+                ("hz", ctypes.c_double)]
 
 
 class DpOpts(ctypes.Structure):
@@ -195,14 +196,14 @@ class Context:
         self._chk(self._lib.fr3d_set_stream(self._ctx, ctypes.c_void_p(stream.cuda_stream)))
 
     # ------------------------------------------------------------ calls of include/fr3d.h
-    def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0):
-        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative)
+    def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0, hz=0.0):
+        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative, hz)
         self._chk(self._lib.fr3d_load_kernel(self._ctx, ctypes.byref(g)))
         self.geom = g
 
-    def load_layered(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0):
+    def load_layered(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0, hz=0.0):
         """Per-frequency z-systems (Algorithm 1 as run in Sec. 5) instead of the 3D embedding."""
-        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative)
+        g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative, hz)
         self._chk(self._lib.fr3d_load_layered(self._ctx, ctypes.byref(g)))
         self.geom = g
 

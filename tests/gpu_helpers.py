@@ -7,8 +7,8 @@ from oracle.geometry import Geom
 from paper_1703_01216_amd import inputs
 
 
-def geom(nx, ny, nz, D=None, kind=0, q=None, h=1.0):
-    return Geom(nx, ny, nz, h=h, D=D, kind=kind, q=q)
+def geom(nx, ny, nz, D=None, kind=0, q=None, h=1.0, hz=None):
+    return Geom(nx, ny, nz, h=h, D=D, kind=kind, q=q, hz=hz)
 
 
 def instance(g: Geom, seed, delta_rel=0.01, recipe="blobs"):

@@ -65,7 +65,8 @@ def test_create_without_gpu_reports_device_error(lib):
 def test_struct_layouts_match_header():
     from paper_1703_01216_amd import fr3d
     # int32 x3, (pad) double x2, int32 x3 (+pad)
-    assert ctypes.sizeof(fr3d.Geom) == 48 and fr3d.Geom.h.offset == 16 and fr3d.Geom.kind.offset == 32
+    assert ctypes.sizeof(fr3d.Geom) == 56 and fr3d.Geom.h.offset == 16 and fr3d.Geom.kind.offset == 32
+    assert fr3d.Geom.hz.offset == 48
     assert ctypes.sizeof(fr3d.Report) == 56 and fr3d.Report.n_evals.offset == 40 and fr3d.Report.n_clamped.offset == 48
     assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 96 and fr3d.DpOpts.seed_walk.offset == 80
     assert fr3d.DpOpts.candidates.offset == 88

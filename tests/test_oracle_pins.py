@@ -11,8 +11,8 @@ import os
 import numpy as np
 import pytest
 
-from oracle import dft, discrepancy, features, mlp, recovery, synth, tikhonov
-from oracle.geometry import Geom, kernel_dz, kernel_inv, sample_kernel, sources, v0
+from oracle import dft, discrepancy, features, layered, mlp, recovery, synth, tikhonov
+from oracle.geometry import Geom, kernel_dz, kernel_fn, kernel_inv, sample_kernel, sources, v0
 from oracle.operator import circulant_apply, forward_circulant, forward_direct, offset_table, pad
 from paper_1703_01216_amd import inputs
 
@@ -165,6 +165,36 @@ def test_forward_direct_equals_circulant(shape, D, kind):
     a = forward_direct(g, zeta)
     b = forward_circulant(g, zeta)
     assert np.max(np.abs(a - b)) < 1e-13 * np.abs(a).max()
+
+
+def test_anisotropic_cells_brute_force():
+    # Thin layers (Sec. 6: vertical cells finer than lateral ones): the sum
+    # over explicit cell centres ((i+.5)h, (j+.5)h, (k+.5)hz) of R and
+    # ((i+.5)h, (j+.5)h, (D+k+.5)hz) of Y with weight h^2 hz, written out
+    # point by point, equals the table-based direct sum and the circulant form.
+    g = Geom(3, 2, 3, h=0.5, hz=0.125, D=9.0)
+    zeta = inputs.rng(6).standard_normal(g.shape)
+    K = kernel_fn(0)
+    out = np.zeros(g.shape)
+    for kz in range(3):
+        for jy in range(2):
+            for ix in range(3):
+                y = np.array([(ix + .5) * 0.5, (jy + .5) * 0.5, (9.0 + kz + .5) * 0.125])
+                acc = 0.0
+                for kz2 in range(3):
+                    for jy2 in range(2):
+                        for ix2 in range(3):
+                            r = np.array([(ix2 + .5) * 0.5, (jy2 + .5) * 0.5, (kz2 + .5) * 0.125])
+                            d = y - r
+                            acc += 0.5 * 0.5 * 0.125 * K(d[0], d[1], d[2]) * zeta[kz2, jy2, ix2]
+                out[kz, jy, ix] = acc
+    assert np.allclose(forward_direct(g, zeta), out, rtol=1e-13, atol=0)
+    assert np.allclose(forward_circulant(g, zeta), out, rtol=1e-12, atol=1e-14 * np.abs(out).max())
+    kt = layered.lateral_kernel_spectrum(g)
+    assert np.allclose(layered.forward_layered(g, kt, zeta), out, rtol=1e-12, atol=1e-14 * np.abs(out).max())
+    # the sources sit at nz + G/4 and nz + 3G/4 vertical cells
+    src = sources(g)
+    assert np.allclose(np.unique(src[:, 2]), [(3 + 1.5) * 0.125, (3 + 4.5) * 0.125])
 
 
 @pytest.mark.slow
@@ -598,7 +628,6 @@ def test_mlp_param_count():
 
 # ---------------------------------------------------------------- Algorithm 1 with per-frequency z-systems (Sec. 5)
 
-from oracle import layered  # noqa: E402
 
 
 @pytest.mark.parametrize("shape,kind", [((4, 3, 5), 0), ((3, 4, 4), 1), ((6, 6, 2), 0)])
