@@ -197,6 +197,12 @@ def layered_section(torch, fr3d, n=256, nz=51, reps=3):
         out[name] = {"solve_ms": el * 1e3, "n_evals": rep["n_evals"], "flags": rep["flags"],
                      "alpha": rep["alpha"], "r_over_delta": rep["residual"] / delta}
     c.close()
+    # the model example itself (Sec. 6 geometry and xi, FP64, TSVD, perturbation 1e-3)
+    from paper_1703_01216_amd import model_example
+    me = model_example.run(n, nz, amplitude=1e-3, precision=64)
+    out["model_example_fp64_tsvd"] = {k: me[k] for k in ("setup_ms", "solve_ms", "n_evals", "flags", "alpha",
+                                                           "r_over_delta")}
+    out["model_example_fp64_tsvd"]["mean_delta_C"] = sum(me["delta_C"]) / len(me["delta_C"])
     return out
 
 

@@ -176,6 +176,52 @@ def xi_torch(shape, inclusions, device="cuda"):
     return xi
 
 
+# ---------------------------------------------------------------- the model example (Sec. 6)
+# R = [-10, 10]^2 x [1, 2], Y = [-10, 10]^2 x [6, 7], ten point sources at
+# (0, 0), (+-8, 0), (0, +-8) and heights 3 and 5; c0 = 0.5; g(t) = e^-t
+# (A0 = 1).  On n x n x nz cells: h = 20/n, hz = 1/nz, Y's bottom 5 = D hz
+# above R's, so D = 5 nz; the library's default source cross (lateral centre
+# and +-0.4 n, heights nz + G/4 and nz + 3G/4 with G = D - nz) lands on the
+# paper's points exactly.
+
+MODEL_C0 = 0.5
+
+
+def model_geometry(n: int, nz: int):
+    """dict(nx, ny, nz, h, hz, D) of the model example on n x n x nz cells."""
+    return dict(nx=n, ny=n, nz=nz, h=20.0 / n, hz=1.0 / nz, D=5.0 * nz)
+
+
+def model_xi(n: int, nz: int, xp=np, device=None):
+    """The model solution xi(x, y, z) at R's cell centres ([nz][n][n]); the
+    printed formula is garbled in two places and is read with z in a2 and a3
+    and +(y + 4)^2 in the third exponent, which makes every exponent
+    negative definite."""
+    h, hz = 20.0 / n, 1.0 / nz
+    if xp is np:
+        ar = lambda m: np.arange(m, dtype=np.float64)  # noqa: E731
+    else:
+        ar = lambda m: xp.arange(m, dtype=xp.float64, device=device)  # noqa: E731
+    x = (-10.0 + (ar(n) + 0.5) * h).reshape(1, 1, n)
+    y = (-10.0 + (ar(n) + 0.5) * h).reshape(1, n, 1)
+    z = (1.0 + (ar(nz) + 0.5) * hz).reshape(nz, 1, 1)
+    zero = 0.0 * z
+    a1 = (1.0 - 4.0 * (z - 1.5) ** 2) ** 2
+    a2 = 0.4 * xp.maximum(1.0 - (z - 1.3) ** 2, zero)
+    a3 = 0.2 * xp.maximum((1.0 - (z - 1.7) ** 2) ** 2, zero)
+    u, v = x + 4.0, y - 5.0
+    p, q = x - 4.0, y + 4.0
+    return (a1 * xp.exp(-x ** 2 - 2.0 * y ** 2)
+            + a2 * xp.exp(-3.0 * u ** 2 - v ** 2 + u * v)
+            + a3 * xp.exp(-0.9 * (p ** 2 + q ** 2 + p * q)))
+
+
+def model_noise(shape, seed: int, amplitude: float):
+    """Perturbation of the data: uniform in [-amplitude, amplitude] (Sec. 6
+    perturbs with a maximum of about 1e-8)."""
+    return rng(seed + 11_000_017).uniform(-amplitude, amplitude, size=shape)
+
+
 def workload_instance(cfg: int, index: int, n=None):
     """The synthetic instance of workload ``cfg`` (1..5) with index ``index``.
 
