@@ -681,3 +681,41 @@ def test_layered_filters_and_monotone_residual():
     i3 = layered.solve_layered(g, kt, F, 1e-3, tikhonov.ITERATED, 3)
     assert np.allclose(o1["zeta"], i1["zeta"], rtol=0, atol=1e-12 * np.abs(o1["zeta"]).max())
     assert i3["r_norm"] < o1["r_norm"]
+
+
+# ---------------------------------------------------------------- exact restricted-operator Tikhonov (Sec. 3-4)
+
+from oracle import exact  # noqa: E402
+
+
+@pytest.mark.parametrize("shape,kind", [((3, 4, 5), 0), ((4, 3, 3), 1)])
+def test_exact_adjoint(shape, kind):
+    # <A z, r>_Y = <z, A^T r>_R, and the spectral adjoint equals the direct sum
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz, kind=kind, hz=0.75)
+    khat = np.fft.fftn(sample_kernel(g))
+    z = inputs.rng(31).standard_normal(shape)
+    r = inputs.rng(32).standard_normal(shape)
+    at = exact.adjoint(g, khat, r)
+    assert np.allclose(at, exact.adjoint_direct(g, r), rtol=0, atol=1e-12 * np.abs(at).max())
+    lhs = float(np.sum(forward_direct(g, z) * r))
+    rhs = float(np.sum(z * exact.adjoint_direct(g, r)))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [1e-1, 1e-3])
+def test_exact_cg_equals_dense_normal_equations(alpha):
+    g = Geom(4, 3, 3)
+    F = inputs.rng(33).standard_normal(g.shape)
+    de = exact.dense_exact(g, F, alpha)
+    cg = exact.cg_exact(g, F, alpha, tol=1e-13)
+    assert np.linalg.norm(cg["zeta"] - de["zeta"]) < 1e-9 * np.linalg.norm(de["zeta"])
+    assert cg["r_norm"] == pytest.approx(de["r_norm"], rel=1e-9)
+    # it minimises the exact functional: the embedded estimate restricted to R,
+    # a feasible point, scores no better
+    emb = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), F, alpha)["zeta"]
+
+    def obj(z):
+        return float(np.sum((forward_direct(g, z) - F) ** 2) + alpha * np.sum(z * z))
+    assert obj(de["zeta"]) <= obj(emb) * (1 + 1e-12)
+    assert obj(de["zeta"]) <= obj(de["zeta"] + 1e-3 * inputs.rng(34).standard_normal(g.shape))
