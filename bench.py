@@ -206,6 +206,33 @@ def layered_section(torch, fr3d, n=256, nz=51, reps=3):
     return out
 
 
+def exact_section(torch, fr3d, Fs, n, alpha=1e-3, max_iter=200):
+    """Tikhonov for the exact restricted operator (CG on the normal
+    equations, two transform round trips per step) on one instance of the
+    bench workload: per-step time and the estimate's gap to the 3D
+    embedding's at the same alpha."""
+    c = fr3d.Context(0)
+    c.load_kernel(n, n, n, precision=32)
+    c.apply_tuning()
+    F = Fs[0]
+    z = torch.empty_like(F)
+    c.solve_exact(F, alpha, z, max_iter=2, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = c.solve_exact(F, alpha, z, max_iter=max_iter, tol=1e-6)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ze = torch.empty_like(F)
+    c.set_data(F, 1.0)
+    re = c.solve_alpha(alpha, ze)
+    gap = float(torch.linalg.vector_norm((z - ze).double()) / torch.linalg.vector_norm(ze.double()))
+    c.close()
+    return {"alpha": alpha, "cg_steps": rep["n_evals"], "converged": rep["flags"] == 0,
+            "ms_per_cg_step": el / max(rep["n_evals"], 1) * 1e3, "solve_ms": el * 1e3,
+            "residual_exact": rep["residual"], "residual_embedded": re["residual"],
+            "zeta_gap_to_embedded": gap}
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     """Plain device-to-device copy of a 1 GiB buffer (read + write = 2 GiB per
     copy): the practical HBM ceiling and the calibration kernel for counters."""
@@ -292,6 +319,7 @@ def main():
     ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w,kary16")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
+    ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-lane kernel-timing section (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -392,6 +420,9 @@ def main():
     if "learned_w" in results and "bisection_w" in results:
         out["config"]["speedup_learned_vs_bisection_tol_0.1"] = (
             results["learned_w"]["solves_per_s"] / results["bisection_w"]["solves_per_s"])
+    if args.exact:
+        out["config"]["exact_cg"] = exact_section(torch, fr3d, Fs, n)
+        print(f"[bench] exact: {out['config']['exact_cg']}", file=sys.stderr, flush=True)
     if args.w3 > 0:
         del Fs, V0
         torch.cuda.empty_cache()

@@ -55,6 +55,7 @@ typedef enum {
 #define FR3D_MAXITER 4       /* step limit reached; alpha is the upper bracket end */
 #define FR3D_NAN_INPUT 8     /* a norm came out non-finite */
 #define FR3D_PRED_FALLBACK 16 /* predicted alpha rejected; the search continued */
+#define FR3D_CG_LIMIT 32      /* exact-operator solve: CG stopped at max_iter before its tolerance */
 
 /* Geometry of R and Y (Sec. 3: both are horizontal layers with the same
  * lateral footprint; Sec. 5: uniform grids, midpoint quadrature weight = the
@@ -212,6 +213,28 @@ fr3d_status fr3d_recover_c(fr3d_ctx* ctx, const void* zeta_dev, const void* V0_d
  * cross (lateral centre and +-0.4 n along x and y) at heights nz + G/4 and
  * nz + 3G/4 with G = D - nz.  Writes nz*ny*nx values. */
 fr3d_status fr3d_source_potential(fr3d_ctx* ctx, double A0, void* V0_dev);
+
+/* Tikhonov's method for the exact discrete operator A: L2(R) -> L2(Y) (the
+ * quadrature of Eq. (8); Sec. 3's regularised normal solution, nothing on a
+ * padded box): zeta = argmin ||A zeta - F||^2_Y + alpha ||zeta||^2_R, by
+ * conjugate gradients on (A^T A + alpha I) zeta = A^T F from zero; every
+ * product with A and A^T runs through the context's transforms (A^T with
+ * the conjugate kernel spectrum).  Stops when the normal-equation residual
+ * is <= tol ||A^T F|| (checked every 16 steps) or after max_iter steps
+ * (flag FR3D_CG_LIMIT).  F: data on Y, zeta: out, nz*ny*nx device arrays;
+ * alpha in the units of geom.alpha_relative.  rep: alpha, residual =
+ * ||A zeta - F||_Y, zeta_norm, n_evals = CG steps.  Overwrites the context's
+ * data spectrum (set_data again before the other solves); synchronises. */
+fr3d_status fr3d_solve_exact(fr3d_ctx* ctx, const void* F_dev, double alpha, void* zeta_dev, int32_t max_iter,
+                             double tol, fr3d_report* rep);
+
+/* The same with alpha chosen by the plain discrepancy rule of
+ * fr3d_solve_discrepancy (bisection in log10 alpha, range ends first, any
+ * point within tol accepted; use_predictor and candidates are rejected),
+ * each point a CG solve from zero; n_evals counts alpha points, flags add
+ * FR3D_CG_LIMIT if any solve hit max_iter. */
+fr3d_status fr3d_solve_exact_discrepancy(fr3d_ctx* ctx, const void* F_dev, double delta, const fr3d_dp_opts* opts,
+                                         void* zeta_dev, int32_t max_iter, double tol, fr3d_report* rep);
 
 /* Apply the forward operator: F = A zeta on Y (Eq. (8) by midpoint
  * quadrature), through the same padded transforms and the loaded kernel

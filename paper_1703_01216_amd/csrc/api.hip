@@ -68,6 +68,78 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nblk, int strid
   }
 }
 
+// ---- conjugate gradients on the normal equations of the exact operator.
+// Device scalars cg[]: 0 r.r, 1 p.q, 2 r.r after the step, 3 b.b, 4 x.x, 5 t.t.
+template <typename T>
+__global__ void k_dot_part(const T* __restrict__ a, const T* __restrict__ b, long long n, double* part) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    s += (double)a[i] * (double)b[i];
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// q += alpha p; partial p.q
+template <typename T>
+__global__ void k_cg_q(T* __restrict__ q, const T* __restrict__ p, double alpha, long long n, double* part) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const double pv = (double)p[i];
+    const T qv = (T)((double)q[i] + alpha * pv);
+    q[i] = qv;
+    s += pv * (double)qv;
+  }
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// a = r.r / p.q;  x += a p;  r -= a q;  partial of the new r.r
+template <typename T>
+__global__ void k_cg_step(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                          long long n, const double* __restrict__ cg, double* part) {
+  __shared__ double red[NT / 64];
+  const double a = cg[0] / cg[1];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    x[i] = (T)((double)x[i] + a * (double)p[i]);
+    const T rv = (T)((double)r[i] - a * (double)q[i]);
+    r[i] = rv;
+    s += (double)rv * (double)rv;
+  }
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = r + (r.r new / r.r) p
+template <typename T>
+__global__ void k_cg_dir(T* __restrict__ p, const T* __restrict__ r, long long n, const double* __restrict__ cg) {
+  const double beta = cg[2] / cg[0];
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    p[i] = (T)((double)r[i] + beta * (double)p[i]);
+}
+
+__global__ void k_cg_roll(double* cg) { cg[0] = cg[2]; }
+
+// t -= F; partial t.t
+template <typename T>
+__global__ void k_sub_sq(T* __restrict__ t, const T* __restrict__ F, long long n, double* part) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const T v = (T)((double)t[i] - (double)F[i]);
+    t[i] = v;
+    s += (double)v * (double)v;
+  }
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T> __global__ void k_fill0(T* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) x[i] = (T)0;
+}
+
 // V0(x) = -(A0/4 pi) sum_l 1/|x - x_l| at R's cell centres (Sec. 6 point sources).
 struct Sources { double x[10], y[10], z[10]; };
 
@@ -206,6 +278,12 @@ struct fr3d_ctx {
   // timing
   bool timing = false;
   int filt = 0, forder = 1;          // regularising filter and its order
+  // conjugate-gradient workspace of the exact-operator solves (r, p, q, t; partials; scalars)
+  void* cg_buf = nullptr;
+  size_t cg_cap = 0;
+  double* cg_part = nullptr;
+  double* cg_dev = nullptr;
+  double* cg_host = nullptr;  // pinned
   bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
   hipStream_t cap_stream = nullptr; // stream the graphs are captured on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -499,7 +577,7 @@ LayArgs lay_args(fr3d_ctx* c) {
   return la;
 }
 
-template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out) {
+template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out, bool adj = false) {
   const bool dbl = sizeof(T) == 8;
   void *twx, *twy, *twz;
   fr3d_status st;
@@ -508,6 +586,7 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     return st;
   Bufs<T> b = bufs<T>(c, L);
   InvArgs a = inv_args(c, L, mode == 0);
+  a.adj = adj ? 1 : 0;
   if (mode == 0 && L.kmax > 0) {
     // K-candidate step (runs only while the search is in that state)
     const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny, nB = (size_t)c->kxn * c->g.nz * c->py;
@@ -866,6 +945,10 @@ fr3d_status fr3d_destroy(fr3d_ctx* c) {
   }
   for (auto& e : c->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  dfree(c->cg_buf);
+  dfree(c->cg_part);
+  dfree(c->cg_dev);
+  hfree(c->cg_host);
   dfree(c->pred_p);
   dfree(c->pred_m);
   dfree(c->pred_v);
@@ -1304,6 +1387,208 @@ fr3d_status fr3d_source_potential(fr3d_ctx* c, double A0, void* V0) {
     hipLaunchKernelGGL(k_v0<float>, grid, dim3(256), 0, L.stream, (float*)V0, c->g.nx, c->g.ny, c->g.nz, h, c->hz, A0, s);
   LCHK(c, hipGetLastError());
   return FR3D_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int CG_PARTS = 1024;
+
+fr3d_status cg_alloc(fr3d_ctx* c) {
+  const size_t bytes = 4 * (size_t)ncells(c) * c->esz;
+  if (c->cg_cap < bytes) {
+    dfree(c->cg_buf);
+    c->cg_cap = 0;
+    HIPCHK(c, hipMalloc(&c->cg_buf, bytes));
+    c->cg_cap = bytes;
+  }
+  if (!c->cg_part) HIPCHK(c, hipMalloc(&c->cg_part, CG_PARTS * sizeof(double)));
+  if (!c->cg_dev) HIPCHK(c, hipMalloc(&c->cg_dev, 8 * sizeof(double)));
+  if (!c->cg_host) HIPCHK(c, hipHostMalloc(&c->cg_host, 8 * sizeof(double), hipHostMallocDefault));
+  return FR3D_OK;
+}
+
+// out = A in (adj = false: R -> Y) or A^T in (adj = true: Y -> R) through
+// lane 0's buffers (its data spectrum is overwritten).
+template <typename T> fr3d_status apply_lin(fr3d_ctx* c, const T* in, T* out, bool adj) {
+  Lane& L = c->lanes[0];
+  fr3d_status s;
+  if ((s = forward_data<T>(c, L, in))) return s;
+  L.has_data = false;
+  return inverse<T>(c, L, 1, out, adj);
+}
+
+// Sum of the per-block partials into cg[slot] (one workgroup, fixed order).
+fr3d_status cg_sum(fr3d_ctx* c, hipStream_t st, int nb, int slot) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, st, (const double*)c->cg_part, nb, 1, 1, c->cg_dev + slot);
+  LCHK(c, hipGetLastError());
+  return FR3D_OK;
+}
+
+// CG on (A^T A + a I) x = A^T F from x = 0 until ||r|| <= tol ||A^T F||
+// (checked every 16 steps) or max_iter steps; then ||A x - F||_Y and ||x||_R.
+template <typename T>
+fr3d_status cg_solve(fr3d_ctx* c, const T* F, double a, T* x, int max_iter, double tol, int* iters, bool* conv,
+                     double* rnorm, double* xnorm) {
+  fr3d_status s;
+  if ((s = cg_alloc(c))) return s;
+  const long long n = ncells(c);
+  T* r = (T*)c->cg_buf;
+  T* p = r + n;
+  T* q = p + n;
+  T* t = q + n;
+  hipStream_t st = c->lanes[0].stream;
+  const int nb = (int)std::min<long long>((n + NT - 1) / NT, CG_PARTS);
+  if ((s = apply_lin<T>(c, F, r, true))) return s;  // r = b = A^T F
+  hipLaunchKernelGGL(k_fill0<T>, dim3(nb), dim3(NT), 0, st, x, n);
+  HIPCHK(c, hipMemcpyAsync(p, r, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_dot_part<T>, dim3(nb), dim3(NT), 0, st, (const T*)r, (const T*)r, n, c->cg_part);
+  LCHK(c, hipGetLastError());
+  if ((s = cg_sum(c, st, nb, 0))) return s;
+  HIPCHK(c, hipMemcpyAsync(c->cg_dev + 3, c->cg_dev, sizeof(double), hipMemcpyDeviceToDevice, st));
+  int it = 0;
+  bool done = false;
+  for (;;) {
+    if (it % 16 == 0 || it >= max_iter) {
+      HIPCHK(c, hipMemcpyAsync(c->cg_host, c->cg_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      const double rr = c->cg_host[0], bb = c->cg_host[3];
+      if (!std::isfinite(rr)) return fail(c, FR3D_E_DEVICE, "CG residual is not finite");
+      if (bb == 0.0 || rr <= tol * tol * bb) { done = true; break; }
+      if (it >= max_iter) break;
+    }
+    if ((s = apply_lin<T>(c, p, t, false))) return s;  // t = A p
+    if ((s = apply_lin<T>(c, t, q, true))) return s;   // q = A^T A p
+    hipLaunchKernelGGL(k_cg_q<T>, dim3(nb), dim3(NT), 0, st, q, (const T*)p, a, n, c->cg_part);
+    LCHK(c, hipGetLastError());
+    if ((s = cg_sum(c, st, nb, 1))) return s;
+    hipLaunchKernelGGL(k_cg_step<T>, dim3(nb), dim3(NT), 0, st, x, r, (const T*)p, (const T*)q, n,
+                       (const double*)c->cg_dev, c->cg_part);
+    LCHK(c, hipGetLastError());
+    if ((s = cg_sum(c, st, nb, 2))) return s;
+    hipLaunchKernelGGL(k_cg_dir<T>, dim3(nb), dim3(NT), 0, st, p, (const T*)r, n, (const double*)c->cg_dev);
+    hipLaunchKernelGGL(k_cg_roll, dim3(1), dim3(1), 0, st, c->cg_dev);
+    LCHK(c, hipGetLastError());
+    ++it;
+  }
+  // residual on Y and norm on R of the estimate
+  if ((s = apply_lin<T>(c, x, t, false))) return s;
+  hipLaunchKernelGGL(k_sub_sq<T>, dim3(nb), dim3(NT), 0, st, t, F, n, c->cg_part);
+  LCHK(c, hipGetLastError());
+  if ((s = cg_sum(c, st, nb, 5))) return s;
+  hipLaunchKernelGGL(k_dot_part<T>, dim3(nb), dim3(NT), 0, st, (const T*)x, (const T*)x, n, c->cg_part);
+  LCHK(c, hipGetLastError());
+  if ((s = cg_sum(c, st, nb, 4))) return s;
+  HIPCHK(c, hipMemcpyAsync(c->cg_host, c->cg_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  *iters = it;
+  *conv = done;
+  *rnorm = std::sqrt(c->cg_host[5]);
+  *xnorm = std::sqrt(c->cg_host[4]);
+  return FR3D_OK;
+}
+
+fr3d_status exact_eval(fr3d_ctx* c, const void* F, double alpha_abs, void* x, int max_iter, double tol, int* iters,
+                       bool* conv, double* rn, double* xn) {
+  return c->esz == 8 ? cg_solve<double>(c, (const double*)F, alpha_abs, (double*)x, max_iter, tol, iters, conv, rn, xn)
+                     : cg_solve<float>(c, (const float*)F, alpha_abs, (float*)x, max_iter, tol, iters, conv, rn, xn);
+}
+
+fr3d_status check_exact(fr3d_ctx* c, const void* F, void* zeta, int max_iter, double tol) {
+  if (!need(c, true, false)) return FR3D_E_STATE;
+  if (!F || !zeta) return fail(c, FR3D_E_INVALID, "null array");
+  if (max_iter < 1) return fail(c, FR3D_E_INVALID, "max_iter must be >= 1");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(c, FR3D_E_INVALID, "tol must be finite and > 0");
+  return FR3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr3d_status fr3d_solve_exact(fr3d_ctx* c, const void* F, double alpha, void* zeta, int32_t max_iter, double tol,
+                             fr3d_report* rep) {
+  if (!c) return FR3D_E_INVALID;
+  fr3d_status s;
+  if ((s = check_exact(c, F, zeta, max_iter, tol))) return s;
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(c, FR3D_E_INVALID, "alpha must be finite and > 0");
+  const double a_scale = c->g.alpha_relative ? c->smax : 1.0;
+  int iters = 0;
+  bool conv = false;
+  double rn = 0, xn = 0;
+  if ((s = exact_eval(c, F, alpha * a_scale, zeta, max_iter, tol, &iters, &conv, &rn, &xn))) return s;
+  if (rep) {
+    *rep = fr3d_report{};
+    rep->alpha = alpha;
+    rep->residual = rn;
+    rep->zeta_norm = xn;
+    rep->n_evals = iters;
+    rep->flags = conv ? 0 : FR3D_CG_LIMIT;
+    rep->n_clamped = -1;
+  }
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_solve_exact_discrepancy(fr3d_ctx* c, const void* F, double delta, const fr3d_dp_opts* o, void* zeta,
+                                         int32_t max_iter, double tol, fr3d_report* rep) {
+  if (!c) return FR3D_E_INVALID;
+  fr3d_status s;
+  if ((s = check_exact(c, F, zeta, max_iter, tol))) return s;
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(c, FR3D_E_INVALID, "delta must be >= 0");
+  fr3d_dp_opts d;
+  if ((s = check_opts(c, o, &d))) return s;
+  if (d.use_predictor || d.candidates) return fail(c, FR3D_E_INVALID, "the exact-operator search is the plain rule");
+  const double a_scale = c->g.alpha_relative ? c->smax : 1.0;
+  // the plain rule (bisection in log10 alpha), as on the device for the other forms
+  int n_evals = 0, flags = 0;
+  double r = 0, zn = 0, tgt = 0, last_t = 0;
+  auto ev = [&](double t, double* rho, double* ratio) -> fr3d_status {
+    int iters = 0;
+    bool conv = false;
+    fr3d_status e = exact_eval(c, F, std::pow(10.0, t) * a_scale, zeta, max_iter, tol, &iters, &conv, &r, &zn);
+    if (e) return e;
+    if (!conv) flags |= FR3D_CG_LIMIT;
+    ++n_evals;
+    last_t = t;
+    const double g = d.tau * delta + d.h_op * zn;
+    const double t2 = g * g + d.mu * d.mu;
+    tgt = std::sqrt(t2);
+    *rho = r * r - t2;
+    *ratio = t2 > 0 ? r / tgt : INFINITY;
+    return FR3D_OK;
+  };
+  double rho = 0, ratio = 0, t = d.log10_alpha_hi;
+  auto finish = [&](double tt, int fl) {
+    if (rep) {
+      *rep = fr3d_report{};
+      rep->alpha = std::pow(10.0, tt);
+      rep->residual = r;
+      rep->zeta_norm = zn;
+      rep->delta = delta;
+      rep->target = tgt;
+      rep->n_evals = n_evals;
+      rep->flags = flags | fl;
+      rep->n_clamped = -1;
+    }
+    return FR3D_OK;
+  };
+  if ((s = ev(d.log10_alpha_hi, &rho, &ratio))) return s;
+  if (std::fabs(ratio - 1.0) <= d.tol) return finish(d.log10_alpha_hi, 0);
+  if (rho < 0) return finish(d.log10_alpha_hi, FR3D_NOROOT_HIGH);
+  if ((s = ev(d.log10_alpha_lo, &rho, &ratio))) return s;
+  if (std::fabs(ratio - 1.0) <= d.tol) return finish(d.log10_alpha_lo, 0);
+  if (rho > 0) return finish(d.log10_alpha_lo, FR3D_NOROOT_LOW);
+  double a = d.log10_alpha_lo, b = d.log10_alpha_hi;
+  for (int k = 0; k < d.max_steps; ++k) {
+    t = 0.5 * (a + b);
+    if ((s = ev(t, &rho, &ratio))) return s;
+    if (std::fabs(ratio - 1.0) <= d.tol) return finish(t, 0);
+    if (rho < 0) a = t;
+    else b = t;
+  }
+  if (last_t != b && (s = ev(b, &rho, &ratio))) return s;
+  return finish(b, FR3D_MAXITER);
 }
 
 fr3d_status fr3d_apply_operator(fr3d_ctx* c, const void* zeta, void* F) {

@@ -116,7 +116,8 @@ __device__ __forceinline__ double lay_gain(int filt, int order, double lam, doub
 // One workgroup per distinct system, serving the frequencies ky = |ky| and
 // Py - |ky| (same A).  Mode 0 (search): w = A^T f^, b = V^T w, then for each
 // candidate x^ = V (h b), r^ = A x^ - f^ written as (x^, r^) pairs; mode 1
-// (forward operator): (A x^, 0).  FP64 arithmetic, T in and out.
+// (forward operator): (A x^, 0), or (A^T x^, 0) with a.adj.  FP64
+// arithmetic, T in and out.
 template <typename T, int MODE, bool KM>
 __global__ __launch_bounds__(LNT) void k_lay_filter(const c2<T>* __restrict__ B, c4<T>* __restrict__ W1, LayArgs la,
                                                      InvArgs a) {
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(LNT) void k_lay_filter(const c2<T>* __restrict__ B,
     if (act) {
       double2 y = make_double2(0.0, 0.0);
       for (int j = 0; j < M; ++j) {
-        const double k = ktv[i - j + M - 1];
+        const double k = a.adj ? ktv[j - i + M - 1] : ktv[i - j + M - 1];  // A^T or A
         y.x += k * fs[q][j].x;
         y.y += k * fs[q][j].y;
       }

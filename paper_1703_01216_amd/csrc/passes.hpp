@@ -84,6 +84,7 @@ struct InvArgs {
   // norm_part + j norm_stride; zeta is not written.  The passes of a
   // K-candidate step run only while the search is in that state, the passes
   // of a single evaluation only while it is not.
+  int adj;                  // forward-operator mode: 1 applies the adjoint (conjugate spectrum)
   int filt;                 // regularising filter: 0 Tikhonov, 1 iterated Tikhonov, 2 truncated SVD
   int order;                // order of iterated Tikhonov (>= 1)
   int kmode;

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 //             Tikhonov           g = 1/(s + a),                 e = a/(s + a)
 //             iterated, order m  g = sum_{j<m} q^j / (s + a),   e = q^m,  q = a/(s + a)
 //             truncated SVD      g = 1/s, e = 0 if s >= a;      g = 0, e = 1 otherwise
-//   MODE 1: u^ = k^ f^,  r^ = 0                                  (forward operator)
+//   MODE 1: u^ = k^ f^ (a.adj: conj(k^) f^, the adjoint),  r^ = 0  (forward operator)
 // transforms u^ and then r^ along z in the same LDS tile and writes z < nz
 // as (u, r) pairs.
 //
@@ -335,7 +335,8 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
       r = mk<T>((T)(fx * cr), (T)(fy * cr));
     } else {
-      u = mk<T>((T)(fx * kk.x - fy * kk.y), (T)(fx * kk.y + fy * kk.x));
+      const double kyv = a.adj ? -kk.y : kk.y;  // adjoint: conj(k^), the correlation with K
+      u = mk<T>((T)(fx * kk.x - fy * kyv), (T)(fx * kyv + fy * kk.x));
       r = mk<T>(0, 0);
     }
   };

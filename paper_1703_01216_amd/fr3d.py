@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfr3d.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE = 0, 1, 2, 3, 4
+CG_LIMIT = 32
 NOROOT_HIGH, NOROOT_LOW, MAXITER, NAN_INPUT, PRED_FALLBACK = 1, 2, 4, 8, 16
 
 EXPORTED = [
@@ -26,7 +27,7 @@ EXPORTED = [
     "fr3d_set_data", "fr3d_solve_alpha", "fr3d_solve_discrepancy", "fr3d_recover_c",
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
-    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered",
+    "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -98,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "fr3d_set_graphs": (I32, [P, I32]),
         "fr3d_set_filter": (I32, [P, I32, I32]),
         "fr3d_load_layered": (I32, [P, ctypes.POINTER(Geom)]),
+        "fr3d_solve_exact": (I32, [P, P, D, P, I32, D, ctypes.POINTER(Report)]),
+        "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
         "fr3d_solve_group": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
@@ -220,6 +223,21 @@ class Context:
         rep = Report()
         self._chk(self._lib.fr3d_solve_discrepancy(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
                                                    ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_exact(self, F, alpha, zeta, max_iter=2000, tol=1e-6):
+        """Tikhonov for the exact operator by CG (fr3d_solve_exact)."""
+        rep = Report()
+        self._chk(self._lib.fr3d_solve_exact(self._ctx, self._arr(F, "F"), float(alpha), self._arr(zeta, "zeta"),
+                                             int(max_iter), float(tol), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_exact_discrepancy(self, F, delta, zeta, max_iter=2000, tol=1e-6, opts: DpOpts | None = None, **kw):
+        o = opts if opts is not None else default_opts(**kw)
+        rep = Report()
+        self._chk(self._lib.fr3d_solve_exact_discrepancy(self._ctx, self._arr(F, "F"), float(delta), ctypes.byref(o),
+                                                         self._arr(zeta, "zeta"), int(max_iter), float(tol),
+                                                         ctypes.byref(rep)))
         return rep.as_dict()
 
     def recover_c(self, zeta, V0, c0, c_out):
