@@ -138,9 +138,15 @@ FR3D_PLAN(512, 3, 8, 8, 8)
 // ---------------------------------------------------------------- LDS tile transform
 // A tile holds NC pencils of length P in LDS.  COLFAST: element (col, p) at
 // p*LD + col (pencils interleaved, column index fastest); otherwise at
-// col*LD + p (pencils contiguous).  NT threads cooperate.
+// col*LD + rsw(p) (pencils contiguous, bank-skewed).  NT threads cooperate.
+// Row layout: element p of a pencil sits at p + p/16, so the stride-R
+// stores of a Stockham stage (R <= 16) fall on distinct LDS banks; the row
+// pitch LD must then be >= RowLD<P>.
+__device__ __forceinline__ int rsw(int p) { return p + (p >> 4); }
+template <int P> struct RowLD { static constexpr int value = P + P / 16 + 1; };
+
 template <bool COLFAST, int LD> __device__ __forceinline__ int tile_addr(int col, int p) {
-  return COLFAST ? p * LD + col : col * LD + p;
+  return COLFAST ? p * LD + col : col * LD + rsw(p);
 }
 
 template <typename T, int P, int NC, int LD, int NT, bool COLFAST, int DIR, int R, int NS>

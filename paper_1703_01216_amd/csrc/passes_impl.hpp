@@ -39,7 +39,7 @@ template <typename T, int P, bool GEN, int SH>
 __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __restrict__ A, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
   constexpr int C = TileC<T, P, SH>::C;  // complex pencils per tile = C, real rows = 2C
-  constexpr int LD = P + 1;
+  constexpr int LD = RowLD<P>::value;
   constexpr int N = P / 2;
   __shared__ c2<T> lds[C * LD];
   __shared__ c2<T> tw[P];
@@ -66,12 +66,12 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       const int e = tid + i * NT;
       if (PE::ok(e)) {
         const int r = e / N, x = e % N;
-        ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = v[i];
+        ldsr[2 * ((r >> 1) * LD + rsw(x)) + (r & 1)] = v[i];
       }
     }
     for (int e = tid; e < C * (P - N); e += NT) {
       const int c = e / (P - N), x = N + e % (P - N);
-      lds[c * LD + x] = mk<T>(0, 0);
+      lds[c * LD + rsw(x)] = mk<T>(0, 0);
     }
   } else {
     if (tid < P) tw[tid] = twv;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) && zok) {
         v = a.h * a.h * a.hz * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.hz);
       }
-      ldsr[2 * ((r >> 1) * LD + x) + (r & 1)] = (T)v;
+      ldsr[2 * ((r >> 1) * LD + rsw(x)) + (r & 1)] = (T)v;
     }
   }
   for (int m = tid + NT; m < P; m += NT) tw[m] = twg[m];
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
     const int y = y0 + yl;
     if (y >= a.ny_in) continue;
     const int c = yl >> 1;
-    const c2<T> Z = lds[c * LD + kx];
-    const c2<T> Zm = lds[c * LD + (P - kx) % P];
+    const c2<T> Z = lds[c * LD + rsw(kx)];
+    const c2<T> Zm = lds[c * LD + rsw((P - kx) % P)];
     c2<T> v;
     if ((yl & 1) == 0) v = mk<T>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
     else v = mk<T>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
@@ -111,7 +111,7 @@ template <typename T, int P, bool PRUNE, int SH>
 __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* __restrict__ B, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
   constexpr int C = TileC<T, P, SH>::C;
-  constexpr int LD = P + 1;
+  constexpr int LD = RowLD<P>::value;
   constexpr int NIN = PRUNE ? P / 2 : P;
   constexpr int TOT = C * NIN;
   using PE = Per<TOT>;
@@ -132,18 +132,18 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
 #pragma unroll
   for (int i = 0; i < PE::n; ++i) {
     const int e = tid + i * NT;
-    if (PE::ok(e)) lds[(e / NIN) * LD + e % NIN] = v[i];
+    if (PE::ok(e)) lds[(e / NIN) * LD + rsw(e % NIN)] = v[i];
   }
   if constexpr (PRUNE) {
     for (int e = tid; e < C * (P - NIN); e += NT) {
       const int r = e / (P - NIN), y = NIN + e % (P - NIN);
-      lds[r * LD + y] = mk<T>(0, 0);
+      lds[r * LD + rsw(y)] = mk<T>(0, 0);
     }
   }
   __syncthreads();
   tile_fft<T, P, C, LD, NT, false, -1>(lds, tw, tid);
   c2<T>* dst = B + row0 * P;
-  for (int e = tid; e < rows * P; e += NT) dst[e] = lds[(e / P) * LD + e % P];
+  for (int e = tid; e < rows * P; e += NT) dst[e] = lds[(e / P) * LD + rsw(e % P)];
 }
 
 // ============================================================ forward z pass
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
                                            const c2<T>* __restrict__ twg) {
   constexpr int C = TileC<T, P, SH + 1>::C;  // rows per tile (two pencils each)
   constexpr int NC = 2 * C;
-  constexpr int LD = P + 1;
+  constexpr int LD = RowLD<P>::value;
   constexpr int NOUT = P / 2;
   constexpr int TOT = C * P;
   using PE = Per<TOT>;
@@ -503,15 +503,15 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
     const int e = tid + i * NT;
     if (!PE::ok(e)) continue;
     const int r = e / P, y = e % P;
-    lds[(2 * r) * LD + y] = mk<T>(v[i].x, v[i].y);
-    lds[(2 * r + 1) * LD + y] = mk<T>(v[i].z, v[i].w);
+    lds[(2 * r) * LD + rsw(y)] = mk<T>(v[i].x, v[i].y);
+    lds[(2 * r + 1) * LD + rsw(y)] = mk<T>(v[i].z, v[i].w);
   }
   __syncthreads();
   tile_fft<T, P, NC, LD, NT, false, +1>(lds, tw, tid);
   c4<T>* dst = W2 + row0 * NOUT;
   for (int e = tid; e < rows * NOUT; e += NT) {
     const int r = e / NOUT, y = e % NOUT;
-    const c2<T> u = lds[(2 * r) * LD + y], w = lds[(2 * r + 1) * LD + y];
+    const c2<T> u = lds[(2 * r) * LD + rsw(y)], w = lds[(2 * r + 1) * LD + rsw(y)];
     c4<T> o;
     o.x = u.x; o.y = u.y; o.z = w.x; o.w = w.y;
     dst[e] = o;
