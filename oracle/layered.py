@@ -13,7 +13,9 @@ Readings (each also listed in the design notes):
   DFT of the wrapped lateral samples h^2 hz K(ox h, oy h, (D + dz) hz).  M = M' =
   nz.  K is even in x and y, so k~ and every A are real.
 * One alpha for all frequencies, chosen by the discrepancy principle on the
-  residual over Y (Sec. 4 rule applied to the whole data set).
+  residual over Y (Sec. 4 rule applied to the whole data set); or, reading
+  Algorithm 1 step 2 per frequency (``solve_per_frequency``), one alpha per
+  system by the same rule on that system's own residual.
 * Regularising algorithms (Sec. 5: standard and iterated Tikhonov, TSVD),
   through the SVD A = U S V^T with filter factors phi(s):
   Tikhonov s^2/(s^2 + a), iterated Tikhonov of order m 1 - (a/(s^2 + a))^m
@@ -144,3 +146,47 @@ def dense_layered(g: Geom, F, alpha: float, method: int = TIKHONOV):
     res = (C @ u - f).reshape(g.nz, py, px)
     u = u.reshape(g.nz, py, px)
     return dict(zeta=u[:, : g.ny, : g.nx], r=res[:, : g.ny, : g.nx])
+
+
+def solve_per_frequency(g: Geom, kt, F, delta: float, tau: float = 1.0, lo: float = -8.0, hi: float = 0.0,
+                        tol: float = 1e-3, max_steps: int = 40, method: int = TIKHONOV, order: int = 1):
+    """Algorithm 1 step 2 read per lateral frequency: every system gets its own
+    alpha, chosen by the plain discrepancy rule (bisection in log10 alpha) on
+    its own residual ||A x^ - f^|| against tau delta.  Units: the unnormalised
+    lateral DFT, in which white noise of norm delta on Y has expected energy
+    delta^2 at every frequency (Parseval: the PxPy frequencies carry PxPy
+    delta^2).  Returns dict(zeta, r, zeta_norm, r_norm, alphas [Py][Px],
+    flags [Py][Px])."""
+    from . import discrepancy
+    A = system_matrices(g, kt)
+    fh = np.moveaxis(lateral_spectrum(g, np.asarray(F, dtype=np.float64)), 0, 2)   # [Py][Px][nz]
+    py, px = fh.shape[:2]
+    U, S, Vt = np.linalg.svd(A)
+    xh = np.zeros_like(fh)
+    alphas = np.zeros((py, px))
+    flags = np.zeros((py, px), dtype=np.int64)
+    for iy in range(py):
+        for ix in range(px):
+            Am, f = A[iy, ix], fh[iy, ix]
+            b = U[iy, ix].T @ f
+
+            def solve(a):
+                phi = filter_factors(S[iy, ix], a, method, order)
+                gain = np.where(S[iy, ix] > 0, phi / np.where(S[iy, ix] > 0, S[iy, ix], 1.0), 0.0)
+                return Vt[iy, ix].T @ (gain * b)
+
+            def ev(a):
+                x = solve(a)
+                return float(np.linalg.norm(Am @ x - f)), float(np.linalg.norm(x))
+            res = discrepancy.bisection(ev, delta, lo=lo, hi=hi, max_steps=max_steps, tol=tol, tau=tau)
+            alphas[iy, ix] = res["alpha"]
+            flags[iy, ix] = res["flags"]
+            xh[iy, ix] = solve(res["alpha"])
+    rh = np.einsum("...ij,...j->...i", A, xh) - fh
+    xs = np.fft.ifft2(np.moveaxis(xh, 2, 0), axes=(1, 2))
+    rs = np.fft.ifft2(np.moveaxis(rh, 2, 0), axes=(1, 2))
+    zeta = xs.real[:, : g.ny, : g.nx]
+    r = rs.real[:, : g.ny, : g.nx]
+    return dict(zeta=zeta, r=r, zeta_norm=float(np.sqrt(np.sum(zeta * zeta))),
+                r_norm=float(np.sqrt(np.sum(r * r))), alphas=alphas, flags=flags,
+                imag_max=float(max(np.abs(xs.imag).max(), np.abs(rs.imag).max())))

@@ -719,3 +719,37 @@ def test_exact_cg_equals_dense_normal_equations(alpha):
         return float(np.sum((forward_direct(g, z) - F) ** 2) + alpha * np.sum(z * z))
     assert obj(de["zeta"]) <= obj(emb) * (1 + 1e-12)
     assert obj(de["zeta"]) <= obj(de["zeta"] + 1e-3 * inputs.rng(34).standard_normal(g.shape))
+
+
+def test_per_frequency_alphas_meet_their_discrepancy():
+    # Algorithm 1 step 2 per frequency: every system's alpha is re-checked by an
+    # independent dense normal-equation solve of that system (no SVD): inside
+    # the tolerance, or on the flagged side of the target at the range end.
+    g = Geom(4, 4, 5)
+    kt = layered.lateral_kernel_spectrum(g)
+    d = synth.make_data(g, inputs.xi_blobs(g.shape, 3, count=2, sigma=(1.0, 1.5)), inputs.noise(g.shape, 3), 0.05)
+    F, delta = d["F"], d["delta"]
+    out = layered.solve_per_frequency(g, kt, F, delta, tol=1e-6)
+    A = layered.system_matrices(g, kt)
+    fh = np.moveaxis(layered.lateral_spectrum(g, F), 0, 2)
+    seen = set()
+    for iy in range(A.shape[0]):
+        for ix in range(A.shape[1]):
+            a, fl = out["alphas"][iy, ix], out["flags"][iy, ix]
+            Am, f = A[iy, ix], fh[iy, ix]
+            x = np.linalg.solve(Am.T @ Am + a * np.eye(Am.shape[1]), Am.T @ f)
+            r = np.linalg.norm(Am @ x - f)
+            seen.add(int(fl))
+            if fl == 0:
+                assert abs(r / delta - 1) <= 1e-6 * (1 + 1e-6)
+            elif fl == discrepancy.NOROOT_HIGH:
+                assert a == 1.0 and r < delta
+            elif fl == discrepancy.NOROOT_LOW:
+                assert a == pytest.approx(1e-8) and r > delta
+    assert 0 in seen and len(seen) >= 2          # the case mix the data produce
+    assert out["imag_max"] < 1e-10 * np.abs(out["zeta"]).max()
+    # with one alpha everywhere the per-frequency form reduces to the global one
+    glob = layered.solve_layered(g, kt, F, 1e-3)
+    same = layered.solve_per_frequency(g, kt, F, 0.0, lo=-3.0, hi=-3.0 + 1e-12, tol=0.0, max_steps=0)
+    assert np.abs(same["alphas"] - 1e-3).max() < 1e-14
+    assert np.linalg.norm(same["zeta"] - glob["zeta"]) < 1e-12 * np.linalg.norm(glob["zeta"])
