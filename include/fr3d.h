@@ -214,6 +214,24 @@ fr3d_status fr3d_recover_c(fr3d_ctx* ctx, const void* zeta_dev, const void* V0_d
  * nz + 3G/4 with G = D - nz.  Writes nz*ny*nx values. */
 fr3d_status fr3d_source_potential(fr3d_ctx* ctx, double A0, void* V0_dev);
 
+/* Algorithm 1 step 2 read per lateral frequency (per-frequency systems only,
+ * after fr3d_load_layered and fr3d_set_data): every system gets its own
+ * alpha by the plain discrepancy rule of fr3d_solve_discrepancy (upper end,
+ * lower end, bisection in log10 alpha over opts' range, any point within
+ * opts.tol accepted) applied to its own residual ||A x^ - f^|| against
+ * tau delta, in unnormalised lateral-DFT units (white noise of norm delta on
+ * Y has expected energy delta^2 at every frequency); then one lateral
+ * inverse writes zeta on R.  alpha_dev (double [Px/2+1][Py]) and flags_dev
+ * (int32 [Px/2+1][Py]), if not NULL, receive each frequency's alpha (in
+ * the search's units, relative to s_max when the geometry says so) and
+ * flags.  rep: alpha = 10^(mean log10 alpha over all Px Py frequencies),
+ * residual = ||r||_Y and zeta_norm of the result, flags = OR of the
+ * per-frequency flags, n_evals = 1.  use_predictor, candidates and a
+ * nonzero h_op or mu are rejected (FR3D_E_INVALID); a context without the per-frequency systems or
+ * data gives FR3D_E_STATE; synchronises. */
+fr3d_status fr3d_solve_per_frequency(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev, double* alpha_dev,
+                                     int32_t* flags_dev, fr3d_report* rep);
+
 /* Tikhonov's method for the exact discrete operator A: L2(R) -> L2(Y) (the
  * quadrature of Eq. (8); Sec. 3's regularised normal solution, nothing on a
  * padded box): zeta = argmin ||A zeta - F||^2_Y + alpha ||zeta||^2_R, by

@@ -284,6 +284,8 @@ struct fr3d_ctx {
   double* cg_part = nullptr;
   double* cg_dev = nullptr;
   double* cg_host = nullptr;  // pinned
+  double* pf_part = nullptr;  // per-system partials of the per-frequency alpha search
+  size_t pf_cap = 0;
   bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
   hipStream_t cap_stream = nullptr; // stream the graphs are captured on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -946,6 +948,7 @@ fr3d_status fr3d_destroy(fr3d_ctx* c) {
   for (auto& e : c->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   dfree(c->cg_buf);
+  dfree(c->pf_part);
   dfree(c->cg_part);
   dfree(c->cg_dev);
   hfree(c->cg_host);
@@ -1506,6 +1509,73 @@ fr3d_status check_exact(fr3d_ctx* c, const void* F, void* zeta, int max_iter, do
 }  // namespace
 
 extern "C" {
+
+fr3d_status fr3d_solve_per_frequency(fr3d_ctx* c, const fr3d_dp_opts* o, void* zeta, double* alpha_dev,
+                                     int32_t* flags_dev, fr3d_report* rep) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, true)) return FR3D_E_STATE;
+  if (!c->layered) return fail(c, FR3D_E_STATE, "per-frequency alphas need the per-frequency systems (fr3d_load_layered)");
+  if (!zeta) return fail(c, FR3D_E_INVALID, "zeta is null");
+  fr3d_dp_opts d;
+  fr3d_status s = check_opts(c, o, &d);
+  if (s) return s;
+  if (d.use_predictor || d.candidates || d.h_op != 0 || d.mu != 0)
+    return fail(c, FR3D_E_INVALID, "the per-frequency search is the plain rule (no predictor, candidates, h_op or mu)");
+  Lane& L = c->lanes[0];
+  const size_t nf = (size_t)c->kxn * (c->py / 2 + 1);
+  if (c->pf_cap < nf) {
+    dfree(c->pf_part);
+    c->pf_cap = 0;
+    HIPCHK(c, hipMalloc(&c->pf_part, nf * 5 * sizeof(double)));
+    c->pf_cap = nf;
+  }
+  if ((s = fixed_search(c, L, 1.0, zeta))) return s;  // one spatial evaluation: norms and zeta on R
+  PfArgs pf{};
+  pf.target = d.tau * L.delta;
+  pf.a_scale = c->g.alpha_relative ? c->smax : 1.0;
+  pf.lo = d.log10_alpha_lo;
+  pf.hi = d.log10_alpha_hi;
+  pf.tol = d.tol;
+  pf.max_steps = d.max_steps;
+  pf.alpha_out = alpha_dev;
+  pf.flags_out = (int*)flags_dev;
+  pf.part = c->pf_part;
+  const bool dbl = c->esz == 8;
+  void *twx, *twy;
+  if ((s = get_twiddles(c, c->px, dbl, &twx)) || (s = get_twiddles(c, c->py, dbl, &twy))) return s;
+  InvArgs a = inv_args(c, L, true);
+  const Launch none{L.stream, nullptr, nullptr, 0};
+  Launch ly = none, lx = none;
+  ly.sh = c->tile_sh[4];
+  lx.sh = c->tile_sh[5];
+  if (dbl) {
+    Bufs<double> b = bufs<double>(c, L);
+    LCHK(c, launch_lay_pf<double>(b.S, b.W1, lay_args(c), a, pf, none));
+    LCHK(c, launch_iy<double>(c->py, b.W1, b.W2, a, (const c2<double>*)twy, ly));
+    LCHK(c, launch_ix<double>(c->px, 0, b.W2, (double*)nullptr, a, (const c2<double>*)twx, lx));
+  } else {
+    Bufs<float> b = bufs<float>(c, L);
+    LCHK(c, launch_lay_pf<float>(b.S, b.W1, lay_args(c), a, pf, none));
+    LCHK(c, launch_iy<float>(c->py, b.W1, b.W2, a, (const c2<float>*)twy, ly));
+    LCHK(c, launch_ix<float>(c->px, 0, b.W2, (float*)nullptr, a, (const c2<float>*)twx, lx));
+  }
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NT), 0, L.stream, (const double*)c->pf_part, (int)nf, 5, 5, L.scal);
+  LCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(L.scal_host, L.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+  if ((s = post_ctrl(c, L))) return s;
+  HIPCHK(c, hipEventSynchronize(L.ev));
+  if (L.ctrl_host->active) return fail(c, FR3D_E_DEVICE, "per-frequency evaluation did not finish");
+  if (rep) {
+    fill_report(*L.ctrl_host, rep);
+    const double* sc = L.scal_host;
+    rep->alpha = std::pow(10.0, sc[0] / sc[1]);
+    rep->delta = L.delta;
+    rep->target = pf.target;
+    rep->n_evals = 1;
+    rep->flags = (sc[2] > 0 ? FR3D_NOROOT_HIGH : 0) | (sc[3] > 0 ? FR3D_NOROOT_LOW : 0) | (sc[4] > 0 ? FR3D_MAXITER : 0);
+  }
+  return FR3D_OK;
+}
 
 fr3d_status fr3d_solve_exact(fr3d_ctx* c, const void* F, double alpha, void* zeta, int32_t max_iter, double tol,
                              fr3d_report* rep) {

@@ -231,6 +231,170 @@ __global__ __launch_bounds__(LNT) void k_lay_filter(const c2<T>* __restrict__ B,
   }
 }
 
+// Per-frequency alphas (see layered.hpp).  Wave 2q runs the search of the
+// system copy q (ky or Py - ky); the other waves wait at the barrier.
+template <typename T>
+__global__ __launch_bounds__(LNT) void k_lay_pf(const c2<T>* __restrict__ B, c4<T>* __restrict__ W1, LayArgs la,
+                                                 InvArgs a, PfArgs pf) {
+  __shared__ double Vs[LAY_MMAX * LAY_MMAX];
+  __shared__ double ls[LAY_MMAX];
+  __shared__ double ktv[2 * LAY_MMAX];
+  __shared__ double2 fs[2][LAY_MMAX], ws[2][LAY_MMAX], hb[2][LAY_MMAX], xs[2][LAY_MMAX];
+  __shared__ double b2[2][LAY_MMAX];
+  __shared__ double alph[2], tsel[2];
+  __shared__ int flg[2];
+  if (inv_idle(a)) return;
+  const int M = la.M, L = 2 * M - 1;
+  const int f = blockIdx.x;
+  const int kx = f / la.pyh, my = f % la.pyh;
+  const int nky = (my > 0 && 2 * my != la.py) ? 2 : 1;
+  const int tid = threadIdx.x;
+  for (int l = tid; l < L; l += LNT) ktv[l] = la.kt[(size_t)f * L + l];
+  {
+    constexpr int NV = (LAY_MMAX * LAY_MMAX + LNT - 1) / LNT;
+    const double* Vf = la.V + (size_t)f * M * M;
+    const int MM = M * M;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = tid + k * LNT;
+      v[k] = e < MM ? Vf[e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e = tid + k * LNT;
+      if (e < MM) Vs[e] = v[k];
+    }
+  }
+  for (int k = tid; k < M; k += LNT) ls[k] = la.lam[(size_t)f * M + k];
+  for (int e = tid; e < nky * M; e += LNT) {
+    const int q = e / M, i = e % M;
+    const int ky = q == 0 ? my : la.py - my;
+    const c2<T> v = B[((size_t)kx * M + i) * la.py + ky];
+    fs[q][i] = make_double2((double)v.x, (double)v.y);
+  }
+  __syncthreads();
+  const int q = tid / 128, i = tid % 128;
+  const bool act = q < nky && i < M;
+  const int ky = q == 0 ? my : la.py - my;
+  if (act) {  // w = A^T f
+    double2 s = make_double2(0.0, 0.0);
+    for (int r = 0; r < M; ++r) {
+      const double k = ktv[r - i + M - 1];
+      s.x += k * fs[q][r].x;
+      s.y += k * fs[q][r].y;
+    }
+    ws[q][i] = s;
+  }
+  __syncthreads();
+  double2 bk = make_double2(0.0, 0.0);  // b = V^T w
+  if (act) {
+    for (int r = 0; r < M; ++r) {
+      const double v = Vs[r * M + i];
+      bk.x += v * ws[q][r].x;
+      bk.y += v * ws[q][r].y;
+    }
+    b2[q][i] = bk.x * bk.x + bk.y * bk.y;
+  }
+  __syncthreads();
+  if (i < 64 && q < nky) {  // the search, one wave per system copy
+    const int lane = i;
+    double ff = 0.0;
+    for (int k = lane; k < M; k += 64) ff += fs[q][k].x * fs[q][k].x + fs[q][k].y * fs[q][k].y;
+    ff = wave_sum<double>(ff);
+    const double T2 = pf.target * pf.target;
+    auto rho_ratio = [&](double t, double& rho, double& ratio) {
+      const double aa = pow(10.0, t) * pf.a_scale;
+      double s = 0.0;
+      for (int k = lane; k < M; k += 64) {
+        const double lam = ls[k];
+        const double h = lay_gain(a.filt, a.order, lam, aa);
+        s += (2.0 * h - lam * h * h) * b2[q][k];
+      }
+      s = wave_sum<double>(s);
+      const double r2 = fmax(ff - s, 0.0);
+      rho = r2 - T2;
+      ratio = T2 > 0 ? sqrt(r2) / pf.target : INFINITY;
+    };
+    double rho, ratio, t = pf.hi;
+    int fl = 0;
+    bool done = false;
+    rho_ratio(pf.hi, rho, ratio);
+    if (fabs(ratio - 1.0) <= pf.tol) done = true;
+    else if (rho < 0) { fl = F_NOROOT_HIGH; done = true; }
+    if (!done) {
+      t = pf.lo;
+      rho_ratio(pf.lo, rho, ratio);
+      if (fabs(ratio - 1.0) <= pf.tol) done = true;
+      else if (rho > 0) { fl = F_NOROOT_LOW; done = true; }
+    }
+    if (!done) {
+      double lo = pf.lo, hi = pf.hi;
+      for (int st = 0; st < pf.max_steps && !done; ++st) {
+        t = 0.5 * (lo + hi);
+        rho_ratio(t, rho, ratio);
+        if (fabs(ratio - 1.0) <= pf.tol) done = true;
+        else if (rho < 0) lo = t;
+        else hi = t;
+      }
+      if (!done) { t = hi; fl = F_MAXITER; }
+    }
+    if (lane == 0) {
+      tsel[q] = t;
+      alph[q] = pow(10.0, t) * pf.a_scale;
+      flg[q] = fl;
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const double h = lay_gain(a.filt, a.order, ls[i], alph[q]);
+    hb[q][i] = make_double2(h * bk.x, h * bk.y);
+  }
+  __syncthreads();
+  if (act) {  // x = V (h b)
+    double2 x = make_double2(0.0, 0.0);
+    for (int k = 0; k < M; ++k) {
+      const double v = Vs[i * M + k];
+      x.x += v * hb[q][k].x;
+      x.y += v * hb[q][k].y;
+    }
+    xs[q][i] = x;
+  }
+  __syncthreads();
+  if (act) {  // r = A x - f
+    double2 r = make_double2(-fs[q][i].x, -fs[q][i].y);
+    for (int j = 0; j < M; ++j) {
+      const double k = ktv[i - j + M - 1];
+      r.x += k * xs[q][j].x;
+      r.y += k * xs[q][j].y;
+    }
+    c4<T> o;
+    o.x = (T)xs[q][i].x; o.y = (T)xs[q][i].y; o.z = (T)r.x; o.w = (T)r.y;
+    W1[((size_t)kx * M + i) * la.py + ky] = o;
+  }
+  if (tid == 0) {
+    // counts over the full Px x Py spectrum: columns 0 < kx < Px/2 stand for
+    // their mirror images too
+    const double wx = (kx > 0 && kx != la.kxn - 1) ? 2.0 : 1.0;
+    double sl = 0.0, nh = 0.0, nl = 0.0, nm = 0.0;
+    for (int c = 0; c < nky; ++c) {
+      sl += wx * tsel[c];
+      nh += wx * (flg[c] == F_NOROOT_HIGH);
+      nl += wx * (flg[c] == F_NOROOT_LOW);
+      nm += wx * (flg[c] == F_MAXITER);
+      const int kyc = c == 0 ? my : la.py - my;
+      if (pf.alpha_out) pf.alpha_out[(size_t)kx * la.py + kyc] = pow(10.0, tsel[c]);
+      if (pf.flags_out) pf.flags_out[(size_t)kx * la.py + kyc] = flg[c];
+    }
+    double* pp = pf.part + (size_t)5 * f;
+    pp[0] = sl;
+    pp[1] = wx * nky;
+    pp[2] = nh;
+    pp[3] = nl;
+    pp[4] = nm;
+  }
+}
+
 __global__ __launch_bounds__(LNT) void k_lay_max_part(const double* __restrict__ lam, long long n, double* part) {
   __shared__ double red[LNT / 64];
   double m = 0.0;
@@ -297,6 +461,17 @@ hipError_t launch_lay_max(const double* lam, long long n, double* part, double* 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_lay_pf(const c2<T>* B, c4<T>* W1, const LayArgs& la, const InvArgs& a, const PfArgs& pf,
+                         const Launch& L) {
+  if (la.M < 1 || la.M > LAY_MMAX) return hipErrorInvalidValue;
+  return go_lay(k_lay_pf<T>, dim3((unsigned)(la.kxn * la.pyh)), L, B, W1, la, a, pf);
+}
+
+template hipError_t launch_lay_pf<float>(const c2<float>*, c4<float>*, const LayArgs&, const InvArgs&,
+                                         const PfArgs&, const Launch&);
+template hipError_t launch_lay_pf<double>(const c2<double>*, c4<double>*, const LayArgs&, const InvArgs&,
+                                          const PfArgs&, const Launch&);
 template hipError_t launch_lay_filter<float>(int, const c2<float>*, c4<float>*, const LayArgs&, const InvArgs&,
                                              const Launch&);
 template hipError_t launch_lay_filter<double>(int, const c2<double>*, c4<double>*, const LayArgs&, const InvArgs&,

@@ -45,6 +45,27 @@ template <typename T>
 hipError_t launch_lay_filter(int mode, const c2<T>* B, c4<T>* W1, const LayArgs& la, const InvArgs& a,
                              const Launch& L);
 
+// Per-frequency alphas (Algorithm 1 step 2 read per lateral frequency): for
+// each frequency, the plain discrepancy rule (upper end, lower end, then
+// bisection in log10 alpha, any point within tol accepted) on that system's
+// residual ||A x^ - f^||, evaluated in closed form from the SVD,
+//   ||A x - f||^2 = ||f||^2 - sum_k (2 h_k - s_k^2 h_k^2) |b_k|^2,
+// against target = tau delta (unnormalised lateral DFT units); then that
+// frequency's (x^, r^) as in k_lay_filter.  Per system partials
+// part[5 f + (0..4)] = (sum log10 alpha, frequencies, NOROOT_HIGH count,
+// NOROOT_LOW count, MAXITER count), counted over the full Px x Py spectrum;
+// alpha_out / flags_out [Kx][Py] optional.
+struct PfArgs {
+  double target, a_scale, lo, hi, tol;
+  int max_steps;
+  double* alpha_out;
+  int* flags_out;
+  double* part;
+};
+template <typename T>
+hipError_t launch_lay_pf(const c2<T>* B, c4<T>* W1, const LayArgs& la, const InvArgs& a, const PfArgs& pf,
+                         const Launch& L);
+
 // max lam (the squared operator norm) into *out (device), via partials.
 hipError_t launch_lay_max(const double* lam, long long n, double* part, double* out, hipStream_t s);
 

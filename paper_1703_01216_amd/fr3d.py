@@ -28,6 +28,7 @@ EXPORTED = [
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
+    "fr3d_solve_per_frequency",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_set_filter": (I32, [P, I32, I32]),
         "fr3d_load_layered": (I32, [P, ctypes.POINTER(Geom)]),
         "fr3d_solve_exact": (I32, [P, P, D, P, I32, D, ctypes.POINTER(Report)]),
+        "fr3d_solve_per_frequency": (I32, [P, ctypes.POINTER(DpOpts), P, P, P, ctypes.POINTER(Report)]),
         "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
@@ -223,6 +225,15 @@ class Context:
         rep = Report()
         self._chk(self._lib.fr3d_solve_discrepancy(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
                                                    ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_per_frequency(self, zeta, alphas=None, flags=None, opts: DpOpts | None = None, **kw):
+        """One alpha per lateral frequency (fr3d_solve_per_frequency); alphas
+        (float64) and flags (int32), if given, are cuda tensors of Kx x Py."""
+        o = opts if opts is not None else default_opts(**kw)
+        rep = Report()
+        self._chk(self._lib.fr3d_solve_per_frequency(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
+                                                     _ptr(alphas), _ptr(flags), ctypes.byref(rep)))
         return rep.as_dict()
 
     def solve_exact(self, F, alpha, zeta, max_iter=2000, tol=1e-6):

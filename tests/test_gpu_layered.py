@@ -166,3 +166,115 @@ def test_layered_versus_3d_embedding(fr3d):
     assert np.isfinite(gap) and gap > 0
     # both fit the data on Y to the same order at this alpha
     assert 1 / 1.5 <= rl["residual"] / r3["residual"] <= 1.5
+
+
+def _pf_case(fr3d, g, seed, delta_rel, precision, **kw):
+    d = instance(g, seed, delta_rel)
+    c = ctx_layered(fr3d, g, precision)
+    F = dev(d["F"], precision)
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    kxn = g.pshape[2] // 2 + 1
+    al = torch.zeros((kxn, g.pshape[1]), dtype=torch.float64, device="cuda")
+    fl = torch.zeros((kxn, g.pshape[1]), dtype=torch.int32, device="cuda")
+    rep = c.solve_per_frequency(z, al, fl, **kw)
+    ref = layered.solve_per_frequency(g, layered.lateral_kernel_spectrum(g), d["F"], d["delta"], **kw)
+    # library [kx][ky] for kx <= Px/2 against the oracle's [ky][kx]
+    return c, d, z, rep, ref, host(al), fl.cpu().numpy(), ref["alphas"][:, :kxn].T, ref["flags"][:, :kxn].T
+
+
+@pytest.mark.parametrize("shape,seed,delta_rel", [((16, 16, 12), 45, 0.01), ((12, 8, 7), 46, 0.05),
+                                                  ((24, 12, 9), 47, 0.02)])
+def test_per_frequency_alphas_fp64_match_oracle(fr3d, shape, seed, delta_rel):
+    # Algorithm 1 step 2 per lateral frequency: the same plain rule on every
+    # system; every decision, alpha and flag agrees, and the estimate within
+    # the SVD-route bar of the smallest alpha chosen
+    g = geom(*shape)
+    c, d, z, rep, ref, al, fl, ral, rfl = _pf_case(fr3d, g, seed, delta_rel, 64)
+    assert np.array_equal(fl, rfl)
+    assert np.allclose(al, ral, rtol=1e-12, atol=0)
+    assert len(set(rfl.ravel().tolist())) >= 2          # several outcomes among the systems
+    bar = 1e-9 * max(1.0, c.get_smax() / ral.min() / 1e6)
+    assert rel_l2(host(z), ref["zeta"]) < bar
+    assert rep["residual"] == pytest.approx(ref["r_norm"], rel=bar)
+    assert rep["zeta_norm"] == pytest.approx(ref["zeta_norm"], rel=bar)
+    assert rep["alpha"] == pytest.approx(10.0 ** np.log10(ref["alphas"]).mean(), rel=1e-12)
+    want = 0
+    for v in np.unique(ref["flags"]):
+        want |= int(v)
+    assert rep["flags"] == want and rep["n_evals"] == 1
+
+
+@pytest.mark.parametrize("filt", [1, 2])
+def test_per_frequency_filters_fp64_match_oracle(fr3d, filt):
+    # the same rule with the iterated-Tikhonov (order 3) and TSVD filters
+    g = geom(12, 12, 8)
+    d = instance(g, 48, 0.02)
+    c = ctx_layered(fr3d, g, 64)
+    c.set_filter(filt, 3 if filt == 1 else 1)
+    F = dev(d["F"], 64)
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    kxn = g.pshape[2] // 2 + 1
+    al = torch.zeros((kxn, g.pshape[1]), dtype=torch.float64, device="cuda")
+    fl = torch.zeros((kxn, g.pshape[1]), dtype=torch.int32, device="cuda")
+    c.solve_per_frequency(z, al, fl)
+    ref = layered.solve_per_frequency(g, layered.lateral_kernel_spectrum(g), d["F"], d["delta"], method=filt,
+                                      order=3 if filt == 1 else 1)
+    assert np.array_equal(fl.cpu().numpy(), ref["flags"][:, :kxn].T)
+    assert np.allclose(host(al), ref["alphas"][:, :kxn].T, rtol=1e-12, atol=0)
+    bar = 1e-9 * max(1.0, c.get_smax() / ref["alphas"].min() / 1e6)
+    assert rel_l2(host(z), ref["zeta"]) < bar
+
+
+def test_per_frequency_fp32_bisection_to_the_end(fr3d):
+    # FP32: with tol = 0 every search bisects to the end, so a decision that
+    # FP32 rounding flips (rho within rounding of zero) moves the final alpha
+    # only by the last interval, and the alphas differ by the shift of each
+    # system's root: a relative error u in its residual moves log10 alpha by
+    # u / s, s = d ln||r|| / d log10 alpha at the root (computed here by
+    # dense solves of the system).  The FP32 spectrum carries u <~ 1e-5 of
+    # the per-frequency residual (the transform's rounding, ~1e-7 of ||F||,
+    # against residuals ~delta = 2e-2 ||F||).  The estimate moves less
+    # than 1e-4: large shifts belong to flat residuals, whose x barely moves.
+    g = geom(16, 16, 12)
+    kw = dict(tol=0.0, max_steps=40)
+    c, d, z, rep, ref, al, fl, ral, rfl = _pf_case(fr3d, g, 49, 0.02, 32, **kw)
+    ends = rfl != discrepancy.MAXITER
+    assert np.array_equal(fl[ends], rfl[ends]) and np.all(fl[~ends] == discrepancy.MAXITER)
+    assert np.allclose(al[ends], ral[ends], rtol=1e-14, atol=0)
+    A = layered.system_matrices(g, layered.lateral_kernel_spectrum(g))
+    fh = np.moveaxis(layered.lateral_spectrum(g, d["F"]), 0, 2)
+    for kx, ky in zip(*np.nonzero(~ends)):
+        Am, f = A[ky, kx], fh[ky, kx]
+
+        def lnr(t):
+            x = np.linalg.solve(Am.T @ Am + 10.0 ** t * np.eye(Am.shape[1]), Am.T @ f)
+            return np.log(np.linalg.norm(Am @ x - f))
+        t = np.log10(ral[kx, ky])
+        slope = (lnr(t + 1e-4) - lnr(t - 1e-4)) / 2e-4
+        assert abs(np.log10(al[kx, ky]) - t) <= 1e-5 / slope + 1e-10, (kx, ky, slope)
+    assert rel_l2(host(z), ref["zeta"]) < 1e-4
+
+
+def test_per_frequency_single_alpha_equals_global_and_errors(fr3d):
+    # a range of width ~0 pins every system to one alpha: the global estimate
+    g = geom(12, 12, 8)
+    d = instance(g, 50, 0.02)
+    c = ctx_layered(fr3d, g, 64)
+    F = dev(d["F"], 64)
+    c.set_data(F, d["delta"])
+    z1, z2 = torch.empty_like(F), torch.empty_like(F)
+    c.solve_per_frequency(z1, log10_alpha_lo=-3.0, log10_alpha_hi=-3.0 + 1e-12, tol=0.0, max_steps=0)
+    c.solve_alpha(1e-3, z2)
+    assert rel_l2(host(z1), host(z2)) < 1e-11
+    for kw in ({"candidates": 4}, {"h_op": 0.1}, {"mu": 0.1}):
+        with pytest.raises(fr3d.Fr3dError) as ei:
+            c.solve_per_frequency(z1, **kw)
+        assert ei.value.status == fr3d.E_INVALID
+    c3 = fr3d.Context()
+    c3.load_kernel(12, 12, 8, precision=64)
+    c3.set_data(F, d["delta"])
+    with pytest.raises(fr3d.Fr3dError) as ei:
+        c3.solve_per_frequency(z1)
+    assert ei.value.status == fr3d.E_STATE
