@@ -328,7 +328,7 @@ def main():
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
-    ap.add_argument("--modes", default="learned,bisection,learned_w,bisection_w,kary16")
+    ap.add_argument("--modes", default="learned,bisection,learned_walk,learned_w,bisection_w,kary16")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
@@ -360,17 +360,24 @@ def main():
     modes = args.modes.split(",")
     if "learned" in modes:
         if not os.path.exists(args.predictor):
-            print(f"[bench] no predictor at {args.predictor}; skipping the learned search", file=sys.stderr)
-            modes.remove("learned")
+            print(f"[bench] no predictor at {args.predictor}; skipping the learned searches", file=sys.stderr)
+            modes = [m for m in modes if not m.startswith("learned")]
         else:
             ctx.predictor_load(args.predictor)
     Fs, deltas, V0 = make_instances(ctx, torch, n, args.batch)
     print(f"[bench] {len(Fs)} instances of {n}^3 ready", file=sys.stderr, flush=True)
     tight = dict(tol=1e-3, accept_lo=1 - 1e-3, accept_hi=1 + 1e-3)
     wide = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
-    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **tight),
+    # the secant refinement after the seed assumes the median slope of ln r at
+    # the root measured on training instances (recorded beside the checkpoint)
+    meta_path = os.path.splitext(args.predictor)[0] + ".json"
+    slope = 0.0
+    if os.path.exists(meta_path):
+        slope = float(json.load(open(meta_path)).get("root_slope", {}).get("median", 0.0))
+    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, seed_slope=slope, **tight),
+                 "learned_walk": fr3d.default_opts(use_predictor=1, **tight),
                  "bisection": fr3d.default_opts(**tight),
-                 "learned_w": fr3d.default_opts(use_predictor=1, **wide),
+                 "learned_w": fr3d.default_opts(use_predictor=1, seed_slope=slope, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
     for m in modes:
         if m.startswith("kary"):  # kary<K>: the K-candidate search

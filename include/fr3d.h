@@ -88,6 +88,8 @@ typedef struct {
   int32_t use_predictor;                 /* 1: seed the search with the alpha predictor */
   double seed_walk;                      /* first walk step from the seed in decades, default 0.25 */
   int32_t candidates;                    /* K = 2..16: K-candidate search (K alphas per step); 0: off */
+  double seed_slope;                     /* > 0: secant refinement after the seed with this assumed
+                                            d ln(r/T) / d log10 alpha; 0 (default): the walk */
 } fr3d_dp_opts;
 
 typedef struct {
@@ -164,7 +166,9 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
  * use_predictor: start from the predicted alpha (accepted inside [accept_lo,
  * accept_hi] or within tol), walk toward the sign change with doubling steps
  * from seed_walk decades, then Illinois regula falsi on r/T - 1 inside the
- * bracket.  With candidates = K (2..16, not with use_predictor, max_steps >= 1):
+ * bracket; with seed_slope > 0 instead secant steps on ln(r/T), the first
+ * with the slope seed_slope per decade, later ones through the last two
+ * points, regula falsi (Illinois) when a step would leave a known bracket.  With candidates = K (2..16, not with use_predictor, max_steps >= 1):
  * each step evaluates K alphas in one set of launches, the first step at K
  * points from lo to hi, later steps at the K interior points of the current
  * bracket (log-spaced); the candidate closest to the target within tol is

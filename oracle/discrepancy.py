@@ -29,6 +29,10 @@ Seeded search (a predicted t0 from the alpha predictor; not in the paper):
   that survives two steps in a row is halved), at most max_steps points;
   otherwise alpha = 10^b, MAXITER.  PRED_FALLBACK is set whenever the first
   point is not accepted.
+  Secant refinement (``seeded_secant``): after the seed, steps on
+  g = ln(r/T): the first with an assumed slope of g per decade, later ones
+  through the last two points, regula falsi (Illinois) whenever a step would
+  leave a known bracket; range ends and the step limit as above.
 
 K-candidate search (K alphas per step, log-spaced in the current bracket; not
 in the paper -- the batched form of the same rule):
@@ -159,6 +163,78 @@ def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=
     if ev.last_t != b:
         ev(b)
     return out(b, flags | MAXITER)
+
+
+def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=0.9, acc_hi=1.1,
+                  tau=1.0, h_op=0.0, mu=0.0, slope=0.03):
+    """Seeded search refined by secant steps on g(t) = ln(r / T) (a proposal
+    for the learned path; the paper has no predictor).  From the seed the
+    first step is Newton's with the assumed slope ``slope`` of g per decade
+    of alpha; later steps take the slope through the last two points (the
+    assumed one when that is not positive).  Once points on both sides of
+    the target are known, a step that leaves the bracket is replaced by the
+    regula falsi point, with the Illinois halving of an end kept twice.
+    A point at hi below the target ends with NOROOT_HIGH, one at lo above it
+    with NOROOT_LOW; after max_steps steps the answer is the upper bracket
+    end (MAXITER), evaluated if it was not the last point."""
+    ev = _Counter(evaluate, delta, tau, h_op, mu)
+
+    def ok(ratio):
+        return acc_lo <= ratio <= acc_hi or abs(ratio - 1.0) <= tol
+
+    def out(t, flags):
+        return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace)
+
+    def lg(ratio):
+        # ln(r / T), kept finite
+        return min(max(math.log(ratio), -50.0), 50.0) if ratio > 0 else -50.0
+
+    t = min(max(float(t0), lo), hi)
+    rho, ratio, _, _ = ev(t)
+    if ok(ratio):
+        return out(t, 0)
+    flags = PRED_FALLBACK
+    g = lg(ratio)
+    a = b = ga = gb = None
+    side = 0
+    prev = None
+    steps = 0
+    while True:
+        if rho < 0:                               # below the target: alpha too small
+            if t >= hi:
+                return out(hi, flags | NOROOT_HIGH)
+            if a is not None and b is not None:
+                if side == -1:
+                    gb *= 0.5
+                side = -1
+            a, ga = t, g
+        else:
+            if t <= lo:
+                return out(lo, flags | NOROOT_LOW)
+            if a is not None and b is not None:
+                if side == 1:
+                    ga *= 0.5
+                side = 1
+            b, gb = t, g
+        if steps >= max_steps:
+            tb = b if b is not None else t
+            if ev.last_t != tb:
+                ev(tb)
+            return out(tb, flags | MAXITER)
+        s = (g - prev[1]) / (t - prev[0]) if prev is not None and t != prev[0] else 0.0
+        if not s > 0:
+            s = slope
+        tn = t - g / s
+        if a is not None and b is not None and not a < tn < b:
+            tn = a - ga * (b - a) / (gb - ga)
+        tn = min(max(tn, lo), hi)
+        prev = (t, g)
+        t = tn
+        rho, ratio, _, _ = ev(t)
+        steps += 1
+        if ok(ratio):
+            return out(t, flags)
+        g = lg(ratio)
 
 
 def kary(evaluate, delta, K=16, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, tau=1.0, h_op=0.0, mu=0.0):

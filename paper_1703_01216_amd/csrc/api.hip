@@ -688,7 +688,7 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
-      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk))
+      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
@@ -725,6 +725,7 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   v.h_op = d.h_op;
   v.mu = d.mu;
   v.walk = d.seed_walk;
+  v.slope = d.seed_slope;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -743,10 +744,14 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
     *max_evals = d.max_steps;  // each evaluation call: one K-candidate step, then the answer once found
   } else if (d.use_predictor) {
     LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream));
-    // seed + doubling walk across the range + regula falsi + final re-evaluation
-    int walk = 0;
-    for (double w = d.seed_walk, span = 0; span < d.log10_alpha_hi - d.log10_alpha_lo; w *= 2) { span += w; ++walk; }
-    *max_evals = 1 + walk + d.max_steps + 1;
+    if (d.seed_slope > 0) {
+      *max_evals = 1 + d.max_steps + 1;  // seed + secant steps + final re-evaluation
+    } else {
+      // seed + doubling walk across the range + regula falsi + final re-evaluation
+      int walk = 0;
+      for (double w = d.seed_walk, span = 0; span < d.log10_alpha_hi - d.log10_alpha_lo; w *= 2) { span += w; ++walk; }
+      *max_evals = 1 + walk + d.max_steps + 1;
+    }
   } else {
     *max_evals = 2 + d.max_steps + 1;
   }
@@ -898,6 +903,7 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->mu = 0.0;
   o->use_predictor = 0;
   o->seed_walk = 0.25;
+  o->seed_slope = 0.0;
   o->candidates = 0;
 }
 

@@ -23,6 +23,11 @@
 // sign change with steps walk, 2 walk, 4 walk, ... (NOROOT at a range end),
 // then regula falsi on g = r/T - 1 inside the bracket with the Illinois
 // modification (the value kept at an end that survives two steps is halved).
+// Secant refinement (slope > 0): after the seed, steps on g = ln(r/T), the
+// first with the assumed slope of g per decade, later ones through the last
+// two points (the assumed slope when that is not positive); a step that
+// would leave a known bracket becomes the regula falsi point (Illinois);
+// NOROOT at a range end, MAXITER after max_steps steps (answer b).
 // K-candidate search: each step evaluates K alphas at once (the pass kernels
 // take the candidate from the grid), step 1 at K points from lo to hi, later
 // steps at the K interior points of the bracket (spaced (b - a)/(K + 1)).
@@ -51,6 +56,7 @@ enum : int32_t {
   ST_DONE = 9,
   ST_KARY = 10,   // evaluating K candidates
   ST_KFINAL = 11, // evaluating the answer of the K-candidate search
+  ST_SECANT = 12, // secant refinement of the seeded search
 };
 
 constexpr int KMAX = 16;  // candidates per step of the K-candidate search
@@ -71,6 +77,8 @@ struct Ctrl {
   double ga, gb;     // r/T - 1 at the bracket ends (seeded search)
   double prev_t, prev_g, wstep;
   int32_t side, up;
+  double slope;      // assumed d ln(r/T) / d log10 alpha of the secant refinement (0: walk)
+  int32_t have;      // secant refinement: bit 0 a known, bit 1 b known, bit 2 previous point known
   // K-candidate search
   int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer
   double ct[KMAX];          // log10 alpha of each candidate
@@ -152,6 +160,46 @@ __device__ inline void ctrl_advance_k(Ctrl* c, const double* r2, const double* z
   ctrl_kary_points(c);
 }
 
+// One step of the secant refinement after an evaluation at c->t that was not
+// accepted (rho and r/T of that evaluation).
+__device__ inline void ctrl_secant(Ctrl* c, double rho, double ratio) {
+  const double g = ratio > 0 ? fmin(fmax(log(ratio), -50.0), 50.0) : -50.0;
+  if (rho < 0) {
+    if (c->t >= c->hi) { ctrl_finish(c, F_NOROOT_HIGH); return; }
+    if ((c->have & 3) == 3) {
+      if (c->side == -1) c->gb *= 0.5;
+      c->side = -1;
+    }
+    c->a = c->t; c->ga = g; c->have |= 1;
+  } else {
+    if (c->t <= c->lo) { ctrl_finish(c, F_NOROOT_LOW); return; }
+    if ((c->have & 3) == 3) {
+      if (c->side == 1) c->ga *= 0.5;
+      c->side = 1;
+    }
+    c->b = c->t; c->gb = g; c->have |= 2;
+  }
+  if (c->steps >= c->max_steps) {
+    const double tb = (c->have & 2) ? c->b : c->t;
+    if (tb == c->t) { ctrl_finish(c, F_MAXITER); return; }
+    c->state = ST_FINAL;
+    ctrl_set_t(c, tb);
+    return;
+  }
+  double s = 0.0;
+  if ((c->have & 4) && c->t != c->prev_t) s = (g - c->prev_g) / (c->t - c->prev_t);
+  if (!(s > 0)) s = c->slope;
+  double tn = c->t - g / s;
+  if ((c->have & 3) == 3 && !(c->a < tn && tn < c->b)) tn = c->a - c->ga * (c->b - c->a) / (c->gb - c->ga);
+  tn = fmin(fmax(tn, c->lo), c->hi);
+  c->prev_t = c->t;
+  c->prev_g = g;
+  c->have |= 4;
+  c->steps += 1;
+  c->state = ST_SECANT;
+  ctrl_set_t(c, tn);
+}
+
 // Advance after an evaluation at c->t with ||r||^2 = r2 and ||zeta||^2 = z2.
 __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
   c->r2 = r2;
@@ -205,6 +253,14 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
     case ST_WALK: {
       const double g = ratio - 1.0;
       if (in_window || fabs(g) <= c->tol) { ctrl_finish(c, 0); return; }
+      if (c->state == ST_SEED && c->slope > 0) {
+        c->flags |= F_PRED_FALLBACK;
+        c->have = 0;
+        c->side = 0;
+        c->steps = 0;
+        ctrl_secant(c, rho, ratio);
+        return;
+      }
       if (c->state == ST_SEED) {
         c->flags |= F_PRED_FALLBACK;
         c->wstep = c->walk;
@@ -230,6 +286,10 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
       ctrl_set_t(c, c->up ? fmin(c->t + c->wstep, c->hi) : fmax(c->t - c->wstep, c->lo));
       return;
     }
+    case ST_SECANT:
+      if (in_window || fabs(ratio - 1.0) <= c->tol) { ctrl_finish(c, 0); return; }
+      ctrl_secant(c, rho, ratio);
+      return;
     case ST_FALSI: {
       const double g = ratio - 1.0;
       if (in_window || fabs(g) <= c->tol) { ctrl_finish(c, 0); return; }

@@ -258,6 +258,14 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 // transforms u^ and then r^ along z in the same LDS tile and writes z < nz
 // as (u, r) pairs.
 //
+// 1/x for normal positive x: the hardware estimate refined by two Newton
+// steps r <- r + r (1 - x r), within an ulp of the quotient.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Octant reuse: rows kz and P-kz need the same octant entry (conjugated), so
 // each thread loads f^ for such a pair of rows and the octant entry once;
 // tiles t and ntile-1-t of a plane need mirrored octant columns, so they are
@@ -315,10 +323,10 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const double s = kk.x * kk.x + kk.y * kk.y;
       double gu, cr;
       if (a.filt == 0) {
-        gu = 1.0 / (s + aa);
+        gu = recip(s + aa);
         cr = -aa * gu;
       } else if (a.filt == 1) {
-        const double d = 1.0 / (s + aa), q = aa * d;
+        const double d = recip(s + aa), q = aa * d;
         double qp = 1.0, sum = 1.0;
         for (int j = 1; j < a.order; ++j) {
           qp *= q;
@@ -328,7 +336,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         cr = -(qp * q);
       } else {
         const bool keep = s >= aa;
-        gu = keep ? 1.0 / s : 0.0;
+        gu = keep ? recip(s) : 0.0;
         cr = keep ? 0.0 : -1.0;
       }
       const double cx = kk.x * gu, cy = -kk.y * gu;  // conj(k^) g

@@ -140,6 +140,42 @@ def fit(X_tr, t_tr, X_va, t_va, epochs=150, batch=256, lr=1e-3, seed=1, log=prin
     return ctx, hist
 
 
+def root_slopes(indices, h=0.05, log=print):
+    """d ln r / d log10 alpha at the discrepancy root of workload-5 instances
+    (central difference over +-h decades around the root found by the batch
+    solver to 1e-6); instances without a root inside the range are skipped.
+    The median is the assumed slope of the seeded search's secant refinement."""
+    import numpy as np
+    import torch
+
+    recipes = {i: inputs.workload_params(5, i) for i in indices}
+    groups = {}
+    for i, r in recipes.items():
+        groups.setdefault((r["shape"][0], r["q"]), []).append(i)
+    out = []
+    for (n, q), idx in sorted(groups.items()):
+        ctx = fr3d.Context()
+        ctx.load_kernel(n, n, n, q=q, precision=32)
+        V0 = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+        ctx.source_potential(V0)
+        Fs, deltas = synthesize(ctx, torch, [recipes[i] for i in idx], V0)
+        z = torch.empty_like(Fs[0])
+        for F, d in zip(Fs, deltas):
+            ctx.set_data(F, d)
+            rep = ctx.solve_discrepancy(z, tol=1e-6, max_steps=60)
+            if rep["flags"] != 0:
+                continue
+            t = math.log10(rep["alpha"])
+            rp = ctx.solve_alpha(10.0 ** (t + h), z)["residual"]
+            rm = ctx.solve_alpha(10.0 ** (t - h), z)["residual"]
+            out.append((math.log(rp) - math.log(rm)) / (2 * h))
+        log(f"[slope] n={n} q={q}: {len(idx)} instances")
+        ctx.close()
+        del V0, Fs
+        torch.cuda.empty_cache()
+    return np.array(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--instances", type=int, default=20000)
@@ -148,14 +184,28 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_CKPT)
     ap.add_argument("--first-index", type=int, default=0)
     ap.add_argument("--label-tol", type=float, default=1e-6)
+    ap.add_argument("--root-slope", type=int, default=0,
+                    help="only measure the residual slope at the root on this many training instances and "
+                         "record its median in the checkpoint's JSON summary")
     args = ap.parse_args(argv)
     import numpy as np
     import torch
 
     torch.cuda.set_device(0)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    meta_path = os.path.splitext(args.out)[0] + ".json"
+    if args.root_slope:
+        sl = root_slopes(list(range(args.first_index, args.first_index + args.root_slope)), log=log)
+        summary = json.load(open(meta_path)) if os.path.exists(meta_path) else {}
+        summary["root_slope"] = dict(median=float(np.median(sl)), q25=float(np.percentile(sl, 25)),
+                                     q75=float(np.percentile(sl, 75)), instances=int(sl.size),
+                                     first_index=args.first_index)
+        with open(meta_path, "w") as fh:
+            json.dump(summary, fh, indent=1)
+        log(json.dumps(summary["root_slope"]))
+        return
     n = args.instances
     idx = list(range(args.first_index, args.first_index + n))
-    log = lambda m: print(m, flush=True)  # noqa: E731
     X, t, meta = label_groups(idx, lanes=args.lanes, log=log, tol=args.label_tol)
     n_va = max(1, n // 20)
     n_te = max(1, n // 20)
@@ -175,7 +225,7 @@ def main(argv=None):
                    label_flags={str(k): int((flags == k).sum()) for k in sorted(set(flags.tolist()))},
                    label_mean_evals=float(np.mean([meta[i]["n_evals"] for i in idx])),
                    last=hist[-1])
-    with open(os.path.splitext(args.out)[0] + ".json", "w") as fh:
+    with open(meta_path, "w") as fh:
         json.dump(summary, fh, indent=1)
     log(json.dumps(summary))
 

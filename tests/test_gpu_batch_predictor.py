@@ -183,6 +183,39 @@ def test_predictor_checkpoint(fr3d, tmp_path):
     assert ei.value.status == fr3d.E_INVALID
 
 
+@pytest.mark.parametrize("bias,slope,tol", [(-3.0, 0.05, 1e-3), (-6.5, 0.5, 1e-6), (0.7, 0.2, 1e-3),
+                                             (-20.0, 0.03, 1e-3), (-1.0, 2.0, 1e-9)])
+def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol):
+    # the secant refinement after the seed takes the oracle rule's decisions
+    # (FP64, same evaluations), including the range ends and MAXITER
+    g = geom(16, 16, 16)
+    d = instance(g, 71, 0.02)
+    c = fr3d.Context()
+    c.load_kernel(16, 16, 16, precision=64)
+    p = mlp.init_params(13)
+    for k in ("W1", "W2", "w3"):
+        p[k] = p[k] * 0.0
+    p["b3"][:] = bias
+    c.predictor_set(flat_params(p), identity_norm())
+    F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    kw = dict(tol=tol, accept_lo=1.0, accept_hi=1.0, max_steps=6)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, **kw)
+    khat = np.fft.fftn(sample_kernel(g))
+
+    def ev(a):
+        o = tikhonov.solve_spectral(g, khat, d["F"], a)
+        return o["r_norm"], o["zeta_norm"]
+    ref = discrepancy.seeded_secant(ev, d["delta"], bias, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
+                                    slope=slope)
+    assert rep["flags"] == ref["flags"]
+    assert rep["n_evals"] == ref["n_evals"]
+    assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+    o = tikhonov.solve_spectral(g, khat, d["F"], ref["alpha"])
+    assert rel_l2(host(z), o["zeta"]) < 1e-11
+
+
 @pytest.mark.parametrize("bias", [-3.0, -6.5, 0.7, -20.0])
 def test_seeded_search_matches_rule_fp64(fr3d, bias):
     # The network's output is steered by its last bias; the device search from

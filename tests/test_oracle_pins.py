@@ -439,6 +439,60 @@ def test_seeded_search():
     assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.NOROOT_HIGH and res["alpha"] == 1.0
 
 
+def _loglinear(t_star, s):
+    # residual with ln(r/delta) = s (log10 alpha - t_star) exactly
+    return lambda a: (math.exp(s * (math.log10(a) - t_star)), 1.0)
+
+
+def test_seeded_secant_steps():
+    # Newton with the true slope lands on the root; with twice the slope it
+    # stops halfway and the secant through the two points (exact for a
+    # straight line) lands on it next
+    for s_true, s_assumed, n in ((0.05, 0.05, 2), (0.05, 0.1, 3), (0.7, 0.35, 3)):
+        res = discrepancy.seeded_secant(_loglinear(-3.2, s_true), 1.0, -2.1, tol=1e-9, acc_lo=1.0, acc_hi=1.0,
+                                        slope=s_assumed)
+        assert res["flags"] == discrepancy.PRED_FALLBACK and res["n_evals"] == n
+        assert res["t"] == pytest.approx(-3.2, abs=1e-9)
+        ts = [t for t, *_ in res["trace"]]
+        assert ts[1] == pytest.approx(-2.1 - s_true * (-2.1 + 3.2) / s_assumed, abs=1e-12)
+    # the identity kernel's closed-form root from seeds on both sides
+    ev, delta, Fn = _identity_problem(0.03)
+    t_star = math.log10(delta / (Fn - delta))
+    for off in (-3.3, 2.7, 0.4, -0.2):
+        res = discrepancy.seeded_secant(ev, delta, t_star + off, tol=1e-9, acc_lo=1.0, acc_hi=1.0, slope=0.5)
+        assert res["flags"] == discrepancy.PRED_FALLBACK
+        assert res["alpha"] == pytest.approx(10 ** t_star, rel=1e-7)
+        assert res["n_evals"] < 15
+    # a seed inside the window is accepted at once
+    res = discrepancy.seeded_secant(ev, delta, t_star + 1e-4, slope=0.5)
+    assert res["flags"] == 0 and res["n_evals"] == 1
+
+
+def test_seeded_secant_range_ends_and_step_limit():
+    # the root lies below lo: the first step clips to lo, rho(lo) > 0
+    tight = dict(tol=1e-3, acc_lo=1.0, acc_hi=1.0)
+    res = discrepancy.seeded_secant(_loglinear(-9.0, 0.1), 1.0, -5.0, slope=0.1, **tight)
+    assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.NOROOT_LOW
+    assert res["alpha"] == 1e-8 and res["n_evals"] == 2
+    # above hi
+    res = discrepancy.seeded_secant(_loglinear(0.5, 0.1), 1.0, -1.0, slope=0.1, **tight)
+    assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.NOROOT_HIGH
+    assert res["alpha"] == 1.0 and res["n_evals"] == 2
+    # a tenfold slope overestimate and one step: MAXITER at the upper end,
+    # which is the last point (no extra evaluation)
+    res = discrepancy.seeded_secant(_loglinear(-3.0, 0.5), 1.0, -2.0, tol=1e-6, acc_lo=1.0, acc_hi=1.0,
+                                    slope=5.0, max_steps=1)
+    assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.MAXITER
+    assert res["t"] == pytest.approx(-2.1) and res["n_evals"] == 2
+    # the bracket safeguard: an extrapolation past a known end becomes the
+    # regula falsi point, so every point after the bracket stays inside it
+    res = discrepancy.seeded_secant(_loglinear(-3.0, 0.5), 1.0, -1.0, tol=1e-9, acc_lo=1.0, acc_hi=1.0,
+                                    slope=0.05)
+    ts = [t for t, *_ in res["trace"]]
+    assert ts[1] == -8.0 and all(-8.0 < t < -1.0 for t in ts[2:])
+    assert res["t"] == pytest.approx(-3.0, abs=1e-9)
+
+
 def test_seeded_matches_bisection_answer_quality():
     # same acceptance band: both searches end inside it
     ev, delta, Fn = _identity_problem(0.02)
