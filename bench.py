@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "regularized 3D solves/sec at 256^3 to discrepancy delta, learned-alpha vs bisection"
 HBM_PEAK_GBS = 8000.0
+CAL_FIRST = 100000  # first instance index of the seed calibration set (disjoint from the timed batch)
 PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
@@ -69,12 +70,12 @@ def pass_bytes(n, esz=4):
     }
 
 
-def make_instances(ctx, torch, n, batch):
+def make_instances(ctx, torch, n, batch, first=0):
     from paper_1703_01216_amd import inputs
     V0 = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
     ctx.source_potential(V0, 1.0)
     Fs, deltas = [], []
-    for i in range(batch):
+    for i in range(first, first + batch):
         seed = inputs.instance_seed(2, i)
         xi = inputs.xi_torch((n, n, n), inputs.inclusion_params((n, n, n), seed))
         F = torch.empty_like(xi)
@@ -329,6 +330,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
     ap.add_argument("--modes", default="learned,bisection,learned_walk,learned_w,bisection_w,kary16")
+    ap.add_argument("--calibrate", type=int, default=48,
+                    help="instances (not timed) that calibrate the learned seed for this geometry; 0: none")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
@@ -370,14 +373,24 @@ def main():
     wide = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
     # the secant refinement after the seed assumes the median slope of ln r at
     # the root measured on training instances (recorded beside the checkpoint)
-    meta_path = os.path.splitext(args.predictor)[0] + ".json"
-    slope = 0.0
-    if os.path.exists(meta_path):
-        slope = float(json.load(open(meta_path)).get("root_slope", {}).get("median", 0.0))
-    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, seed_slope=slope, **tight),
+    # the learned searches: the network's seed calibrated for this geometry
+    # on instances of the same recipe that are not timed (indices from
+    # CAL_FIRST), then the secant refinement with the calibrated slope
+    sk, cal = {}, None
+    if any(m.startswith("learned") for m in modes) and args.calibrate:
+        from paper_1703_01216_amd import calibrate
+        t0c = time.perf_counter()
+        Fc, dc, _ = make_instances(ctx, torch, n, args.calibrate, first=CAL_FIRST)
+        cal = calibrate.seed_calibration(ctx, Fc, dc)
+        cal["seconds"] = time.perf_counter() - t0c
+        cal["first_index"] = CAL_FIRST
+        del Fc
+        sk = {k: cal[k] for k in ("seed_shift", "seed_shift_x", "seed_slope", "seed_slope_x")}
+        print(f"[bench] seed calibration: {cal}", file=sys.stderr, flush=True)
+    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
                  "learned_walk": fr3d.default_opts(use_predictor=1, **tight),
                  "bisection": fr3d.default_opts(**tight),
-                 "learned_w": fr3d.default_opts(use_predictor=1, seed_slope=slope, **wide),
+                 "learned_w": fr3d.default_opts(use_predictor=1, **sk, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
     for m in modes:
         if m.startswith("kary"):  # kary<K>: the K-candidate search
@@ -425,7 +438,7 @@ def main():
                    "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
                    "graphs": bool(args.graphs),
                    "tile_shifts": tuning,
-                   "modes": results},
+                   "modes": results, "seed_calibration": cal},
         "roofline": roofline,
         "passes": passes,
         "copy": copy,

@@ -90,6 +90,11 @@ typedef struct {
   int32_t candidates;                    /* K = 2..16: K-candidate search (K alphas per step); 0: off */
   double seed_slope;                     /* > 0: secant refinement after the seed with this assumed
                                             d ln(r/T) / d log10 alpha; 0 (default): the walk */
+  double seed_slope_x;                   /* with seed_slope > 0: the slope is seed_slope
+                                            10^(seed_slope_x x_64), clamped to [1e-4, 1e3] (x_64 =
+                                            log10(delta/||F||), the noise feature); default 0 */
+  double seed_shift, seed_shift_x;       /* seed = clip(prediction + seed_shift + seed_shift_x x_64) in
+                                            decades (a calibration for one geometry); default 0, 0 */
 } fr3d_dp_opts;
 
 typedef struct {

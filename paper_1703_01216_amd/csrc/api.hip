@@ -688,7 +688,8 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
-      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope))
+      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x) ||
+      !std::isfinite(d->seed_shift) || !std::isfinite(d->seed_shift_x))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
@@ -726,6 +727,9 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   v.mu = d.mu;
   v.walk = d.seed_walk;
   v.slope = d.seed_slope;
+  v.slope_x = d.seed_slope_x;
+  v.shift = d.seed_shift;
+  v.shift_x = d.seed_shift_x;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -904,6 +908,9 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->use_predictor = 0;
   o->seed_walk = 0.25;
   o->seed_slope = 0.0;
+  o->seed_slope_x = 0.0;
+  o->seed_shift = 0.0;
+  o->seed_shift_x = 0.0;
   o->candidates = 0;
 }
 

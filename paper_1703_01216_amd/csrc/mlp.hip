@@ -117,10 +117,14 @@ __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, con
       const float la = norm[2 * MLP_IN] + norm[2 * MLP_IN + 1] * y;
       if (out) out[b] = la;
       if (seed && b == 0) {
-        const double t = fmin(fmax((double)la, seed->lo), seed->hi);
+        // calibrated seed and secant slope (x_64 = log10(delta/||F||), the noise feature)
+        const double x64 = (double)X[MLP_IN - 1];
+        const double t = fmin(fmax((double)la + seed->shift + seed->shift_x * x64, seed->lo), seed->hi);
         seed->t = t;
         seed->alpha_abs = pow(10.0, t) * seed->a_scale;
         seed->state = ST_SEED;
+        if (seed->slope > 0 && seed->slope_x != 0)
+          seed->slope = fmin(fmax(seed->slope * pow(10.0, seed->slope_x * x64), 1e-4), 1e3);
       }
     }
   }

@@ -51,7 +51,9 @@ class DpOpts(ctypes.Structure):
                 ("accept_lo", ctypes.c_double), ("accept_hi", ctypes.c_double),
                 ("tau", ctypes.c_double), ("h_op", ctypes.c_double), ("mu", ctypes.c_double),
                 ("use_predictor", ctypes.c_int32), ("seed_walk", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("seed_slope", ctypes.c_double)]
+                ("candidates", ctypes.c_int32), ("seed_slope", ctypes.c_double),
+                ("seed_slope_x", ctypes.c_double), ("seed_shift", ctypes.c_double),
+                ("seed_shift_x", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):

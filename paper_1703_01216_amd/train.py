@@ -140,11 +140,13 @@ def fit(X_tr, t_tr, X_va, t_va, epochs=150, batch=256, lr=1e-3, seed=1, log=prin
     return ctx, hist
 
 
-def root_slopes(indices, h=0.05, log=print):
+def root_slopes(indices, ckpt, h=0.05, log=print):
     """d ln r / d log10 alpha at the discrepancy root of workload-5 instances
     (central difference over +-h decades around the root found by the batch
-    solver to 1e-6); instances without a root inside the range are skipped.
-    The median is the assumed slope of the seeded search's secant refinement."""
+    solver to 1e-6), with the predictor's clipped seed t0 and the noise
+    feature x_64 of each; instances without a root inside the range are
+    skipped.  Their median is the default slope of the seeded search's secant
+    refinement (calibrate.py fits one geometry more closely)."""
     import numpy as np
     import torch
 
@@ -152,28 +154,34 @@ def root_slopes(indices, h=0.05, log=print):
     groups = {}
     for i, r in recipes.items():
         groups.setdefault((r["shape"][0], r["q"]), []).append(i)
-    out = []
+    rows = []
     for (n, q), idx in sorted(groups.items()):
         ctx = fr3d.Context()
         ctx.load_kernel(n, n, n, q=q, precision=32)
+        ctx.predictor_load(ckpt)
         V0 = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
         ctx.source_potential(V0)
         Fs, deltas = synthesize(ctx, torch, [recipes[i] for i in idx], V0)
         z = torch.empty_like(Fs[0])
+        y = torch.empty(1, dtype=torch.float32, device="cuda")
         for F, d in zip(Fs, deltas):
             ctx.set_data(F, d)
+            feat, _ = ctx.get_features()
+            ctx.predictor_forward(feat.view(1, 65).contiguous(), y)
+            t0 = min(max(float(y[0]), -8.0), 0.0)
+            x64 = float(feat[64])
             rep = ctx.solve_discrepancy(z, tol=1e-6, max_steps=60)
             if rep["flags"] != 0:
                 continue
             t = math.log10(rep["alpha"])
             rp = ctx.solve_alpha(10.0 ** (t + h), z)["residual"]
             rm = ctx.solve_alpha(10.0 ** (t - h), z)["residual"]
-            out.append((math.log(rp) - math.log(rm)) / (2 * h))
+            rows.append((t0, x64, (math.log(rp) - math.log(rm)) / (2 * h)))
         log(f"[slope] n={n} q={q}: {len(idx)} instances")
         ctx.close()
         del V0, Fs
         torch.cuda.empty_cache()
-    return np.array(out)
+    return np.array(rows)
 
 
 def main(argv=None):
@@ -184,6 +192,7 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_CKPT)
     ap.add_argument("--first-index", type=int, default=0)
     ap.add_argument("--label-tol", type=float, default=1e-6)
+    ap.add_argument("--predictor", default=DEFAULT_CKPT, help="checkpoint whose seeds the slope model uses")
     ap.add_argument("--root-slope", type=int, default=0,
                     help="only measure the residual slope at the root on this many training instances and "
                          "record its median in the checkpoint's JSON summary")
@@ -195,7 +204,9 @@ def main(argv=None):
     log = lambda m: print(m, flush=True)  # noqa: E731
     meta_path = os.path.splitext(args.out)[0] + ".json"
     if args.root_slope:
-        sl = root_slopes(list(range(args.first_index, args.first_index + args.root_slope)), log=log)
+        rows = root_slopes(list(range(args.first_index, args.first_index + args.root_slope)), args.predictor,
+                           log=log)
+        sl = rows[:, 2]
         summary = json.load(open(meta_path)) if os.path.exists(meta_path) else {}
         summary["root_slope"] = dict(median=float(np.median(sl)), q25=float(np.percentile(sl, 25)),
                                      q75=float(np.percentile(sl, 75)), instances=int(sl.size),

@@ -183,9 +183,10 @@ def test_predictor_checkpoint(fr3d, tmp_path):
     assert ei.value.status == fr3d.E_INVALID
 
 
-@pytest.mark.parametrize("bias,slope,tol", [(-3.0, 0.05, 1e-3), (-6.5, 0.5, 1e-6), (0.7, 0.2, 1e-3),
-                                             (-20.0, 0.03, 1e-3), (-1.0, 2.0, 1e-9)])
-def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol):
+@pytest.mark.parametrize("bias,slope,tol,shift", [(-3.0, 0.05, 1e-3, 0.0), (-6.5, 0.5, 1e-6, 0.0),
+                                                   (0.7, 0.2, 1e-3, 0.0), (-20.0, 0.03, 1e-3, 0.0),
+                                                   (-1.0, 2.0, 1e-9, 0.0), (-3.0, 0.3, 1e-6, -0.75)])
+def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
     # the secant refinement after the seed takes the oracle rule's decisions
     # (FP64, same evaluations), including the range ends and MAXITER
     g = geom(16, 16, 16)
@@ -201,13 +202,14 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol):
     c.set_data(F, d["delta"])
     z = torch.empty_like(F)
     kw = dict(tol=tol, accept_lo=1.0, accept_hi=1.0, max_steps=6)
-    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, **kw)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, seed_shift=shift, **kw)
     khat = np.fft.fftn(sample_kernel(g))
 
     def ev(a):
         o = tikhonov.solve_spectral(g, khat, d["F"], a)
         return o["r_norm"], o["zeta_norm"]
-    ref = discrepancy.seeded_secant(ev, d["delta"], bias, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
+    # a seed shift moves the network's output before the clip to the range
+    ref = discrepancy.seeded_secant(ev, d["delta"], bias + shift, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
                                     slope=slope)
     assert rep["flags"] == ref["flags"]
     assert rep["n_evals"] == ref["n_evals"]
