@@ -29,7 +29,52 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// The prediction la (log10 alpha) of row 0 as the first point of a seeded
+// search: calibrated seed and secant slope (x_64 = log10(delta/||F||), the
+// noise feature).
+__device__ __forceinline__ void write_seed(Ctrl* seed, float la, const float* X) {
+  const double x64 = (double)X[MLP_IN - 1];
+  const double t = fmin(fmax((double)la + seed->shift + seed->shift_x * x64, seed->lo), seed->hi);
+  seed->t = t;
+  seed->alpha_abs = pow(10.0, t) * seed->a_scale;
+  seed->state = ST_SEED;
+  if (seed->slope > 0 && seed->slope_x != 0)
+    seed->slope = fmin(fmax(seed->slope * pow(10.0, seed->slope_x * x64), 1e-4), 1e3);
+}
+
 // ------------------------------------------------------------------ forward
+// One row (the seed of a search): the same products (bf16 operands, FP32
+// sums) as matrix-vector products over a whole workgroup -- two threads per
+// output unit -- instead of one wavefront with 16-row matrix tiles, 15 of
+// whose rows would be empty.
+__global__ __launch_bounds__(256) void k_mlp_fwd1(const float* __restrict__ p, const float* __restrict__ norm,
+                                                  const float* __restrict__ X, float* __restrict__ out, Ctrl* seed) {
+  __shared__ float xs[MLP_IN], h1[MLP_H], h2[MLP_H], red[4];
+  const int tid = threadIdx.x, j = tid >> 1, hf = tid & 1;
+  if (tid < MLP_IN) xs[tid] = rbf((X[tid] - norm[tid]) / norm[MLP_IN + tid]);
+  __syncthreads();
+  float s = 0.0f;
+  for (int k = hf; k < MLP_IN; k += 2) s += rbf(p[OFF_W1 + j * MLP_IN + k]) * xs[k];
+  s += __shfl_xor(s, 1, 64);
+  if (hf == 0) h1[j] = rbf(gelu(s + p[OFF_B1 + j]));
+  __syncthreads();
+  s = 0.0f;
+  for (int k = hf; k < MLP_H; k += 2) s += rbf(p[OFF_W2 + j * MLP_H + k]) * h1[k];
+  s += __shfl_xor(s, 1, 64);
+  if (hf == 0) h2[j] = rbf(gelu(s + p[OFF_B2 + j]));
+  __syncthreads();
+  float v = tid < MLP_H ? h2[tid] * rbf(p[OFF_W3 + tid]) : 0.0f;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    const float y = (red[0] + red[1] + red[2] + red[3]) + p[OFF_B3];
+    const float la = norm[2 * MLP_IN] + norm[2 * MLP_IN + 1] * y;
+    if (out) out[0] = la;
+    if (seed) write_seed(seed, la, X);
+  }
+}
+
 // One wavefront per 16 batch rows.
 __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, const float* __restrict__ norm,
                                                 const float* __restrict__ X, int B, float* __restrict__ out,
@@ -116,16 +161,7 @@ __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, con
       if (train) w.y[b] = y;
       const float la = norm[2 * MLP_IN] + norm[2 * MLP_IN + 1] * y;
       if (out) out[b] = la;
-      if (seed && b == 0) {
-        // calibrated seed and secant slope (x_64 = log10(delta/||F||), the noise feature)
-        const double x64 = (double)X[MLP_IN - 1];
-        const double t = fmin(fmax((double)la + seed->shift + seed->shift_x * x64, seed->lo), seed->hi);
-        seed->t = t;
-        seed->alpha_abs = pow(10.0, t) * seed->a_scale;
-        seed->state = ST_SEED;
-        if (seed->slope > 0 && seed->slope_x != 0)
-          seed->slope = fmin(fmax(seed->slope * pow(10.0, seed->slope_x * x64), 1e-4), 1e3);
-      }
+      if (seed && b == 0) write_seed(seed, la, X);
     }
   }
 }
@@ -288,6 +324,10 @@ void mlp_work_carve(MlpWork* w, void* base, int cap) {
 hipError_t mlp_forward(const float* params, const float* norm, const float* X, int B, float* out, MlpWork* w,
                        Ctrl* seed, hipStream_t s) {
   if (B <= 0 || (w && B > w->cap) || (seed && B != 1)) return hipErrorInvalidValue;
+  if (seed && !w) {
+    hipLaunchKernelGGL(k_mlp_fwd1, dim3(1), dim3(256), 0, s, params, norm, X, out, seed);
+    return hipGetLastError();
+  }
   MlpWork dummy{};
   hipLaunchKernelGGL(k_mlp_fwd, dim3((B + 15) / 16), dim3(64), 0, s, params, norm, X, B, out, w ? *w : dummy,
                      w ? 1 : 0, seed);

@@ -7,11 +7,14 @@
   tensor); Adam against its formula; checkpoint round trip; the seeded search
   takes the oracle rule's decisions (FP64 path).
 """
+import math
+
 import numpy as np
 import pytest
 
-from oracle import discrepancy, mlp, tikhonov
+from oracle import discrepancy, features, mlp, tikhonov
 from oracle.geometry import sample_kernel
+from oracle.operator import pad
 
 from gpu_helpers import geom, instance, rel_l2
 
@@ -113,6 +116,32 @@ def test_predictor_forward_matches_oracle(fr3d):
     c.predictor_forward(torch.tensor(X, device="cuda"), y)
     yo2, _ = mlp.forward(p32, (X.astype(np.float64) - 0.5) / 2.0, bf16=True)
     assert rel_l2(host(y), -4.0 + 1.5 * yo2) < 2e-3
+
+
+def test_seed_matches_oracle_network(fr3d):
+    # the single-row kernel that seeds a search computes the same network:
+    # with the whole range open and any ratio accepted, the search returns
+    # 10^(network output on the data's features), features and network
+    # from the oracle
+    p = mlp.init_params(5)
+    flat = flat_params(p)
+    p32 = unflat(flat)
+    g = geom(24, 16, 12)
+    d = instance(g, 72, 0.03)
+    c = fr3d.Context()
+    c.load_kernel(24, 16, 12, precision=64)
+    nm = identity_norm()
+    nm[130], nm[131] = -4.0, 1.5
+    c.predictor_set(flat, nm)
+    F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    rep = c.solve_discrepancy(z, use_predictor=1, accept_lo=0.0, accept_hi=1e300, log10_alpha_lo=-60.0,
+                              log10_alpha_hi=60.0)
+    assert rep["n_evals"] == 1 and rep["flags"] == 0
+    x, _ = features.features(np.fft.fftn(pad(g, d["F"])), d["delta"], np.linalg.norm(d["F"]))
+    yo, _ = mlp.forward(p32, np.asarray(x, dtype=np.float64)[None, :], bf16=True)
+    assert math.log10(rep["alpha"]) == pytest.approx(-4.0 + 1.5 * float(yo[0]), abs=2e-3)
 
 
 def test_predictor_gradients_match_oracle(fr3d):
