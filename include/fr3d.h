@@ -134,6 +134,18 @@ fr3d_status fr3d_set_lanes(fr3d_ctx* ctx, int32_t lanes);
  * set earlier. */
 fr3d_status fr3d_load_kernel(fr3d_ctx* ctx, const fr3d_geom* geom);
 
+/* The same with the caller's kernel table instead of the sampled kernel of
+ * Sec. 3 (the circulant embedding of Sec. 5 with any kernel that is real
+ * and even in x and y): k_dev (device, FP64, read during the call only)
+ * holds the wrapped samples k[c][b][a], Pz x Py x Px with a fastest, that is
+ * the weight of the pair of cells whose offset is (a, b, c) modulo P, as in
+ * (A zeta)[y] = sum_r k[(y - r) mod P] zeta[r], including the cell volume.
+ * geom gives nx, ny, nz, precision and alpha_relative (kind is not used; h,
+ * hz, D and q only place the point sources of fr3d_source_potential).
+ * Samples that are not finite, all zero or not even in x and y (relative
+ * deviation above 1e-12) give FR3D_E_INVALID and leave no kernel loaded. */
+fr3d_status fr3d_load_kernel_samples(fr3d_ctx* ctx, const fr3d_geom* geom, const double* k_dev);
+
 /* Algorithm 1 as run in Sec. 5: load the geometry for the lateral 2D
  * transform and per-frequency dense z-systems of Eq. (14) instead of the 3D
  * embedding.  Lateral axes are zero-padded to 2n (the exact discrete lateral

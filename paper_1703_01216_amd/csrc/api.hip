@@ -989,7 +989,48 @@ fr3d_status fr3d_set_lanes(fr3d_ctx* c, int32_t lanes) {
   return ensure_lanes(c);
 }
 
-fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
+// Per-workgroup largest deviation of the samples from evenness in x and y
+// (part[b]) and largest magnitude (part[nb + b]).
+__global__ void k_even_dev(const double* __restrict__ k, int px, int py, int pz, double* part) {
+  __shared__ double rd[NT], rm[NT];
+  double dev = 0.0, mag = 0.0;
+  const long long n = (long long)px * py * pz;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += (long long)gridDim.x * NT) {
+    const int x = (int)(e % px), y = (int)((e / px) % py);
+    const long long z = e / ((long long)px * py);
+    const double v = k[e];
+    const double vx = k[(z * py + y) * px + (px - x) % px];
+    const double vy = k[(z * py + (py - y) % py) * px + x];
+    dev = fmax(dev, fmax(fabs(v - vx), fabs(v - vy)));
+    mag = fmax(mag, fabs(v));
+  }
+  rd[threadIdx.x] = dev;
+  rm[threadIdx.x] = mag;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + s]);
+      rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rd[0];
+    part[gridDim.x + blockIdx.x] = rm[0];
+  }
+}
+
+fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc);
+
+fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) { return load_kernel_impl(c, g, nullptr); }
+
+fr3d_status fr3d_load_kernel_samples(fr3d_ctx* c, const fr3d_geom* g, const double* k_dev) {
+  if (!c) return FR3D_E_INVALID;
+  if (!k_dev) return fail(c, FR3D_E_INVALID, "k_dev is null");
+  return load_kernel_impl(c, g, k_dev);
+}
+
+fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc) {
   if (!c) return FR3D_E_INVALID;
   if (!g) return fail(c, FR3D_E_INVALID, "geom is null");
   if (g->nx < 2 || g->ny < 2 || g->nz < 2) return fail(c, FR3D_E_INVALID, "grid extents must be >= 2");
@@ -1020,8 +1061,32 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
   c->bins_part_n = (size_t)kxn * c->py + 64;  // >= workgroups of the z pass (tile pairs, padded grid)
   c->norm_part_n = (size_t)g->nz * g->ny;  // >= workgroups of the x pass
   const size_t noct = kxn * (c->pz / 2 + 1) * (c->py / 2 + 1);
-  HIPCHK(c, hipMalloc(&c->oct, noct * sizeof(double2)));
   fr3d_status st;
+  if (ksrc) {
+    // the octant form needs a real table even in x and y
+    Lane& Lv = c->lanes[0];
+    constexpr int nb = 512;
+    double* part = nullptr;
+    HIPCHK(c, hipMalloc(&part, 2 * nb * sizeof(double)));
+    hipLaunchKernelGGL(k_even_dev, dim3(nb), dim3(NT), 0, Lv.stream, ksrc, c->px, c->py, c->pz, part);
+    hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(NT), 0, Lv.stream, (const double*)part, nb, Lv.scal);
+    hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(NT), 0, Lv.stream, (const double*)(part + nb), nb, Lv.scal + 1);
+    hipError_t ev = hipGetLastError();
+    if (ev == hipSuccess) ev = hipMemcpyAsync(Lv.scal_host, Lv.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, Lv.stream);
+    if (ev == hipSuccess) ev = hipStreamSynchronize(Lv.stream);
+    (void)hipFree(part);
+    if (ev != hipSuccess) return fail(c, FR3D_E_DEVICE, "kernel samples check: %s", hipGetErrorString(ev));
+    const double dev = Lv.scal_host[0], mag = Lv.scal_host[1];
+    if (!std::isfinite(dev) || !std::isfinite(mag) || !(mag > 0)) {
+      c->has_kernel = false;
+      return fail(c, FR3D_E_INVALID, "kernel samples must be finite and not all zero");
+    }
+    if (dev > 1e-12 * mag) {
+      c->has_kernel = false;
+      return fail(c, FR3D_E_INVALID, "kernel samples must be even in x and y (relative deviation %.3g)", dev / mag);
+    }
+  }
+  HIPCHK(c, hipMalloc(&c->oct, noct * sizeof(double2)));
   for (auto& L : c->lanes)
     if ((st = alloc_lane_geometry(c, L))) return st;
   Lane& L0 = c->lanes[0];
@@ -1037,6 +1102,7 @@ fr3d_status fr3d_load_kernel(fr3d_ctx* c, const fr3d_geom* g) {
     return st;
   }
   FwdArgs a = fwd_args(c, L0, true);
+  a.ksrc = ksrc;
   const Launch Lk{L0.stream, nullptr, nullptr, 0};
   hipError_t le = launch_fx<double>(c->px, true, nullptr, Ak, a, (const double2*)twx, Lk);
   if (le == hipSuccess) le = launch_fy<double>(c->py, false, Ak, Bk, a, (const double2*)twy, Lk);

@@ -63,6 +63,7 @@ struct FwdArgs {
   int nx, ny, nz;     // cell counts
   int kind;
   int zlin;           // generator mode: plane z samples the z offset z - (nz - 1) (no wrap)
+  const double* ksrc; // generator mode: read the wrapped samples [Pz][Py][Px] from here instead
   // energy epilogue
   BinGeom bg;
   double* bins_part;  // [64][z-pass workgroups]

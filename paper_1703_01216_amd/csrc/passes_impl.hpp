@@ -80,9 +80,13 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
       const int yb = y0 + r;
       double v = 0.0;
       int ox, oy, oz;
-      const bool zok = a.zlin ? (oz = z - (a.nz - 1), true) : wrap_offset(z, a.nz, a.pz, oz);
-      if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) && zok) {
-        v = a.h * a.h * a.hz * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.hz);
+      if (a.ksrc) {
+        if (yb < a.ny_in) v = a.ksrc[((size_t)z * a.py + yb) * P + x];
+      } else {
+        const bool zok = a.zlin ? (oz = z - (a.nz - 1), true) : wrap_offset(z, a.nz, a.pz, oz);
+        if (yb < a.ny_in && wrap_offset(x, a.nx, P, ox) && wrap_offset(yb, a.ny, a.py, oy) && zok) {
+          v = a.h * a.h * a.hz * kernel_value(a.kind, ox * a.h, oy * a.h, (a.D + oz) * a.hz);
+        }
       }
       ldsr[2 * ((r >> 1) * LD + rsw(x)) + (r & 1)] = (T)v;
     }

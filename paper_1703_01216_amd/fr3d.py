@@ -28,7 +28,7 @@ EXPORTED = [
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
-    "fr3d_solve_per_frequency",
+    "fr3d_solve_per_frequency", "fr3d_load_kernel_samples",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_load_layered": (I32, [P, ctypes.POINTER(Geom)]),
         "fr3d_solve_exact": (I32, [P, P, D, P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_per_frequency": (I32, [P, ctypes.POINTER(DpOpts), P, P, P, ctypes.POINTER(Report)]),
+        "fr3d_load_kernel_samples": (I32, [P, ctypes.POINTER(Geom), P]),
         "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
@@ -206,6 +207,15 @@ class Context:
     def load_kernel(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0, hz=0.0):
         g = Geom(nx, ny, nz, h, D, kind, q, precision, alpha_relative, hz)
         self._chk(self._lib.fr3d_load_kernel(self._ctx, ctypes.byref(g)))
+        self.geom = g
+
+    def load_kernel_samples(self, k, nx, ny, nz, h=1.0, D=0.0, q=-1, precision=32, alpha_relative=0, hz=0.0):
+        """The caller's wrapped kernel table k (float64 cuda tensor [2nz][2ny][2nx])."""
+        if not (k.is_cuda and k.dtype == self.torch.float64 and k.is_contiguous()
+                and tuple(k.shape) == (2 * nz, 2 * ny, 2 * nx)):
+            raise ValueError("k must be a contiguous float64 cuda tensor of shape (2nz, 2ny, 2nx)")
+        g = Geom(nx, ny, nz, h, D, 0, q, precision, alpha_relative, hz)
+        self._chk(self._lib.fr3d_load_kernel_samples(self._ctx, ctypes.byref(g), _ptr(k)))
         self.geom = g
 
     def load_layered(self, nx, ny, nz, h=1.0, D=0.0, kind=0, q=-1, precision=32, alpha_relative=0, hz=0.0):
