@@ -106,6 +106,10 @@ typedef struct {
   int32_t n_evals;          /* number of alpha evaluations (inverse transforms) */
   int32_t flags;            /* FR3D_* report flags */
   int64_t n_clamped;        /* cells clamped by the recovery of c (batch with recovery), else -1 */
+  double residual_full_box; /* with diagnostics on (fr3d_set_diagnostics), the residual of the
+                               regularised model on the whole padded box, ||C u - E_Y F|| =
+                               (sum |r^|^2 / (Px Py Pz))^(1/2) by Parseval, at alpha (3D form, single
+                               evaluations); otherwise -1 */
 } fr3d_report;
 
 /* Defaults of fr3d_dp_opts. */
@@ -337,6 +341,14 @@ fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
  * apply unchanged (r grows with alpha for all three).  Waits for the
  * context's streams.  E_INVALID on a bad kind or order. */
 fr3d_status fr3d_set_filter(fr3d_ctx* ctx, int32_t kind, int32_t order);
+
+/* Diagnostics of the 3D form: with enable = 1 every single evaluation also
+ * forms the full-box residual (a sum over the inverse z pass's tiles and
+ * one small reduction kernel), reported as residual_full_box; it is the
+ * residual on the whole padded box, a diagnostic beside the residual on Y
+ * that the discrepancy rule uses.  Default 0 (the field is -1).
+ * Synchronises the context's lanes. */
+fr3d_status fr3d_set_diagnostics(fr3d_ctx* ctx, int32_t enable);
 
 /* With enable = 1, each lane captures its evaluation's launch sequence (the
  * z, y and x passes and the norm kernel, for K-candidate searches both the

@@ -202,6 +202,17 @@ __global__ void k_smax_part(const double2* __restrict__ oct, long long n, double
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Full-box residual of a single evaluation: ctrl->r2_full = scale * (fixed-
+// order sum of the inverse z pass's per-workgroup |r^|^2 partials).
+__global__ void k_full_final(InvArgs a, int nblk) {
+  __shared__ double red[NT / 64];
+  if (inv_idle(a)) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += NT) s += a.full_part[k];
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) a.ctrl->r2_full = s * a.scale;
+}
+
 __global__ void k_max_parts(const double* __restrict__ part, int n, double* out) {
   __shared__ double red[NT];
   double m = 0.0;
@@ -287,6 +298,7 @@ struct fr3d_ctx {
   double* pf_part = nullptr;  // per-system partials of the per-frequency alpha search
   size_t pf_cap = 0;
   bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
+  bool diag = false;                // form the full-box residual of every single evaluation
   hipStream_t cap_stream = nullptr; // stream the graphs are captured on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double acc_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -599,6 +611,7 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     ak.w2_stride = (long long)nA;
     ak.norm_stride = (long long)c->norm_part_n;
     ak.norm_part = L.knorm;
+    ak.full_part = nullptr;
     // candidates per z-pass workgroup: all K unless the grid would be small
     const long long tiles = (long long)c->kxn * std::max<long long>(1, (long long)c->py * c->pz / (c->esz == 8 ? 2048 : 4096));
     int kb = L.kmax;
@@ -616,8 +629,15 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     LCHK(c, launch_iy<T>(c->py, W1k, W2k, ak, (const c2<T>*)twy, ly));
     LCHK(c, launch_ix<T>(c->px, 0, W2k, (T*)nullptr, ak, (const c2<T>*)twx, lx));
   }
+  const bool diag = c->diag && mode == 0 && !c->layered;
+  if (diag) a.full_part = L.bins_part;  // free between the forward pass's features and the next data set
+  unsigned nzb = 0;
   if (c->layered) LCHK(c, launch_lay_filter<T>(mode, b.S, b.W1, lay_args(c), a, mkL(c, L, 3)));
-  else LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
+  else LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3), &nzb));
+  if (diag) {
+    hipLaunchKernelGGL(k_full_final, dim3(1), dim3(NT), 0, L.stream, a, (int)nzb);
+    LCHK(c, hipGetLastError());
+  }
   LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, L, 4)));
   LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, L, 5)));
   return FR3D_OK;
@@ -666,6 +686,7 @@ fr3d_status eval_lane(fr3d_ctx* c, Lane& L) {
 
 Ctrl ctrl_base(fr3d_ctx* c, Lane& L) {
   Ctrl v{};
+  v.r2_full = -1.0;
   v.a_scale = c->g.alpha_relative ? c->smax : 1.0;
   v.delta = L.delta;
   v.tau = 1.0;
@@ -789,6 +810,7 @@ void fill_report(const Ctrl& h, fr3d_report* r) {
   r->n_evals = h.n_evals;
   r->flags = h.flags;
   r->n_clamped = -1;
+  r->residual_full_box = h.r2_full >= 0 ? std::sqrt(h.r2_full) : -1.0;
 }
 
 int env_int(const char* name, int dflt) {
@@ -1675,6 +1697,7 @@ fr3d_status fr3d_solve_exact(fr3d_ctx* c, const void* F, double alpha, void* zet
     rep->n_evals = iters;
     rep->flags = conv ? 0 : FR3D_CG_LIMIT;
     rep->n_clamped = -1;
+    rep->residual_full_box = -1.0;
   }
   return FR3D_OK;
 }
@@ -1719,6 +1742,7 @@ fr3d_status fr3d_solve_exact_discrepancy(fr3d_ctx* c, const void* F, double delt
       rep->n_evals = n_evals;
       rep->flags = flags | fl;
       rep->n_clamped = -1;
+      rep->residual_full_box = -1.0;
     }
     return FR3D_OK;
   };
@@ -1838,6 +1862,18 @@ fr3d_status fr3d_set_filter(fr3d_ctx* c, int32_t kind, int32_t order) {
   c->filt = kind;
   c->forder = kind == 1 ? order : 1;
   // captured evaluations hold the old filter in their arguments
+  for (auto& L : c->lanes) {
+    if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+    L.gexec = nullptr;
+  }
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_set_diagnostics(fr3d_ctx* c, int32_t enable) {
+  if (!c) return FR3D_E_INVALID;
+  for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
+  c->diag = enable != 0;
+  // captured evaluations hold the old launch sequence
   for (auto& L : c->lanes) {
     if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
     L.gexec = nullptr;

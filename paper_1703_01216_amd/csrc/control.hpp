@@ -73,6 +73,7 @@ struct Ctrl {
   double a, b;       // bracket
   double alpha_abs;  // 10^t * a_scale, read by the filter
   double r2, z2;     // norms of the last evaluation
+  double r2_full;    // full-box ||r||^2 of the last evaluation (diagnostics; < 0: not formed)
   double target;     // T of the last evaluation
   double ga, gb;     // r/T - 1 at the bracket ends (seeded search)
   double prev_t, prev_g, wstep;

@@ -28,7 +28,7 @@ EXPORTED = [
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
-    "fr3d_solve_per_frequency", "fr3d_load_kernel_samples",
+    "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -60,7 +60,7 @@ class Report(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("residual", ctypes.c_double),
                 ("zeta_norm", ctypes.c_double), ("delta", ctypes.c_double),
                 ("target", ctypes.c_double), ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("n_clamped", ctypes.c_int64)]
+                ("n_clamped", ctypes.c_int64), ("residual_full_box", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_solve_exact": (I32, [P, P, D, P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_per_frequency": (I32, [P, ctypes.POINTER(DpOpts), P, P, P, ctypes.POINTER(Report)]),
         "fr3d_load_kernel_samples": (I32, [P, ctypes.POINTER(Geom), P]),
+        "fr3d_set_diagnostics": (I32, [P, I32]),
         "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
@@ -307,6 +308,10 @@ class Context:
     def set_filter(self, kind: int, order: int = 1):
         """0 Tikhonov, 1 iterated Tikhonov of the given order, 2 truncated SVD."""
         self._chk(self._lib.fr3d_set_filter(self._ctx, int(kind), int(order)))
+
+    def set_diagnostics(self, on: bool):
+        """Full-box residual in every report (residual_full_box)."""
+        self._chk(self._lib.fr3d_set_diagnostics(self._ctx, 1 if on else 0))
 
     def set_graphs(self, on: bool):
         self._chk(self._lib.fr3d_set_graphs(self._ctx, 1 if on else 0))

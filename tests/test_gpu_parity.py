@@ -337,3 +337,44 @@ def test_workload1_fp64_against_direct_quadrature(fr3d):
     ref = tikhonov.solve_spectral(g, np.fft.fftn(sample_kernel(g)), d["F"], 1e-4)
     assert rel_l2(host(z), ref["zeta"]) < 1e-11
     assert rep["residual"] == pytest.approx(ref["r_norm"], rel=1e-11)
+
+
+@pytest.mark.parametrize("precision,method", [(64, 0), (32, 0), (64, 2), (64, 1)])
+def test_full_box_residual_diagnostic(fr3d, precision, method):
+    # residual of the regularised model on the whole padded box (Parseval
+    # over the half spectrum), reported with diagnostics on, for each filter
+    g = geom(16, 12, 8)
+    d = instance(g, 81, 0.02)
+    c = ctx_for(fr3d, g, precision)
+    c.set_filter(method, 3 if method == 1 else 1)
+    F = dev(d["F"], precision)
+    z = torch.empty_like(F)
+    c.set_data(F, d["delta"])
+    assert c.solve_alpha(1e-3, z)["residual_full_box"] == -1.0
+    c.set_diagnostics(True)
+    rep = c.solve_alpha(1e-3, z)
+    khat = np.fft.fftn(sample_kernel(g))
+    o = tikhonov.solve_spectral(g, khat, d["F"], 1e-3, method=method, order=3 if method == 1 else 1)
+    bar = 1e-12 if precision == 64 else 1e-5
+    assert rep["residual_full_box"] == pytest.approx(o["r_full"], rel=bar)
+    assert rep["residual"] == pytest.approx(o["r_norm"], rel=bar)
+    assert rep["residual_full_box"] >= rep["residual"] * (1 - bar)
+    if precision == 64 and method == 0:
+        # the search reports it at its answer (the oracle's rule picks the same alpha)
+        rep = c.solve_discrepancy(z)
+
+        def ev(a):
+            oo = tikhonov.solve_spectral(g, khat, d["F"], a)
+            return oo["r_norm"], oo["zeta_norm"]
+        ref = discrepancy.bisection(ev, d["delta"])
+        assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+        assert rep["residual_full_box"] == pytest.approx(
+            tikhonov.solve_spectral(g, khat, d["F"], ref["alpha"])["r_full"], rel=1e-11)
+        # batch reports carry it too, equal to the single solve's; graphs re-capture
+        zs = [torch.empty_like(F) for _ in range(2)]
+        reps = c.solve_batch([F, F], [d["delta"]] * 2, zs)
+        assert all(r["residual_full_box"] == rep["residual_full_box"] for r in reps)
+        c.set_graphs(True)
+        assert c.solve_discrepancy(z)["residual_full_box"] == rep["residual_full_box"]
+        c.set_diagnostics(False)
+        assert c.solve_discrepancy(z)["residual_full_box"] == -1.0

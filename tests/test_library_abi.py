@@ -67,6 +67,7 @@ def test_struct_layouts_match_header():
     # int32 x3, (pad) double x2, int32 x3 (+pad)
     assert ctypes.sizeof(fr3d.Geom) == 56 and fr3d.Geom.h.offset == 16 and fr3d.Geom.kind.offset == 32
     assert fr3d.Geom.hz.offset == 48
-    assert ctypes.sizeof(fr3d.Report) == 56 and fr3d.Report.n_evals.offset == 40 and fr3d.Report.n_clamped.offset == 48
+    assert ctypes.sizeof(fr3d.Report) == 64 and fr3d.Report.n_evals.offset == 40 and fr3d.Report.n_clamped.offset == 48
+    assert fr3d.Report.residual_full_box.offset == 56
     assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 128 and fr3d.DpOpts.seed_walk.offset == 80 and fr3d.DpOpts.seed_slope.offset == 96
     assert fr3d.DpOpts.candidates.offset == 88
