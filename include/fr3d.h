@@ -343,8 +343,8 @@ fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
 fr3d_status fr3d_set_filter(fr3d_ctx* ctx, int32_t kind, int32_t order);
 
 /* Diagnostics of the 3D form: with enable = 1 every single evaluation also
- * forms the full-box residual (a sum over the inverse z pass's tiles and
- * one small reduction kernel), reported as residual_full_box; it is the
+ * forms the full-box residual (one more read of the spectrum and the
+ * octant, and a small reduction), reported as residual_full_box; it is the
  * residual on the whole padded box, a diagnostic beside the residual on Y
  * that the discrepancy rule uses.  Default 0 (the field is -1).
  * Synchronises the context's lanes. */

@@ -202,8 +202,44 @@ __global__ void k_smax_part(const double2* __restrict__ oct, long long n, double
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Full-box residual of a single evaluation: ctrl->r2_full = scale * (fixed-
-// order sum of the inverse z pass's per-workgroup |r^|^2 partials).
+// Full-box residual of a single evaluation (diagnostics): the residual
+// spectrum is r^ = -e(s) f^ with e the filter's residual factor (Tikhonov
+// a/(s+a), iterated Tikhonov (a/(s+a))^m, truncated SVD 0 where s >= a and
+// 1 elsewhere), so by Parseval ||r||^2 = (1/N) sum over the whole box of
+// e^2 |f^|^2, the half spectrum kx <= Px/2 counting planes 0 < kx < Px/2
+// twice.  Per-workgroup partials, then a fixed-order sum into the control
+// block.
+template <typename T>
+__global__ void k_full_part(const c2<T>* __restrict__ S, InvArgs a) {
+  __shared__ double red[NT / 64];
+  if (inv_idle(a)) return;
+  const double aa = a.ctrl->alpha_abs;
+  const int py = a.py, pz = a.pz, oy = py / 2 + 1, oz = pz / 2 + 1;
+  const long long n = (long long)a.kx_n * pz * py;
+  double acc = 0.0;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += (long long)gridDim.x * NT) {
+    const int ky = (int)(e % py), kz = (int)((e / py) % pz), kx = (int)(e / ((long long)py * pz));
+    const int mz = kz <= pz / 2 ? kz : pz - kz, my = ky <= py / 2 ? ky : py - ky;
+    const double2 kk = a.oct[((size_t)kx * oz + mz) * oy + my];
+    const double s = kk.x * kk.x + kk.y * kk.y;
+    double ef;
+    if (a.filt == 0) {
+      ef = aa / (s + aa);
+    } else if (a.filt == 1) {
+      const double q = aa / (s + aa);
+      ef = q;
+      for (int j = 1; j < a.order; ++j) ef *= q;
+    } else {
+      ef = s >= aa ? 0.0 : 1.0;
+    }
+    const c2<T> f = S[e];
+    const double w = (kx == 0 || kx == a.kx_n - 1) ? 1.0 : 2.0;
+    acc += w * ef * ef * ((double)f.x * f.x + (double)f.y * f.y);
+  }
+  const double t = block_sum<NT>(acc, red);
+  if (threadIdx.x == 0) a.full_part[blockIdx.x] = t;
+}
+
 __global__ void k_full_final(InvArgs a, int nblk) {
   __shared__ double red[NT / 64];
   if (inv_idle(a)) return;
@@ -611,7 +647,6 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     ak.w2_stride = (long long)nA;
     ak.norm_stride = (long long)c->norm_part_n;
     ak.norm_part = L.knorm;
-    ak.full_part = nullptr;
     // candidates per z-pass workgroup: all K unless the grid would be small
     const long long tiles = (long long)c->kxn * std::max<long long>(1, (long long)c->py * c->pz / (c->esz == 8 ? 2048 : 4096));
     int kb = L.kmax;
@@ -629,15 +664,16 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
     LCHK(c, launch_iy<T>(c->py, W1k, W2k, ak, (const c2<T>*)twy, ly));
     LCHK(c, launch_ix<T>(c->px, 0, W2k, (T*)nullptr, ak, (const c2<T>*)twx, lx));
   }
-  const bool diag = c->diag && mode == 0 && !c->layered;
-  if (diag) a.full_part = L.bins_part;  // free between the forward pass's features and the next data set
-  unsigned nzb = 0;
-  if (c->layered) LCHK(c, launch_lay_filter<T>(mode, b.S, b.W1, lay_args(c), a, mkL(c, L, 3)));
-  else LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3), &nzb));
-  if (diag) {
-    hipLaunchKernelGGL(k_full_final, dim3(1), dim3(NT), 0, L.stream, a, (int)nzb);
+  if (c->diag && mode == 0 && !c->layered) {
+    InvArgs ad = a;
+    ad.full_part = L.bins_part;  // free between the forward pass's features and the next data set
+    constexpr int nb = 1024;
+    hipLaunchKernelGGL(k_full_part<T>, dim3(nb), dim3(NT), 0, L.stream, (const c2<T>*)b.S, ad);
+    hipLaunchKernelGGL(k_full_final, dim3(1), dim3(NT), 0, L.stream, ad, nb);
     LCHK(c, hipGetLastError());
   }
+  if (c->layered) LCHK(c, launch_lay_filter<T>(mode, b.S, b.W1, lay_args(c), a, mkL(c, L, 3)));
+  else LCHK(c, launch_iz<T>(c->pz, mode, b.S, b.W1, a, (const c2<T>*)twz, mkL(c, L, 3)));
   LCHK(c, launch_iy<T>(c->py, b.W1, b.W2, a, (const c2<T>*)twy, mkL(c, L, 4)));
   LCHK(c, launch_ix<T>(c->px, mode, b.W2, out, a, (const c2<T>*)twx, mkL(c, L, 5)));
   return FR3D_OK;

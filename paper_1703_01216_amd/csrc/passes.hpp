@@ -92,9 +92,8 @@ struct InvArgs {
   int kmax;                 // K (grid extent over candidates)
   int kb;                   // candidates per z-pass workgroup
   long long w1_stride, w2_stride, norm_stride;
-  // single evaluations with diagnostics: per-workgroup sums over the z pass's
-  // tile of |r^|^2 (planes 0 < kx < Px/2 counted twice), for the full-box
-  // residual ||r||^2 = (1/N) sum |r^|^2 (Parseval); null: not formed
+  // single evaluations with diagnostics: per-workgroup partial sums of the
+  // full-box residual (Parseval over the half spectrum); null: not formed
   double* full_part;
 };
 
@@ -128,8 +127,7 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
 // With a.kmode the z, y and x passes cover a.kmax candidates (a grid
 // dimension) and the x pass is followed by the K-way norm kernel.
 template <typename T>
-hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L,
-                     unsigned* nblk = nullptr);
+hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>
 hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>

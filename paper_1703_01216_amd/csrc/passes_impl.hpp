@@ -314,15 +314,10 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
   int kx, tile;
-  constexpr bool DIAG = MODE == 0 && !KM;
-  if (!xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)) {
-    if (DIAG && a.full_part && threadIdx.x == 0) a.full_part[blockIdx.x] = 0.0;
-    return;
-  }
+  if (!xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)) return;
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
-  double rfull = 0.0;  // sum of |r^|^2 over this thread's points (diagnostics)
   const c2<T>* src = S + (size_t)kx * P * py;
   const double2* oc = a.oct + (size_t)kx * oz * oy;
   // filter of one point: u and r from f^ and the (possibly conjugated) k^
@@ -351,7 +346,6 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const double cx = kk.x * gu, cy = -kk.y * gu;  // conj(k^) g
       u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
       r = mk<T>((T)(fx * cr), (T)(fy * cr));
-      if constexpr (DIAG) rfull += cr * cr * (fx * fx + fy * fy);
     } else {
       const double kyv = a.adj ? -kk.y : kk.y;  // adjoint: conj(k^), the correlation with K
       u = mk<T>((T)(fx * kk.x - fy * kyv), (T)(fx * kyv + fy * kk.x));
@@ -481,14 +475,6 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       c4<T> v;
       v.x = uo[i].x; v.y = uo[i].y; v.z = w.x; v.w = w.y;
       dst[(size_t)z * py + ky] = v;
-    }
-  }
-  if constexpr (DIAG) {
-    if (a.full_part) {
-      __shared__ double red[NT / 64];
-      const double w = (kx == 0 || kx == a.kx_n - 1) ? 1.0 : 2.0;  // planes 0 and Px/2 once
-      const double t = block_sum<NT>(w * rfull, red);
-      if (tid == 0) a.full_part[blockIdx.x] = t;
     }
   }
 }
@@ -781,8 +767,7 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
 }
 
 template <typename T>
-hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L,
-                     unsigned* nblk) {
+hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
@@ -793,7 +778,6 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
     const long long ntile = cdiv(a.py, C);                                                                       \
     const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
     dim3 g(16 * cdiv(npairs, 8));                                                                                \
-    if (nblk) *nblk = g.x;                                                                                       \
     if (mode != 0)                                                                                               \
       return sh == 1 ? go(k_iz<T, p, 1, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0, false>, g, L, S, W1, a, tw); \
     if (a.kmode) {                                                                                               \
@@ -858,8 +842,7 @@ hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a,
   template hipError_t launch_fx<T>(int, bool, const T*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&); \
   template hipError_t launch_fy<T>(int, bool, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&); \
   template hipError_t launch_fz<T>(int, int, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&);  \
-  template hipError_t launch_iz<T>(int, int, const c2<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&,    \
-                                   unsigned*);                                                                  \
+  template hipError_t launch_iz<T>(int, int, const c2<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);  \
   template hipError_t launch_iy<T>(int, const c4<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);       \
   template hipError_t launch_ix<T>(int, int, const c4<T>*, T*, const InvArgs&, const c2<T>*, const Launch&);
 
