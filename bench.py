@@ -214,7 +214,7 @@ def layered_section(torch, fr3d, n=256, nz=51, reps=3):
     from paper_1703_01216_amd import model_example
     me = model_example.run(n, nz, amplitude=1e-3, precision=64)
     out["model_example_fp64_tsvd"] = {k: me[k] for k in ("setup_ms", "solve_ms", "n_evals", "flags", "alpha",
-                                                           "r_over_delta")}
+                                                           "r_over_delta", "singular_values")}
     out["model_example_fp64_tsvd"]["mean_delta_C"] = sum(me["delta_C"]) / len(me["delta_C"])
     return out
 

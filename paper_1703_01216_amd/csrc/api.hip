@@ -1856,6 +1856,16 @@ fr3d_status fr3d_get_octant(fr3d_ctx* c, void* out, int64_t bytes) {
   return FR3D_OK;
 }
 
+fr3d_status fr3d_get_singular_values(fr3d_ctx* c, double* out, int64_t bytes) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, false)) return FR3D_E_STATE;
+  if (!c->layered) return fail(c, FR3D_E_STATE, "singular values belong to the per-frequency systems (fr3d_load_layered)");
+  const size_t n = (size_t)c->kxn * (c->py / 2 + 1) * c->g.nz * sizeof(double);
+  if (!out || bytes < (int64_t)n) return fail(c, FR3D_E_INVALID, "need %zu bytes", n);
+  LCHK(c, launch_lay_sv(lay_args(c), out, c->lanes[0].stream));
+  return FR3D_OK;
+}
+
 fr3d_status fr3d_get_data_spectrum(fr3d_ctx* c, void* out, int64_t bytes) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;

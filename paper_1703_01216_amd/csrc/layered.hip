@@ -395,6 +395,25 @@ __global__ __launch_bounds__(LNT) void k_lay_pf(const c2<T>* __restrict__ B, c4<
   }
 }
 
+// One thread per system: the squared singular values to singular values,
+// sorted descending by insertion (M <= 60).
+__global__ __launch_bounds__(LNT) void k_lay_sv(LayArgs la, double* __restrict__ out) {
+  const long long f = (long long)blockIdx.x * LNT + threadIdx.x;
+  if (f >= (long long)la.kxn * la.pyh) return;
+  const int M = la.M;
+  const double* lam = la.lam + (size_t)f * M;
+  double* o = out + (size_t)f * M;
+  for (int k = 0; k < M; ++k) {
+    const double v = sqrt(fmax(lam[k], 0.0));
+    int j = k;
+    while (j > 0 && o[j - 1] < v) {
+      o[j] = o[j - 1];
+      --j;
+    }
+    o[j] = v;
+  }
+}
+
 __global__ __launch_bounds__(LNT) void k_lay_max_part(const double* __restrict__ lam, long long n, double* part) {
   __shared__ double red[LNT / 64];
   double m = 0.0;
@@ -450,6 +469,12 @@ hipError_t launch_lay_filter(int mode, const c2<T>* B, c4<T>* W1, const LayArgs&
     return go_lay(k_lay_filter<T, 0, true>, g, L, B, W1, la, a);
   }
   return go_lay(k_lay_filter<T, 0, false>, g, L, B, W1, la, a);
+}
+
+hipError_t launch_lay_sv(const LayArgs& la, double* out, hipStream_t s) {
+  const long long nf = (long long)la.kxn * la.pyh;
+  hipLaunchKernelGGL(k_lay_sv, dim3((unsigned)((nf + LNT - 1) / LNT)), dim3(LNT), 0, s, la, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_lay_max(const double* lam, long long n, double* part, double* out, hipStream_t s) {

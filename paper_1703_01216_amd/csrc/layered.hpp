@@ -66,6 +66,10 @@ template <typename T>
 hipError_t launch_lay_pf(const c2<T>* B, c4<T>* W1, const LayArgs& la, const InvArgs& a, const PfArgs& pf,
                          const Launch& L);
 
+// Singular values s_k = sqrt(lam_k) of every distinct system, descending:
+// out[f][k], f = kx (Py/2 + 1) + |ky|.
+hipError_t launch_lay_sv(const LayArgs& la, double* out, hipStream_t s);
+
 // max lam (the squared operator norm) into *out (device), via partials.
 hipError_t launch_lay_max(const double* lam, long long n, double* part, double* out, hipStream_t s);
 

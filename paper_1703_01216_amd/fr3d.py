@@ -28,7 +28,7 @@ EXPORTED = [
     "fr3d_source_potential", "fr3d_apply_operator", "fr3d_add_noise", "fr3d_get_octant",
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
-    "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics",
+    "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics", "fr3d_get_singular_values",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_solve_per_frequency": (I32, [P, ctypes.POINTER(DpOpts), P, P, P, ctypes.POINTER(Report)]),
         "fr3d_load_kernel_samples": (I32, [P, ctypes.POINTER(Geom), P]),
         "fr3d_set_diagnostics": (I32, [P, I32]),
+        "fr3d_get_singular_values": (I32, [P, P, I64]),
         "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
@@ -292,6 +293,13 @@ class Context:
         g = self.geom
         out = self.torch.empty((g.nx + 1, 2 * g.nz, 2 * g.ny, 2), dtype=self.dtype, device="cuda")
         self._chk(self._lib.fr3d_get_data_spectrum(self._ctx, _ptr(out), out.numel() * out.element_size()))
+        return out
+
+    def get_singular_values(self):
+        """Per-frequency systems' singular values, descending: [Px/2+1][Py/2+1][nz] float64."""
+        g = self.geom
+        out = self.torch.empty((g.nx + 1, g.ny + 1, g.nz), dtype=self.torch.float64, device="cuda")
+        self._chk(self._lib.fr3d_get_singular_values(self._ctx, _ptr(out), out.numel() * 8))
         return out
 
     def get_features(self):

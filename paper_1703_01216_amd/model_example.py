@@ -31,6 +31,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
@@ -74,11 +76,27 @@ def run(n=256, nz=51, amplitude=1e-8, precision=64, filt=(2, 1), seed=0, log10_a
     cc = torch.empty_like(F)
     n_clamped = c.recover_c(z, V, inputs.MODEL_C0, cc)
     dc = delta_c(z)
+    # Fig. 6: singular values of the per-frequency systems and, with TSVD, how
+    # many each keeps at the chosen alpha (s^2 >= alpha), counted over all
+    # Px Py frequencies (each distinct system stands for its mirror images)
+    sv = c.get_singular_values().double()
+    kept = (sv * sv >= rep["alpha"]).sum(dim=2).cpu().numpy()
+    kxn, pyh = kept.shape
+    wx = np.where((np.arange(kxn) == 0) | (np.arange(kxn) == kxn - 1), 1, 2)
+    wy = np.where((np.arange(pyh) == 0) | (np.arange(pyh) == pyh - 1), 1, 2)
+    w = (wx[:, None] * wy[None, :]).ravel()
+    kv = kept.ravel()
+    order = np.argsort(kv, kind="stable")
+    cw = np.cumsum(w[order]) / w.sum()
+    quant = lambda q: int(kv[order][np.searchsorted(cw, q)])  # noqa: E731
+    svs = {"kept_p10": quant(0.1), "kept_median": quant(0.5), "kept_p90": quant(0.9), "kept_max": int(kv.max()),
+           "frac_kept_15_25": float(w[(kv >= 15) & (kv <= 25)].sum() / w.sum()),
+           "s_lowest_frequency": sv[0, 0].cpu().tolist()}
     out = dict(geometry=g, precision=precision, filter=list(filt), amplitude=amplitude, delta=delta, tau=tau,
                alpha=rep["alpha"], flags=rep["flags"], n_evals=rep["n_evals"],
                r_over_delta=rep["residual"] / delta if delta > 0 else None,
                setup_ms=setup * 1e3, solve_ms=solve * 1e3, n_clamped=n_clamped,
-               z=[1.0 + (k + 0.5) * g["hz"] for k in range(nz)], delta_C=dc.tolist(),
+               z=[1.0 + (k + 0.5) * g["hz"] for k in range(nz)], delta_C=dc.tolist(), singular_values=svs,
                zeta=z, xi=xi, V0=V, F=F)
     if sweep:
         # the cut that minimises the layer-mean Delta_C (it uses the exact xi, so it

@@ -278,3 +278,25 @@ def test_per_frequency_single_alpha_equals_global_and_errors(fr3d):
     with pytest.raises(fr3d.Fr3dError) as ei:
         c3.solve_per_frequency(z1)
     assert ei.value.status == fr3d.E_STATE
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_singular_values_against_oracle(fr3d, precision):
+    # Fig. 6's quantity: the singular values of every distinct system, from
+    # the one-sided Jacobi SVD on the device, against LAPACK on the oracle's
+    # assembled systems (absolute error ~eps ||A||)
+    g = geom(16, 12, 9)
+    c = ctx_layered(fr3d, g, precision)
+    sv = host(c.get_singular_values())
+    A = layered.system_matrices(g, layered.lateral_kernel_spectrum(g))
+    S = np.linalg.svd(A, compute_uv=False)                     # [Py][Px][M], descending
+    kxn, pyh = g.pshape[2] // 2 + 1, g.pshape[1] // 2 + 1
+    ref = np.transpose(S[:pyh, :kxn], (1, 0, 2))
+    assert sv.shape == ref.shape
+    assert np.abs(sv - ref).max() <= 1e-12 * ref.max()
+    assert np.all(np.diff(sv, axis=2) <= 0)
+    with pytest.raises(fr3d.Fr3dError) as ei:
+        c3 = fr3d.Context()
+        c3.load_kernel(8, 8, 8, precision=64)
+        c3.get_singular_values()
+    assert ei.value.status == fr3d.E_STATE

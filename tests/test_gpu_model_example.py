@@ -77,6 +77,14 @@ def test_model_example_paper_size(me, amp, tau):
           f"best cut 1e{b['log10_alpha']:g}: mean Delta_C {b['mean_delta_C']:.3f}, r/delta {b['r_over_delta']:.3g}")
     print("[model example] best-cut Delta_C(z): " + ", ".join(
         f"{z:.3f}:{d:.3f}" for z, d in zip(out["z"], b["delta_C"])))
+    sv = out["singular_values"]
+    print(f"[model example] TSVD kept per frequency at the chosen alpha: p10 {sv['kept_p10']} median "
+          f"{sv['kept_median']} p90 {sv['kept_p90']} max {sv['kept_max']}, share with 15..25 kept "
+          f"{sv['frac_kept_15_25']:.3f}; s(0,0)/s_0: " + ", ".join(
+              f"{v / sv['s_lowest_frequency'][0]:.1e}" for v in sv["s_lowest_frequency"][:30:3]))
+    assert 0 <= sv["kept_p10"] <= sv["kept_median"] <= sv["kept_p90"] <= sv["kept_max"] <= 51
+    s0 = np.array(sv["s_lowest_frequency"])
+    assert np.all(np.diff(s0) <= 0) and s0[0] > 0
     assert np.all(np.isfinite(dc)) and np.all(np.isfinite(b["delta_C"]))
     assert out["flags"] in (0, discrepancy.NOROOT_LOW, discrepancy.MAXITER)
     if out["flags"] == 0:

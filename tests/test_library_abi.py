@@ -33,6 +33,13 @@ def test_exports_every_declared_symbol(lib):
     assert sorted(fr3d.EXPORTED) == names
 
 
+def test_every_symbol_resolves_at_load():
+    # eager binding: a function the library calls but does not define fails here
+    import os
+    from paper_1703_01216_amd import fr3d
+    ctypes.CDLL(fr3d.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+
+
 def test_defaults_and_status_strings(lib):
     from paper_1703_01216_amd import fr3d
     o = fr3d.default_opts()
