@@ -295,6 +295,11 @@ fr3d_status fr3d_add_noise(fr3d_ctx* ctx, void* F_dev, const void* e_dev, double
  *   features: float[65] = log10(E_b/mean E + 1e-30), b < 64, then log10(delta/||F||)
  *   energy: double[64] radial energies E_b over the full spectrum. */
 fr3d_status fr3d_get_octant(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
+fr3d_status fr3d_get_data_spectrum(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
+fr3d_status fr3d_get_features(fr3d_ctx* ctx, float* feat_dev, double* energy_dev);
+/* |k^|max^2 of the loaded kernel (host). */
+fr3d_status fr3d_get_smax(fr3d_ctx* ctx, double* smax);
+
 /* Singular values of the per-frequency systems (Sec. 5, Eq. (14); Fig. 6
  * shows their decay), after fr3d_load_layered: out (device, double,
  * [Px/2+1][Py/2+1][nz]) receives for each distinct system (kx, |ky|) its
@@ -302,10 +307,6 @@ fr3d_status fr3d_get_octant(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
  * smaller buffer gives FR3D_E_INVALID, a 3D context FR3D_E_STATE.
  * Asynchronous on lane 0's stream. */
 fr3d_status fr3d_get_singular_values(fr3d_ctx* ctx, double* out, int64_t bytes);
-fr3d_status fr3d_get_data_spectrum(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
-fr3d_status fr3d_get_features(fr3d_ctx* ctx, float* feat_dev, double* energy_dev);
-/* |k^|max^2 of the loaded kernel (host). */
-fr3d_status fr3d_get_smax(fr3d_ctx* ctx, double* smax);
 
 /* The alpha predictor (not part of the paper): a perceptron 65 -> 128 ->
  * 128 -> 1 with exact-erf GELU, bfloat16 matrix-core products with FP32

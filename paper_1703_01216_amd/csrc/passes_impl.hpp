@@ -167,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double bins[64];
+  __shared__ long long thr[65];  // thr[b] = 3 b^2 L: a point is in bin b iff thr[b] <= 4096 U < thr[b+1]
   const int tid = threadIdx.x;
   const int py = a.py;
   int kx, tile;
@@ -198,6 +199,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
   if (MODE == 0 && tid < 64) bins[tid] = 0.0;
+  if (MODE == 0 && tid < 65) thr[tid] = (long long)tid * tid * a.bg.L3;
 #pragma unroll
   for (int i = 0; i < PE::n; ++i) {
     const int e = tid + i * NT;
@@ -228,10 +230,37 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     };
     if constexpr (C <= NT && NT % C == 0) {
       // each thread walks a run of consecutive kz in one column: its bin
-      // changes rarely, so few LDS atomics
+      // changes rarely, so few LDS atomics, and it is found by stepping from
+      // the previous point's bin with the threshold table (the exact rule
+      // only for the first point)
       constexpr int RPC = C * P / NT;
       const int col = tid % C, k0 = (tid / C) * RPC;
-      for (int j = 0; j < RPC; ++j) visit(k0 + j, col);
+      const int ky = ky0 + col;
+      if (ky < py) {
+        const long long mx = kx <= a.bg.px / 2 ? kx : kx - a.bg.px;
+        const long long my = ky <= a.bg.py / 2 ? ky : ky - a.bg.py;
+        const long long cxy = mx * mx * a.bg.fx + my * my * a.bg.fy;
+        int b = -1;
+        for (int j = 0; j < RPC; ++j) {
+          const int kz = k0 + j;
+          const c2<T> u = lds[kz * LD + col];
+          dst[(size_t)kz * py + ky] = u;
+          const long long mz = kz <= a.bg.pz / 2 ? kz : kz - a.bg.pz;
+          const long long U4 = 16384 * (cxy + mz * mz * a.bg.fz);
+          if (b < 0) {
+            b = energy_bin(a.bg, kx, ky, kz);
+          } else {
+            while (b < 63 && thr[b + 1] <= U4) ++b;
+            while (b > 0 && thr[b] > U4) --b;
+          }
+          if (b != cur) {
+            if (cur >= 0) atomicAdd(&bins[cur], acc);
+            cur = b;
+            acc = 0.0;
+          }
+          acc += w * ((double)u.x * u.x + (double)u.y * u.y);
+        }
+      }
     } else {
       for (int e = tid; e < C * P; e += NT) visit(e / C, e % C);
     }
