@@ -376,16 +376,17 @@ def main():
     # the learned searches: the network's seed calibrated for this geometry
     # on instances of the same recipe that are not timed (indices from
     # CAL_FIRST), then the secant refinement with the calibrated slope
-    sk, cal = {}, None
+    sk, cal, cal_coef = {}, None, None
     if any(m.startswith("learned") for m in modes) and args.calibrate:
         from paper_1703_01216_amd import calibrate
         t0c = time.perf_counter()
         Fc, dc, _ = make_instances(ctx, torch, n, args.calibrate, first=CAL_FIRST)
         cal = calibrate.seed_calibration(ctx, Fc, dc)
+        cal_coef = cal.pop("coef")
         cal["seconds"] = time.perf_counter() - t0c
         cal["first_index"] = CAL_FIRST
         del Fc
-        sk = {k: cal[k] for k in ("seed_shift", "seed_shift_x", "seed_slope", "seed_slope_x")}
+        sk = {k: cal[k] for k in ("seed_slope", "seed_slope_x")}
         print(f"[bench] seed calibration: {cal}", file=sys.stderr, flush=True)
     mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
                  "learned_walk": fr3d.default_opts(use_predictor=1, **tight),
@@ -403,6 +404,9 @@ def main():
     head = modes[0]
     if not args.roofline_only:
         for m in modes:
+            if m.startswith("learned"):
+                # learned_walk: the network's own seed (no calibration) with the walk
+                ctx.predictor_set_calibration(None if m == "learned_walk" else cal_coef)
             r, _ = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup)
             results[m] = r
             print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)

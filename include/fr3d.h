@@ -93,8 +93,6 @@ typedef struct {
   double seed_slope_x;                   /* with seed_slope > 0: the slope is seed_slope
                                             10^(seed_slope_x x_64), clamped to [1e-4, 1e3] (x_64 =
                                             log10(delta/||F||), the noise feature); default 0 */
-  double seed_shift, seed_shift_x;       /* seed = clip(prediction + seed_shift + seed_shift_x x_64) in
-                                            decades (a calibration for one geometry); default 0, 0 */
 } fr3d_dp_opts;
 
 typedef struct {
@@ -331,6 +329,13 @@ fr3d_status fr3d_predictor_train_step(fr3d_ctx* ctx, const float* X_dev, const f
  * checksum; load rejects a corrupt or foreign file with FR3D_E_INVALID. */
 fr3d_status fr3d_predictor_save(fr3d_ctx* ctx, const char* path);
 fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
+/* Calibration of the network's seed for one geometry (callers that fit it on
+ * instances of that geometry, e.g. by least squares): the seed becomes
+ * clip(prediction + coef[0] + sum_k coef[1+k] x_k) with x the 65 raw
+ * features.  coef: 66 host doubles, copied; NULL or n = 0 clears it.
+ * Setting or loading a network clears it.  FR3D_E_INVALID for n != 66 or
+ * non-finite values, FR3D_E_STATE without a network; synchronises. */
+fr3d_status fr3d_predictor_set_calibration(fr3d_ctx* ctx, const double* coef, int64_t n);
 
 /* Tile size of a pass (ids as for timing): shift 0 = a 32 KiB LDS tile of
  * pencils, 1 = half, 2 = quarter (row passes 0, 1, 4); for the inverse z

@@ -315,6 +315,8 @@ struct fr3d_ctx {
   bool has_pred = false;
   float* pred_p = nullptr;     // parameters, FP32 master copy
   float* pred_norm = nullptr;  // 132 normalisation values
+  double* pred_cal = nullptr;  // seed calibration for one geometry: 66 coefficients (device)
+  bool has_cal = false;
   float* pred_m = nullptr;
   float* pred_v = nullptr;
   float* pred_g = nullptr;
@@ -745,8 +747,7 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
-      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x) ||
-      !std::isfinite(d->seed_shift) || !std::isfinite(d->seed_shift_x))
+      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
@@ -785,8 +786,6 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   v.walk = d.seed_walk;
   v.slope = d.seed_slope;
   v.slope_x = d.seed_slope_x;
-  v.shift = d.seed_shift;
-  v.shift_x = d.seed_shift_x;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -804,7 +803,8 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   if (d.candidates) {
     *max_evals = d.max_steps;  // each evaluation call: one K-candidate step, then the answer once found
   } else if (d.use_predictor) {
-    LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream));
+    LCHK(c, mlp_forward(c->pred_p, c->pred_norm, L.feat, 1, nullptr, nullptr, L.ctrl, L.stream,
+                        c->has_cal ? c->pred_cal : nullptr));
     if (d.seed_slope > 0) {
       *max_evals = 1 + d.max_steps + 1;  // seed + secant steps + final re-evaluation
     } else {
@@ -967,8 +967,6 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->seed_walk = 0.25;
   o->seed_slope = 0.0;
   o->seed_slope_x = 0.0;
-  o->seed_shift = 0.0;
-  o->seed_shift_x = 0.0;
   o->candidates = 0;
 }
 
@@ -1028,6 +1026,7 @@ fr3d_status fr3d_destroy(fr3d_ctx* c) {
   dfree(c->pred_v);
   dfree(c->pred_g);
   dfree(c->pred_norm);
+  dfree(c->pred_cal);
   dfree(c->pred_loss);
   dfree(c->pred_work);
   delete c;
@@ -1975,6 +1974,25 @@ fr3d_status fr3d_predictor_set(fr3d_ctx* c, const float* params, int64_t n_param
   HIPCHK(c, hipStreamSynchronize(st));
   c->pred_step = 0;
   c->has_pred = true;
+  c->has_cal = false;  // a calibration belongs to the network it was fitted for
+  return FR3D_OK;
+}
+
+fr3d_status fr3d_predictor_set_calibration(fr3d_ctx* c, const double* coef, int64_t n) {
+  if (!c) return FR3D_E_INVALID;
+  if (!coef || n == 0) {
+    c->has_cal = false;
+    return FR3D_OK;
+  }
+  if (n != MLP_IN + 1) return fail(c, FR3D_E_INVALID, "need %d calibration coefficients", MLP_IN + 1);
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(coef[i])) return fail(c, FR3D_E_INVALID, "calibration coefficients must be finite");
+  if (!c->has_pred) return fail(c, FR3D_E_STATE, "no predictor loaded");
+  if (!c->pred_cal) HIPCHK(c, hipMalloc(&c->pred_cal, (MLP_IN + 1) * sizeof(double)));
+  hipStream_t st = c->lanes[0].stream;
+  HIPCHK(c, hipMemcpyAsync(c->pred_cal, coef, (MLP_IN + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  c->has_cal = true;
   return FR3D_OK;
 }
 

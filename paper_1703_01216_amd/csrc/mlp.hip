@@ -29,17 +29,16 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// The prediction la (log10 alpha) of row 0 as the first point of a seeded
-// search: calibrated seed and secant slope (x_64 = log10(delta/||F||), the
-// noise feature).
-__device__ __forceinline__ void write_seed(Ctrl* seed, float la, const float* X) {
-  const double x64 = (double)X[MLP_IN - 1];
-  const double t = fmin(fmax((double)la + seed->shift + seed->shift_x * x64, seed->lo), seed->hi);
+// The prediction la (log10 alpha) plus its calibration dc as the first
+// point of a seeded search, and the secant slope from the noise feature
+// x_64 = log10(delta/||F||).
+__device__ __forceinline__ void write_seed(Ctrl* seed, double la, double dc, const float* X) {
+  const double t = fmin(fmax(la + dc, seed->lo), seed->hi);
   seed->t = t;
   seed->alpha_abs = pow(10.0, t) * seed->a_scale;
   seed->state = ST_SEED;
   if (seed->slope > 0 && seed->slope_x != 0)
-    seed->slope = fmin(fmax(seed->slope * pow(10.0, seed->slope_x * x64), 1e-4), 1e3);
+    seed->slope = fmin(fmax(seed->slope * pow(10.0, seed->slope_x * (double)X[MLP_IN - 1]), 1e-4), 1e3);
 }
 
 // ------------------------------------------------------------------ forward
@@ -48,8 +47,10 @@ __device__ __forceinline__ void write_seed(Ctrl* seed, float la, const float* X)
 // output unit -- instead of one wavefront with 16-row matrix tiles, 15 of
 // whose rows would be empty.
 __global__ __launch_bounds__(256) void k_mlp_fwd1(const float* __restrict__ p, const float* __restrict__ norm,
-                                                  const float* __restrict__ X, float* __restrict__ out, Ctrl* seed) {
+                                                  const float* __restrict__ X, float* __restrict__ out, Ctrl* seed,
+                                                  const double* __restrict__ cal) {
   __shared__ float xs[MLP_IN], h1[MLP_H], h2[MLP_H], red[4];
+  __shared__ double redc[4];
   const int tid = threadIdx.x, j = tid >> 1, hf = tid & 1;
   if (tid < MLP_IN) xs[tid] = rbf((X[tid] - norm[tid]) / norm[MLP_IN + tid]);
   __syncthreads();
@@ -64,21 +65,29 @@ __global__ __launch_bounds__(256) void k_mlp_fwd1(const float* __restrict__ p, c
   if (hf == 0) h2[j] = rbf(gelu(s + p[OFF_B2 + j]));
   __syncthreads();
   float v = tid < MLP_H ? h2[tid] * rbf(p[OFF_W3 + tid]) : 0.0f;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = v;
+  // calibration of the seed: a linear function of the raw features (FP64)
+  double vc = (cal && tid < MLP_IN) ? cal[1 + tid] * (double)X[tid] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    v += __shfl_xor(v, off, 64);
+    vc += __shfl_xor(vc, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = v;
+    redc[tid >> 6] = vc;
+  }
   __syncthreads();
   if (tid == 0) {
     const float y = (red[0] + red[1] + red[2] + red[3]) + p[OFF_B3];
     const float la = norm[2 * MLP_IN] + norm[2 * MLP_IN + 1] * y;
     if (out) out[0] = la;
-    if (seed) write_seed(seed, la, X);
+    if (seed) write_seed(seed, (double)la, cal ? cal[0] + ((redc[0] + redc[1]) + (redc[2] + redc[3])) : 0.0, X);
   }
 }
 
 // One wavefront per 16 batch rows.
 __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, const float* __restrict__ norm,
                                                 const float* __restrict__ X, int B, float* __restrict__ out,
-                                                MlpWork w, int train, Ctrl* seed) {
+                                                MlpWork w, int train) {
   __shared__ uint16_t xs[16][MLP_INP];
   __shared__ uint16_t hs[16][MLP_H];
   __shared__ float h2s[16][MLP_H];
@@ -161,7 +170,7 @@ __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, con
       if (train) w.y[b] = y;
       const float la = norm[2 * MLP_IN] + norm[2 * MLP_IN + 1] * y;
       if (out) out[b] = la;
-      if (seed && b == 0) write_seed(seed, la, X);
+
     }
   }
 }
@@ -322,15 +331,15 @@ void mlp_work_carve(MlpWork* w, void* base, int cap) {
 }
 
 hipError_t mlp_forward(const float* params, const float* norm, const float* X, int B, float* out, MlpWork* w,
-                       Ctrl* seed, hipStream_t s) {
-  if (B <= 0 || (w && B > w->cap) || (seed && B != 1)) return hipErrorInvalidValue;
-  if (seed && !w) {
-    hipLaunchKernelGGL(k_mlp_fwd1, dim3(1), dim3(256), 0, s, params, norm, X, out, seed);
+                       Ctrl* seed, hipStream_t s, const double* cal) {
+  if (B <= 0 || (w && B > w->cap) || (seed && (B != 1 || w))) return hipErrorInvalidValue;
+  if (seed) {
+    hipLaunchKernelGGL(k_mlp_fwd1, dim3(1), dim3(256), 0, s, params, norm, X, out, seed, cal);
     return hipGetLastError();
   }
   MlpWork dummy{};
   hipLaunchKernelGGL(k_mlp_fwd, dim3((B + 15) / 16), dim3(64), 0, s, params, norm, X, B, out, w ? *w : dummy,
-                     w ? 1 : 0, seed);
+                     w ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -50,10 +50,12 @@ void mlp_work_carve(MlpWork* w, void* base, int cap);
 
 // Forward pass for B rows of raw features X[B][65]: writes log10 alpha to
 // out (may be null) and, with w non-null, the activations a training step
-// needs.  With seed non-null (B = 1) the prediction, clipped to
-// [seed->lo, seed->hi], becomes the first point of a seeded search.
+// needs.  With seed non-null (B = 1, w null) the prediction plus the
+// calibration cal[0] + sum_k cal[1+k] X[k] (cal: 66 doubles on the device,
+// or null for none), clipped to [seed->lo, seed->hi], becomes the first
+// point of a seeded search.
 hipError_t mlp_forward(const float* params, const float* norm, const float* X, int B, float* out, MlpWork* w,
-                       Ctrl* seed, hipStream_t s);
+                       Ctrl* seed, hipStream_t s, const double* cal = nullptr);
 
 // Backward pass (after mlp_forward with the same w) for targets t[B]
 // (log10 alpha), gradients of the mean squared error in standardised units

@@ -29,6 +29,7 @@ EXPORTED = [
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
     "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics", "fr3d_get_singular_values",
+    "fr3d_predictor_set_calibration",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -52,8 +53,7 @@ class DpOpts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("h_op", ctypes.c_double), ("mu", ctypes.c_double),
                 ("use_predictor", ctypes.c_int32), ("seed_walk", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("seed_slope", ctypes.c_double),
-                ("seed_slope_x", ctypes.c_double), ("seed_shift", ctypes.c_double),
-                ("seed_shift_x", ctypes.c_double)]
+                ("seed_slope_x", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_load_kernel_samples": (I32, [P, ctypes.POINTER(Geom), P]),
         "fr3d_set_diagnostics": (I32, [P, I32]),
         "fr3d_get_singular_values": (I32, [P, P, I64]),
+        "fr3d_predictor_set_calibration": (I32, [P, ctypes.POINTER(ctypes.c_double), I64]),
         "fr3d_solve_exact_discrepancy": (I32, [P, P, D, ctypes.POINTER(DpOpts), P, I32, D, ctypes.POINTER(Report)]),
         "fr3d_solve_batch": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(D), ctypes.POINTER(P),
                                    ctypes.POINTER(DpOpts), P, D, ctypes.POINTER(P), P, ctypes.POINTER(Report)]),
@@ -370,6 +371,16 @@ class Context:
     def predictor_train_step(self, X, t, lr, loss=None, grad=None):
         self._chk(self._lib.fr3d_predictor_train_step(self._ctx, _ptr(X), _ptr(t), int(X.shape[0]), float(lr),
                                                       _ptr(loss), _ptr(grad)))
+
+    def predictor_set_calibration(self, coef=None):
+        """Seed calibration (66 coefficients: intercept, then one per raw feature); None clears it."""
+        import numpy as np
+        if coef is None:
+            self._chk(self._lib.fr3d_predictor_set_calibration(self._ctx, None, 0))
+            return
+        c = np.ascontiguousarray(coef, dtype=np.float64).ravel()
+        self._chk(self._lib.fr3d_predictor_set_calibration(
+            self._ctx, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c.size))
 
     def predictor_save(self, path):
         self._chk(self._lib.fr3d_predictor_save(self._ctx, os.fsencode(path)))

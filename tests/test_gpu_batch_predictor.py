@@ -136,11 +136,25 @@ def test_seed_matches_oracle_network(fr3d):
     F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
     c.set_data(F, d["delta"])
     z = torch.empty_like(F)
-    rep = c.solve_discrepancy(z, use_predictor=1, accept_lo=0.0, accept_hi=1e300, log10_alpha_lo=-60.0,
-                              log10_alpha_hi=60.0)
+    wide = dict(accept_lo=0.0, accept_hi=1e300, log10_alpha_lo=-60.0, log10_alpha_hi=60.0)
+    rep = c.solve_discrepancy(z, use_predictor=1, **wide)
     assert rep["n_evals"] == 1 and rep["flags"] == 0
     x, _ = features.features(np.fft.fftn(pad(g, d["F"])), d["delta"], np.linalg.norm(d["F"]))
-    yo, _ = mlp.forward(p32, np.asarray(x, dtype=np.float64)[None, :], bf16=True)
+    x = np.asarray(x, dtype=np.float64)
+    yo, _ = mlp.forward(p32, x[None, :], bf16=True)
+    assert math.log10(rep["alpha"]) == pytest.approx(-4.0 + 1.5 * float(yo[0]), abs=2e-3)
+    # a calibration adds coef[0] + sum_k coef[1+k] x_k to the seed
+    coef = np.random.default_rng(9).uniform(-0.05, 0.05, 66)
+    c.predictor_set_calibration(coef)
+    rep = c.solve_discrepancy(z, use_predictor=1, **wide)
+    want = -4.0 + 1.5 * float(yo[0]) + coef[0] + float(coef[1:] @ x)
+    assert math.log10(rep["alpha"]) == pytest.approx(want, abs=2e-3)
+    for bad in ([0.0] * 65, [float("nan")] * 66):
+        with pytest.raises(fr3d.Fr3dError) as ei:
+            c.predictor_set_calibration(bad)
+        assert ei.value.status == fr3d.E_INVALID
+    c.predictor_set(flat, nm)  # a new network drops the calibration
+    rep = c.solve_discrepancy(z, use_predictor=1, **wide)
     assert math.log10(rep["alpha"]) == pytest.approx(-4.0 + 1.5 * float(yo[0]), abs=2e-3)
 
 
@@ -231,13 +245,16 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
     c.set_data(F, d["delta"])
     z = torch.empty_like(F)
     kw = dict(tol=tol, accept_lo=1.0, accept_hi=1.0, max_steps=6)
-    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, seed_shift=shift, **kw)
+    if shift:
+        c.predictor_set_calibration([shift] + [0.0] * 65)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, **kw)
     khat = np.fft.fftn(sample_kernel(g))
 
     def ev(a):
         o = tikhonov.solve_spectral(g, khat, d["F"], a)
         return o["r_norm"], o["zeta_norm"]
-    # a seed shift moves the network's output before the clip to the range
+    # a calibration with only an intercept shifts the network's output before
+    # the clip to the range
     ref = discrepancy.seeded_secant(ev, d["delta"], bias + shift, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
                                     slope=slope)
     assert rep["flags"] == ref["flags"]
