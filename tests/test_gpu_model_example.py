@@ -66,7 +66,7 @@ def test_model_example_reduced_against_oracle(me):
     assert np.allclose(out["delta_C"], dc, rtol=10 * tol, atol=10 * tol)
 
 
-@pytest.mark.parametrize("amp,tau", [(1e-8, 1.0), (1e-3, 1.0), (1e-3, 1.05)])
+@pytest.mark.parametrize("amp,tau", [(1e-10, 1.0), (1e-8, 1.0), (1e-3, 1.0), (1e-3, 1.05)])
 def test_model_example_paper_size(me, amp, tau):
     out = me.run(256, 51, amplitude=amp, precision=64, sweep=True, tau=tau)
     dc = np.array(out["delta_C"])
