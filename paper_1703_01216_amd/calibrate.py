@@ -56,16 +56,26 @@ def seed_calibration(ctx, Fs, deltas, h=0.05, lo=-8.0, hi=0.0):
             ls.append(math.log10(s))
     if len(X) < 3:
         raise RuntimeError("too few calibration instances with a root in the range")
-    X, dt, ls = np.array(X), np.array(dt), np.array(ls)
+    return fit(np.array(X), np.array(dt), np.array(ls))
+
+
+def fit(X, dt, ls, ridge=RIDGE):
+    """The least-squares fits on calibration rows: X [m][65] raw features,
+    dt = t* - t_net, ls = log10 s*.  Returns the raw-feature coefficients of
+    the seed shift (ridge on standardised features; constant features get
+    no weight) and the power law of the slope in x_64."""
+    import numpy as np
+
+    X, dt, ls = np.asarray(X, dtype=np.float64), np.asarray(dt, dtype=np.float64), np.asarray(ls, dtype=np.float64)
     mu, sd = X.mean(0), X.std(0)
     live = sd > 1e-9
     Z = np.zeros_like(X)
     Z[:, live] = (X[:, live] - mu[live]) / sd[live]
     A = np.c_[np.ones(len(X)), Z]
-    reg = RIDGE * np.eye(A.shape[1])
+    reg = ridge * np.eye(A.shape[1])
     reg[0, 0] = 0.0
     w = np.linalg.solve(A.T @ A + reg, A.T @ dt)
-    coef = np.zeros(66)
+    coef = np.zeros(X.shape[1] + 1)
     coef[1:][live] = w[1:][live] / sd[live]
     coef[0] = w[0] - float(np.sum(coef[1:][live] * mu[live]))
     B = np.c_[np.ones(len(X)), X[:, 64]]
