@@ -332,6 +332,9 @@ def main():
     ap.add_argument("--modes", default="learned,bisection,learned_walk,learned_w,bisection_w,kary16")
     ap.add_argument("--calibrate", type=int, default=48,
                     help="instances (not timed) that calibrate the learned seed for this geometry; 0: none")
+    ap.add_argument("--snap-sigmas", type=float, default=2.0,
+                    help="a calibrated seed within this many residual standard deviations of the lower range "
+                         "end starts the learned search at that end (0: off)")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
@@ -386,7 +389,8 @@ def main():
         cal["seconds"] = time.perf_counter() - t0c
         cal["first_index"] = CAL_FIRST
         del Fc
-        sk = {k: cal[k] for k in ("seed_slope", "seed_slope_x")}
+        cal["seed_snap_lo"] = args.snap_sigmas * cal["shift_residual_decades"]
+        sk = {k: cal[k] for k in ("seed_slope", "seed_slope_x", "seed_snap_lo")}
         print(f"[bench] seed calibration: {cal}", file=sys.stderr, flush=True)
     mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
                  "learned_walk": fr3d.default_opts(use_predictor=1, **tight),

@@ -93,6 +93,8 @@ typedef struct {
   double seed_slope_x;                   /* with seed_slope > 0: the slope is seed_slope
                                             10^(seed_slope_x x_64), clamped to [1e-4, 1e3] (x_64 =
                                             log10(delta/||F||), the noise feature); default 0 */
+  double seed_snap_lo;                   /* >= 0: a seed below log10_alpha_lo + seed_snap_lo (decades)
+                                            starts the search at log10_alpha_lo; default 0 (off) */
 } fr3d_dp_opts;
 
 typedef struct {
@@ -182,8 +184,9 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
 /* Choose alpha by the discrepancy principle and write zeta at that alpha.
  * opts NULL = defaults.  Plain rule: evaluate the range ends (hi first), then
  * bisect in log10 alpha; any point with |r/T - 1| <= tol is accepted.  With
- * use_predictor: start from the predicted alpha (accepted inside [accept_lo,
- * accept_hi] or within tol), walk toward the sign change with doubling steps
+ * use_predictor: start from the predicted alpha (clipped to the range; lo
+ * itself when it is within seed_snap_lo decades above lo; accepted inside
+ * [accept_lo, accept_hi] or within tol), walk toward the sign change with doubling steps
  * from seed_walk decades, then Illinois regula falsi on r/T - 1 inside the
  * bracket; with seed_slope > 0 instead secant steps on ln(r/T), the first
  * with the slope seed_slope per decade, later ones through the last two

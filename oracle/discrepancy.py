@@ -109,9 +109,19 @@ def bisection(evaluate, delta, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, tau=1.0,
     return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace)
 
 
+def _start(t0, lo, hi, snap):
+    """First point of a seeded search: the seed clipped to [lo, hi]; a seed
+    less than ``snap`` decades above lo starts at lo (for such a seed the
+    root is often below the range, and then the point at lo ends the search
+    at once)."""
+    t = min(max(float(t0), lo), hi)
+    return lo if t < lo + snap else t
+
+
 def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=0.9, acc_hi=1.1,
-           tau=1.0, h_op=0.0, mu=0.0, walk=0.25):
-    """Seeded search from a predicted log10 alpha ``t0``."""
+           tau=1.0, h_op=0.0, mu=0.0, walk=0.25, snap=0.0):
+    """Seeded search from a predicted log10 alpha ``t0`` (first point as in
+    ``_start``)."""
     ev = _Counter(evaluate, delta, tau, h_op, mu)
 
     def ok(ratio):
@@ -120,7 +130,7 @@ def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=
     def out(t, flags):
         return dict(alpha=10.0 ** t, t=t, flags=flags, n_evals=ev.n, trace=ev.trace)
 
-    t = min(max(float(t0), lo), hi)
+    t = _start(t0, lo, hi, snap)
     rho, ratio, r, zn = ev(t)
     if ok(ratio):
         return out(t, 0)
@@ -166,7 +176,7 @@ def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=
 
 
 def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=0.9, acc_hi=1.1,
-                  tau=1.0, h_op=0.0, mu=0.0, slope=0.03):
+                  tau=1.0, h_op=0.0, mu=0.0, slope=0.03, snap=0.0):
     """Seeded search refined by secant steps on g(t) = ln(r / T) (a proposal
     for the learned path; the paper has no predictor).  From the seed the
     first step is Newton's with the assumed slope ``slope`` of g per decade
@@ -176,7 +186,8 @@ def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, 
     regula falsi point, with the Illinois halving of an end kept twice.
     A point at hi below the target ends with NOROOT_HIGH, one at lo above it
     with NOROOT_LOW; after max_steps steps the answer is the upper bracket
-    end (MAXITER), evaluated if it was not the last point."""
+    end (MAXITER), evaluated if it was not the last point.  The first point
+    is the seed as in ``_start``."""
     ev = _Counter(evaluate, delta, tau, h_op, mu)
 
     def ok(ratio):
@@ -189,7 +200,7 @@ def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, 
         # ln(r / T), kept finite
         return min(max(math.log(ratio), -50.0), 50.0) if ratio > 0 else -50.0
 
-    t = min(max(float(t0), lo), hi)
+    t = _start(t0, lo, hi, snap)
     rho, ratio, _, _ = ev(t)
     if ok(ratio):
         return out(t, 0)

@@ -3,7 +3,8 @@
     from paper_1703_01216_amd import calibrate
     cal = calibrate.seed_calibration(ctx, Fs, deltas)
     ctx.predictor_set_calibration(cal["coef"])
-    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_slope_x=cal["seed_slope_x"])
+    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_slope_x=cal["seed_slope_x"],
+                             seed_snap_lo=cal["seed_snap_lo"])
 
 The predictor is trained on a mix of grids, source sets and heights of Y; on
 one fixed geometry its seeds carry an error that depends on the data's
@@ -20,14 +21,19 @@ slope d ln r / d log10 alpha at t* (central difference over +-h decades),
 t_net the network's output and x the 65 raw features (x_64 = log10(delta/
 ||F||)); instances without a root in the range are skipped.  coef holds
 c_0 and the c_k for the raw features (the library's
-fr3d_predictor_set_calibration).  Everything runs through the library's
-calls.
+fr3d_predictor_set_calibration).  seed_snap_lo = SNAP_SIGMAS times the
+standard deviation of the shift's residual: a calibrated seed closer than
+that to the lower end of the range is about as likely to have its root
+below the range (the network was trained with such instances labelled at
+the range end), so the search starts at the end, where such an instance
+ends after one evaluation.  Everything runs through the library's calls.
 """
 from __future__ import annotations
 
 import math
 
 RIDGE = 1.0
+SNAP_SIGMAS = 2.0
 
 
 def seed_calibration(ctx, Fs, deltas, h=0.05, lo=-8.0, hi=0.0):
@@ -80,6 +86,7 @@ def fit(X, dt, ls, ridge=RIDGE):
     coef[0] = w[0] - float(np.sum(coef[1:][live] * mu[live]))
     B = np.c_[np.ones(len(X)), X[:, 64]]
     sl = np.linalg.lstsq(B, ls, rcond=None)[0]
+    res = float(np.std(dt - A @ w))
     return dict(coef=coef.tolist(), seed_slope=float(10.0 ** sl[0]), seed_slope_x=float(sl[1]),
-                instances=len(X), shift_residual_decades=float(np.std(dt - A @ w)),
+                seed_snap_lo=SNAP_SIGMAS * res, instances=len(X), shift_residual_decades=res,
                 slope_residual_log10=float(np.std(ls - B @ sl)))

@@ -747,7 +747,8 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
   if (!(d->log10_alpha_lo < d->log10_alpha_hi) || !std::isfinite(d->log10_alpha_lo) ||
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
-      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x))
+      !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x) ||
+      !(d->seed_snap_lo >= 0) || !std::isfinite(d->seed_snap_lo))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
@@ -786,6 +787,7 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   v.walk = d.seed_walk;
   v.slope = d.seed_slope;
   v.slope_x = d.seed_slope_x;
+  v.snap = d.seed_snap_lo;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -967,6 +969,7 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->seed_walk = 0.25;
   o->seed_slope = 0.0;
   o->seed_slope_x = 0.0;
+  o->seed_snap_lo = 0.0;
   o->candidates = 0;
 }
 

@@ -80,6 +80,7 @@ struct Ctrl {
   int32_t side, up;
   double slope;      // assumed d ln(r/T) / d log10 alpha of the secant refinement (0: walk)
   double slope_x;    // secant slope 10^(slope_x x_64) with the noise feature x_64 of the data
+  double snap;       // a seed below lo + snap starts at lo
   int32_t have;      // secant refinement: bit 0 a known, bit 1 b known, bit 2 previous point known
   // K-candidate search
   int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer

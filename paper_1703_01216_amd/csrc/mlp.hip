@@ -33,7 +33,8 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
 // point of a seeded search, and the secant slope from the noise feature
 // x_64 = log10(delta/||F||).
 __device__ __forceinline__ void write_seed(Ctrl* seed, double la, double dc, const float* X) {
-  const double t = fmin(fmax(la + dc, seed->lo), seed->hi);
+  double t = fmin(fmax(la + dc, seed->lo), seed->hi);
+  if (t < seed->lo + seed->snap) t = seed->lo;
   seed->t = t;
   seed->alpha_abs = pow(10.0, t) * seed->a_scale;
   seed->state = ST_SEED;

@@ -24,6 +24,7 @@ def test_raw_coefficients_reproduce_the_fit():
     assert out["shift_residual_decades"] < 1e-7
     assert out["seed_slope"] == pytest.approx(0.004, rel=1e-9)
     assert out["seed_slope_x"] == pytest.approx(-0.5, abs=1e-9)
+    assert out["seed_snap_lo"] == calibrate.SNAP_SIGMAS * out["shift_residual_decades"]
     # with ridge the raw coefficients still give the standardised model's predictions
     out = calibrate.fit(X, dt + 0.01 * rg.standard_normal(80), np.log10(s), ridge=1.0)
     c = np.array(out["coef"])

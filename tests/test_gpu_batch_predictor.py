@@ -226,10 +226,12 @@ def test_predictor_checkpoint(fr3d, tmp_path):
     assert ei.value.status == fr3d.E_INVALID
 
 
-@pytest.mark.parametrize("bias,slope,tol,shift", [(-3.0, 0.05, 1e-3, 0.0), (-6.5, 0.5, 1e-6, 0.0),
-                                                   (0.7, 0.2, 1e-3, 0.0), (-20.0, 0.03, 1e-3, 0.0),
-                                                   (-1.0, 2.0, 1e-9, 0.0), (-3.0, 0.3, 1e-6, -0.75)])
-def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
+@pytest.mark.parametrize("bias,slope,tol,shift,snap", [(-3.0, 0.05, 1e-3, 0.0, 0.0), (-6.5, 0.5, 1e-6, 0.0, 0.0),
+                                                        (0.7, 0.2, 1e-3, 0.0, 0.0), (-20.0, 0.03, 1e-3, 0.0, 0.0),
+                                                        (-1.0, 2.0, 1e-9, 0.0, 0.0), (-3.0, 0.3, 1e-6, -0.75, 0.0),
+                                                        (-7.95, 0.3, 1e-6, 0.0, 0.1), (-7.5, 0.3, 1e-6, 0.0, 0.4),
+                                                        (-7.5, 0.3, 1e-6, 0.0, 0.6)])
+def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift, snap):
     # the secant refinement after the seed takes the oracle rule's decisions
     # (FP64, same evaluations), including the range ends and MAXITER
     g = geom(16, 16, 16)
@@ -247,7 +249,7 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
     kw = dict(tol=tol, accept_lo=1.0, accept_hi=1.0, max_steps=6)
     if shift:
         c.predictor_set_calibration([shift] + [0.0] * 65)
-    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, **kw)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, seed_snap_lo=snap, **kw)
     khat = np.fft.fftn(sample_kernel(g))
 
     def ev(a):
@@ -256,7 +258,9 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
     # a calibration with only an intercept shifts the network's output before
     # the clip to the range
     ref = discrepancy.seeded_secant(ev, d["delta"], bias + shift, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
-                                    slope=slope)
+                                    slope=slope, snap=snap)
+    # the first point: the seed, or the lower range end for a seed within the margin
+    assert ref["trace"][0][0] == (-8.0 if bias + shift < -8.0 + snap else min(max(bias + shift, -8.0), 0.0))
     assert rep["flags"] == ref["flags"]
     assert rep["n_evals"] == ref["n_evals"]
     assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
@@ -264,8 +268,8 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift):
     assert rel_l2(host(z), o["zeta"]) < 1e-11
 
 
-@pytest.mark.parametrize("bias", [-3.0, -6.5, 0.7, -20.0])
-def test_seeded_search_matches_rule_fp64(fr3d, bias):
+@pytest.mark.parametrize("bias,snap", [(-3.0, 0.0), (-6.5, 0.0), (0.7, 0.0), (-20.0, 0.0), (-7.9, 0.2)])
+def test_seeded_search_matches_rule_fp64(fr3d, bias, snap):
     # The network's output is steered by its last bias; the device search from
     # that seed takes the oracle rule's decisions (FP64, same evaluations).
     g = geom(16, 16, 16)
@@ -280,13 +284,13 @@ def test_seeded_search_matches_rule_fp64(fr3d, bias):
     F = torch.tensor(d["F"], dtype=torch.float64, device="cuda")
     c.set_data(F, d["delta"])
     z = torch.empty_like(F)
-    rep = c.solve_discrepancy(z, use_predictor=1)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_snap_lo=snap)
     khat = np.fft.fftn(sample_kernel(g))
 
     def ev(a):
         o = tikhonov.solve_spectral(g, khat, d["F"], a)
         return o["r_norm"], o["zeta_norm"]
-    ref = discrepancy.seeded(ev, d["delta"], bias)
+    ref = discrepancy.seeded(ev, d["delta"], bias, snap=snap)
     assert rep["flags"] == ref["flags"]
     assert rep["n_evals"] == ref["n_evals"]
     assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)

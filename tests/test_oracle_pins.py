@@ -493,6 +493,29 @@ def test_seeded_secant_range_ends_and_step_limit():
     assert res["t"] == pytest.approx(-3.0, abs=1e-9)
 
 
+def test_seed_near_lower_end_starts_there():
+    tight = dict(tol=1e-9, acc_lo=1.0, acc_hi=1.0)
+    # root below the range, seed 0.05 decades above lo: with a 0.1-decade
+    # margin the first point is lo, whose residual is above the target, so
+    # the search ends there after one evaluation (two without the margin)
+    for snap, n in ((0.1, 1), (0.0, 2), (0.04, 2)):
+        res = discrepancy.seeded_secant(_loglinear(-8.3, 0.05), 1.0, -7.95, slope=0.05, snap=snap, **tight)
+        assert res["flags"] == discrepancy.PRED_FALLBACK | discrepancy.NOROOT_LOW
+        assert res["alpha"] == 1e-8 and res["n_evals"] == n
+        assert res["trace"][0][0] == (-8.0 if snap > 0.05 else -7.95)
+    # root inside the margin: from lo, Newton with the true slope of the
+    # straight line lands on the root
+    res = discrepancy.seeded_secant(_loglinear(-7.97, 0.05), 1.0, -7.95, slope=0.05, snap=0.1, **tight)
+    assert res["flags"] == discrepancy.PRED_FALLBACK and res["n_evals"] == 2
+    assert res["t"] == pytest.approx(-7.97, abs=1e-9)
+    # the walk search starts at the same point; a seed above the margin is
+    # kept as it is
+    res = discrepancy.seeded(_loglinear(-8.3, 0.05), 1.0, -7.95, snap=0.1, **tight)
+    assert res["flags"] & discrepancy.NOROOT_LOW and res["n_evals"] == 1
+    res = discrepancy.seeded_secant(_loglinear(-3.0, 0.05), 1.0, -7.85, slope=0.05, snap=0.1, **tight)
+    assert res["trace"][0][0] == -7.85
+
+
 def test_seeded_matches_bisection_answer_quality():
     # same acceptance band: both searches end inside it
     ev, delta, Fn = _identity_problem(0.02)
