@@ -56,6 +56,7 @@ typedef enum {
 #define FR3D_NAN_INPUT 8     /* a norm came out non-finite */
 #define FR3D_PRED_FALLBACK 16 /* predicted alpha rejected; the search continued */
 #define FR3D_CG_LIMIT 32      /* exact-operator solve: CG stopped at max_iter before its tolerance */
+#define FR3D_UNFINISHED 64    /* _dev solve: the search had not ended after the enqueued evaluations */
 
 /* Geometry of R and Y (Sec. 3: both are horizontal layers with the same
  * lateral footprint; Sec. 5: uniform grids, midpoint quadrature weight = the
@@ -200,6 +201,31 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
  * write zeta (n_evals = K steps + 1).  Fills *rep (synchronises). */
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
                                    fr3d_report* rep);
+
+/* fr3d_solve_alpha and fr3d_solve_discrepancy without a host
+ * synchronisation, for callers that chain a solve behind other device work
+ * or capture it into a HIP graph (stream capture on the context's stream,
+ * fr3d_set_stream): the search's first point, every evaluation the search
+ * may need (its bound: 1 for a fixed alpha; 2 + max_steps + 1 for the plain
+ * rule; 1 + max_steps + 1 seeded with seed_slope > 0; seed + walk +
+ * max_steps + 1 seeded otherwise; max_steps K-candidate steps) and a final
+ * kernel that writes the report to rep_dev are enqueued on the context's
+ * stream, and the call returns.  Evaluations enqueued after the search has
+ * ended return at once (a few microseconds per pass launch), so a small
+ * max_steps keeps that idle tail short.  rep_dev: device memory for one
+ * fr3d_report, owned by the caller; zeta_dev and rep_dev must stay valid
+ * until the stream reaches them.  The report equals the synchronous call's
+ * (n_clamped = -1); FR3D_UNFINISHED is set if the search had not ended.  The
+ * evaluations are plain kernel launches (fr3d_set_graphs does not apply), no
+ * memory is allocated or set by the host except the K-candidate workspaces on
+ * a context's first K-candidate search (run one before capturing such
+ * searches).  A captured solve replays with the delta, options and pointers
+ * of its capture.  Errors found on the host are returned: FR3D_E_INVALID
+ * (null zeta_dev or rep_dev, bad options, alpha), FR3D_E_STATE (no kernel or
+ * data, timing on: fr3d_set_timing records host-side events). */
+fr3d_status fr3d_solve_alpha_dev(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_report* rep_dev);
+fr3d_status fr3d_solve_discrepancy_dev(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
+                                       fr3d_report* rep_dev);
 
 /* Solve n instances on the lanes: for item i, set the data F_devs[i] with
  * noise level deltas[i], choose alpha by the discrepancy principle (opts,

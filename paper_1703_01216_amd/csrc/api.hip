@@ -40,6 +40,21 @@ __global__ void k_ctrl_init(Ctrl* c, Ctrl v) {
   if (v.state == ST_KARY) ctrl_kary_points(c);  // first step's candidates
 }
 
+// The report of a search, written on the device (the _dev solves).
+__global__ void k_report(const Ctrl* c, fr3d_report* r) {
+  fr3d_report o;
+  o.alpha = pow(10.0, c->t);
+  o.residual = sqrt(c->r2);
+  o.zeta_norm = sqrt(c->z2);
+  o.delta = c->delta;
+  o.target = c->target;
+  o.n_evals = c->n_evals;
+  o.flags = c->flags | (c->active ? FR3D_UNFINISHED : 0);
+  o.n_clamped = -1;
+  o.residual_full_box = c->r2_full >= 0 ? sqrt(c->r2_full) : -1.0;
+  *r = o;
+}
+
 // Recovery (Algorithm 1, step 4): xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2)
 // with the argument clamped at 1e-6/c0^2; per-block counts of clamped cells.
 template <typename T>
@@ -877,6 +892,18 @@ fr3d_status run_search(fr3d_ctx* c, int max_evals, fr3d_report* rep) {
   return FR3D_OK;
 }
 
+// The whole search on lane 0 with no host read: max_evals evaluations (those
+// after the search has ended return at once), then the report on the device.
+fr3d_status enqueue_search(fr3d_ctx* c, int max_evals, fr3d_report* rep_dev) {
+  Lane& L = c->lanes[0];
+  fr3d_status s;
+  for (int i = 0; i < max_evals; ++i)
+    if ((s = enqueue_eval(c, L))) return s;
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, L.stream, (const Ctrl*)L.ctrl, rep_dev);
+  LCHK(c, hipGetLastError());
+  return FR3D_OK;
+}
+
 bool need(fr3d_ctx* c, bool kernel, bool data) {
   if (kernel && !c->has_kernel) { fail(c, FR3D_E_STATE, "no kernel loaded"); return false; }
   if (data && !c->lanes[0].has_data) { fail(c, FR3D_E_STATE, "no data set"); return false; }
@@ -1290,6 +1317,30 @@ fr3d_status fr3d_solve_discrepancy(fr3d_ctx* c, const fr3d_dp_opts* o, void* zet
   int max_evals = 0;
   if ((s = start_search(c, c->lanes[0], d, zeta, &max_evals))) return s;
   return run_search(c, max_evals, rep);
+}
+
+fr3d_status fr3d_solve_alpha_dev(fr3d_ctx* c, double alpha, void* zeta, fr3d_report* rep_dev) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, true)) return FR3D_E_STATE;
+  if (!zeta || !rep_dev) return fail(c, FR3D_E_INVALID, "zeta or rep_dev is null");
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(c, FR3D_E_INVALID, "alpha must be finite and > 0");
+  if (c->timing) return fail(c, FR3D_E_STATE, "timing is on (host-side events); turn it off for _dev solves");
+  fr3d_status s = fixed_search(c, c->lanes[0], alpha, zeta);
+  if (s) return s;
+  return enqueue_search(c, 1, rep_dev);
+}
+
+fr3d_status fr3d_solve_discrepancy_dev(fr3d_ctx* c, const fr3d_dp_opts* o, void* zeta, fr3d_report* rep_dev) {
+  if (!c) return FR3D_E_INVALID;
+  if (!need(c, true, true)) return FR3D_E_STATE;
+  if (!zeta || !rep_dev) return fail(c, FR3D_E_INVALID, "zeta or rep_dev is null");
+  if (c->timing) return fail(c, FR3D_E_STATE, "timing is on (host-side events); turn it off for _dev solves");
+  fr3d_dp_opts d;
+  fr3d_status s = check_opts(c, o, &d);
+  if (s) return s;
+  int max_evals = 0;
+  if ((s = start_search(c, c->lanes[0], d, zeta, &max_evals))) return s;
+  return enqueue_search(c, max_evals, rep_dev);
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfr3d.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE = 0, 1, 2, 3, 4
 CG_LIMIT = 32
+UNFINISHED = 64
 NOROOT_HIGH, NOROOT_LOW, MAXITER, NAN_INPUT, PRED_FALLBACK = 1, 2, 4, 8, 16
 
 EXPORTED = [
@@ -29,7 +30,7 @@ EXPORTED = [
     "fr3d_get_data_spectrum", "fr3d_get_features", "fr3d_get_smax", "fr3d_set_timing",
     "fr3d_get_timing", "fr3d_status_string", "fr3d_last_error", "fr3d_set_lanes", "fr3d_solve_batch", "fr3d_solve_group", "fr3d_set_graphs", "fr3d_set_filter", "fr3d_load_layered", "fr3d_solve_exact", "fr3d_solve_exact_discrepancy",
     "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics", "fr3d_get_singular_values",
-    "fr3d_predictor_set_calibration",
+    "fr3d_predictor_set_calibration", "fr3d_solve_alpha_dev", "fr3d_solve_discrepancy_dev",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
     "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
 ]
@@ -65,6 +66,13 @@ class Report(ctypes.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+    @classmethod
+    def from_device(cls, rep_dev):
+        """Decode a report written to device memory by a _dev solve (a uint8
+        tensor of ctypes.sizeof(Report) bytes; copied to the host here)."""
+        raw = bytes(rep_dev.cpu().numpy().tobytes())
+        return cls.from_buffer_copy(raw[:ctypes.sizeof(cls)]).as_dict()
+
 
 class Fr3dError(RuntimeError):
     def __init__(self, status, msg):
@@ -86,6 +94,8 @@ def load_library(path: str = LIB_PATH):
         "fr3d_set_data": (I32, [P, P, D]),
         "fr3d_solve_alpha": (I32, [P, D, P, ctypes.POINTER(Report)]),
         "fr3d_solve_discrepancy": (I32, [P, ctypes.POINTER(DpOpts), P, ctypes.POINTER(Report)]),
+        "fr3d_solve_alpha_dev": (I32, [P, D, P, P]),
+        "fr3d_solve_discrepancy_dev": (I32, [P, ctypes.POINTER(DpOpts), P, P]),
         "fr3d_recover_c": (I32, [P, P, P, D, P, ctypes.POINTER(I64)]),
         "fr3d_source_potential": (I32, [P, D, P]),
         "fr3d_apply_operator": (I32, [P, P, P]),
@@ -241,6 +251,25 @@ class Context:
         self._chk(self._lib.fr3d_solve_discrepancy(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
                                                    ctypes.byref(rep)))
         return rep.as_dict()
+
+    def _rep_dev(self, rep_dev):
+        if rep_dev is None or not rep_dev.is_cuda or rep_dev.dtype != self.torch.uint8 or \
+                rep_dev.numel() < ctypes.sizeof(Report) or not rep_dev.is_contiguous():
+            raise ValueError(f"rep_dev must be a contiguous uint8 cuda tensor of >= {ctypes.sizeof(Report)} bytes")
+        return ctypes.c_void_p(rep_dev.data_ptr())
+
+    def solve_alpha_dev(self, alpha, zeta, rep_dev):
+        """fr3d_solve_alpha_dev: enqueued without a host synchronisation; the
+        report goes to rep_dev (decode with Report.from_device)."""
+        self._chk(self._lib.fr3d_solve_alpha_dev(self._ctx, float(alpha), self._arr(zeta, "zeta"),
+                                                 self._rep_dev(rep_dev)))
+
+    def solve_discrepancy_dev(self, zeta, rep_dev, opts: DpOpts | None = None, **kw):
+        """fr3d_solve_discrepancy_dev: the whole search enqueued without a host
+        synchronisation; the report goes to rep_dev."""
+        o = opts if opts is not None else default_opts(**kw)
+        self._chk(self._lib.fr3d_solve_discrepancy_dev(self._ctx, ctypes.byref(o), self._arr(zeta, "zeta"),
+                                                       self._rep_dev(rep_dev)))
 
     def solve_per_frequency(self, zeta, alphas=None, flags=None, opts: DpOpts | None = None, **kw):
         """One alpha per lateral frequency (fr3d_solve_per_frequency); alphas
