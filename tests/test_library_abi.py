@@ -78,3 +78,32 @@ def test_struct_layouts_match_header():
     assert fr3d.Report.residual_full_box.offset == 56
     assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 120 and fr3d.DpOpts.seed_walk.offset == 80 and fr3d.DpOpts.seed_slope.offset == 96 and fr3d.DpOpts.seed_snap_lo.offset == 112
     assert fr3d.DpOpts.candidates.offset == 88
+
+
+def test_ctypes_layouts_equal_c_compiler_layouts(tmp_path):
+    # every field offset and struct size of the binding against what a C
+    # compiler makes of include/fr3d.h
+    import shutil
+    import subprocess
+    from paper_1703_01216_amd import fr3d
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fr3d_geom": fr3d.Geom, "fr3d_dp_opts": fr3d.DpOpts, "fr3d_report": fr3d.Report}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "fr3d.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
