@@ -96,6 +96,24 @@ def test_features(fr3d, shape, precision):
     assert np.abs(host(feat) - x).max() < 1e-4
 
 
+def test_features_bench_geometry(fr3d):
+    # the radial-energy epilogue of the forward z pass at 128^3 -> 256^3
+    # (FP32, the tile variant the bench runs): every bin's energy and the
+    # features against the oracle's binning of the FP64 spectrum
+    g = geom(128, 128, 128)
+    c = ctx_for(fr3d, g, 32)
+    c.apply_tuning()
+    F = np.random.default_rng(5).standard_normal(g.shape)
+    Fd = dev(F, 32)
+    Fh = host(Fd)
+    delta = 0.03 * np.linalg.norm(Fh)
+    c.set_data(Fd, delta)
+    feat, en = c.get_features()
+    x, E = features.features(np.fft.fftn(pad(g, Fh)), delta, np.linalg.norm(Fh))
+    assert np.abs(host(en) - E).max() < 2e-6 * E.max()
+    assert np.abs(host(feat) - x).max() < 1e-4
+
+
 @pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 4), (16, 16, 16), (24, 12, 32), (32, 32, 32), (48, 48, 48)])
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("alpha", [1e-2, 1e-4])
