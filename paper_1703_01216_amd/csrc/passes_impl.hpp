@@ -167,7 +167,6 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
   __shared__ double bins[64];
-  __shared__ long long thr[65];  // thr[b] = 3 b^2 L: a point is in bin b iff thr[b] <= 4096 U < thr[b+1]
   const int tid = threadIdx.x;
   const int py = a.py;
   int kx, tile;
@@ -199,7 +198,6 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
   if (MODE == 0 && tid < 64) bins[tid] = 0.0;
-  if (MODE == 0 && tid < 65) thr[tid] = (long long)tid * tid * a.bg.L3;
 #pragma unroll
   for (int i = 0; i < PE::n; ++i) {
     const int e = tid + i * NT;
@@ -229,30 +227,38 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       acc += w * ((double)u.x * u.x + (double)u.y * u.y);
     };
     if constexpr (C <= NT && NT % C == 0) {
-      // each thread walks a run of consecutive kz in one column: its bin
-      // changes rarely, so few LDS atomics, and it is found by stepping from
-      // the previous point's bin with the threshold table (the exact rule
-      // only for the first point)
+      // each thread walks a run of consecutive kz in one column, so its bin
+      // changes rarely and few LDS atomics are needed.  A point's bin is
+      // floor(sqrt(4096 U / 3L)) capped at 63 (the rule of energy_bin),
+      // taken from an FP32 estimate: q = 4096 U / 3L <= 4096 and a few
+      // roundings of 6e-8 relative keep sqrt(q) within 2e-5 of its value,
+      // so the floor is exact unless sqrt(q) lies within 1e-4 of an
+      // integer; there the rule is applied exactly in FP64 (4096 U and
+      // b^2 3L are integers below 2^36).  No branch on the common path and
+      // no table in LDS.
       constexpr int RPC = C * P / NT;
       const int col = tid % C, k0 = (tid / C) * RPC;
       const int ky = ky0 + col;
       if (ky < py) {
         const long long mx = kx <= a.bg.px / 2 ? kx : kx - a.bg.px;
         const long long my = ky <= a.bg.py / 2 ? ky : ky - a.bg.py;
-        const long long cxy = mx * mx * a.bg.fx + my * my * a.bg.fy;
-        int b = -1;
+        const double cxy16 = 16384.0 * (double)(mx * mx * a.bg.fx + my * my * a.bg.fy);
+        const double fz16 = 16384.0 * (double)a.bg.fz, L3 = (double)a.bg.L3;
+        const float cxy16f = (float)cxy16, fz16f = (float)fz16, invL3f = (float)(1.0 / L3);
         for (int j = 0; j < RPC; ++j) {
           const int kz = k0 + j;
           const c2<T> u = lds[kz * LD + col];
           dst[(size_t)kz * py + ky] = u;
-          const long long mz = kz <= a.bg.pz / 2 ? kz : kz - a.bg.pz;
-          const long long U4 = 16384 * (cxy + mz * mz * a.bg.fz);
-          if (b < 0) {
-            b = energy_bin(a.bg, kx, ky, kz);
-          } else {
-            while (b < 63 && thr[b + 1] <= U4) ++b;
-            while (b > 0 && thr[b] > U4) --b;
+          const int mz = kz <= a.bg.pz / 2 ? kz : kz - a.bg.pz;
+          const float sq = __builtin_amdgcn_sqrtf(fmaf((float)(mz * mz), fz16f, cxy16f) * invL3f);
+          int b = (int)sq;
+          const float fr = sq - (float)b;
+          if (fr < 1e-4f || fr > 0.9999f) {
+            const double U4 = fma((double)(mz * mz), fz16, cxy16);
+            b += (double)((b + 1) * (b + 1)) * L3 <= U4 ? 1 : 0;
+            b -= (double)(b * b) * L3 > U4 ? 1 : 0;
           }
+          b = b < 63 ? b : 63;
           if (b != cur) {
             if (cur >= 0) atomicAdd(&bins[cur], acc);
             cur = b;
