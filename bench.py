@@ -10,13 +10,23 @@ stays resident in HBM.  One step solves the whole batch with the lane
 scheduler: per instance the forward transform of F, the alpha search and the
 recovery of c.
 
-Four searches run on the same batch:
-  learned     -- the trained predictor's alpha first, then walk + regula falsi,
-                 every point accepted when |r/delta - 1| <= 1e-3 (the headline value)
-  bisection   -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
-  learned_w, bisection_w -- the same two with the wider acceptance |r/delta - 1| <= 0.1
+Searches run on the same batch (config.modes):
+  learned      -- the predictor's seed, calibrated for this geometry on untimed
+                  instances, then secant steps on ln(r/T) (a seed next to the lower
+                  range end starts there); every point accepted when
+                  |r/delta - 1| <= 1e-3 (the headline value)
+  bisection    -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
+  learned_walk -- the network's own seed, then walk + regula falsi (no calibration)
+  learned_w, bisection_w -- the learned and bisection searches with the wider
+                  acceptance |r/delta - 1| <= 0.1
+  kary16       -- the 16-candidate search
+Then a single-lane section times every pass kernel with HIP events (the
+roofline of the dominant kernel), the CPU oracle is timed on a bounded sample,
+and the uneven-size batch, the per-frequency form and the exact-operator CG
+solve are timed once each.
 
-    python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--lanes L] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--lanes L] [--modes M,...]
+                    [--calibrate C] [--graphs 0|1] [--no-cpu] [--roofline-only]
 
 Prints one JSON line.  Only the CPU-baseline leg calls the oracle.
 """
