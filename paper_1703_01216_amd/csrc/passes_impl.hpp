@@ -322,6 +322,25 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
   return !(h && tile == t);
 }
 
+// Half tiles (C ky columns: half of each 128 B line of f^): tiles 2m and
+// 2m + 1 share the lines of f^, and the mirrored pair (line pair L - 1 - m)
+// shares octant columns with them; the four run as workgroups w, w + 8,
+// w + 16, w + 24, i.e. on one XCD, so the second read of a line or of an
+// octant column hits that XCD's L2.
+__device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& plane, int& tile) {
+  const int L = (ntile + 1) / 2, G = (L + 1) / 2;  // line pairs, groups per plane
+  const int x = w & 7, s = w >> 3;
+  const int sub = s & 3;
+  const int grp = (s >> 2) * 8 + x;
+  plane = grp / G;
+  const int gi = grp % G;
+  if (plane >= nplane) return false;
+  const int m2 = L - 1 - gi;
+  if (sub >= 2 && m2 == gi) return false;  // the middle line pair is its own mirror
+  tile = 2 * (sub < 2 ? gi : m2) + (sub & 1);
+  return tile < ntile;
+}
+
 template <typename T, int P, int MODE, int SH, bool KM>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
@@ -349,7 +368,9 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
   int kx, tile;
-  if (!xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)) return;
+  const bool mine = SH == 0 ? xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)
+                            : xcd_quad_map(blockIdx.x, a.kx_n, ntile, kx, tile);
+  if (!mine) return;
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
@@ -812,7 +833,8 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
     const int C = sh >= 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
     const long long ntile = cdiv(a.py, C);                                                                       \
     const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
-    dim3 g(16 * cdiv(npairs, 8));                                                                                \
+    const long long ngroups = (long long)a.kx_n * (((ntile + 1) / 2 + 1) / 2);                                   \
+    dim3 g(sh >= 1 ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));                                             \
     if (mode != 0)                                                                                               \
       return sh == 1 ? go(k_iz<T, p, 1, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0, false>, g, L, S, W1, a, tw); \
     if (a.kmode) {                                                                                               \
