@@ -202,7 +202,8 @@ fr3d_status fr3d_solve_alpha(fr3d_ctx* ctx, double alpha, void* zeta_dev, fr3d_r
 fr3d_status fr3d_solve_discrepancy(fr3d_ctx* ctx, const fr3d_dp_opts* opts, void* zeta_dev,
                                    fr3d_report* rep);
 
-/* fr3d_solve_alpha and fr3d_solve_discrepancy without a host
+/* fr3d_solve_alpha and fr3d_solve_discrepancy (Algorithm 1 steps 2-3 and
+ * the discrepancy principle of Sec. 4) without a host
  * synchronisation, for callers that chain a solve behind other device work
  * or capture it into a HIP graph (stream capture on the context's stream,
  * fr3d_set_stream): the search's first point, every evaluation the search
