@@ -326,15 +326,20 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
 // 2m + 1 share the lines of f^, and the mirrored pair (line pair L - 1 - m)
 // shares octant columns with them; the four run as workgroups w, w + 8,
 // w + 16, w + 24, i.e. on one XCD, so the second read of a line or of an
-// octant column hits that XCD's L2.
+// octant column hits that XCD's L2.  Each XCD takes a contiguous range of
+// these groups in order: the octant line at the edge between neighbouring
+// groups (the mirrored columns are offset by one) is then read by the same
+// XCD in consecutive groups.
 __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& plane, int& tile) {
   const int L = (ntile + 1) / 2, G = (L + 1) / 2;  // line pairs, groups per plane
+  const int ngroups = nplane * G, per = (ngroups + 7) / 8;  // groups per XCD
   const int x = w & 7, s = w >> 3;
-  const int sub = s & 3;
-  const int grp = (s >> 2) * 8 + x;
+  const int sub = s & 3, q = s >> 2;
+  if (q >= per) return false;
+  const int grp = x * per + q;
+  if (grp >= ngroups) return false;
   plane = grp / G;
   const int gi = grp % G;
-  if (plane >= nplane) return false;
   const int m2 = L - 1 - gi;
   if (sub >= 2 && m2 == gi) return false;  // the middle line pair is its own mirror
   tile = 2 * (sub < 2 ? gi : m2) + (sub & 1);
