@@ -155,6 +155,11 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
 // MODE 0 (data): n inputs, P outputs, fused radial-energy epilogue writing
 // per-workgroup bin partials.  MODE 1 (kernel spectrum): P inputs, only
 // kz <= P/2 and ky <= Py/2 stored (the octant).
+// Slot of a forward z workgroup's bin partials (the grid is a multiple of
+// 8 workgroups): workgroups of one XCD (w mod 8) fill adjacent slots, so each
+// 128 B line of a bin's row of partials is written from one XCD's L2.
+__device__ __forceinline__ int bins_slot(int w, int nblk) { return (w & 7) * (nblk >> 3) + (w >> 3); }
+
 template <typename T, int P, int MODE, int SH>
 __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* __restrict__ S, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     kx = pidx / npr;
     tile = 2 * (pidx % npr) + (sidx & 1);
     if (kx >= a.kx_n || tile >= ntile) {  // padding of the grid: an empty partial
-      if (tid < 64) a.bins_part[(size_t)tid * gridDim.x + blockIdx.x] = 0.0;
+      if (tid < 64) a.bins_part[(size_t)tid * gridDim.x + bins_slot(blockIdx.x, gridDim.x)] = 0.0;
       return;
     }
   } else {
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();
     const int bid = blockIdx.x, nblk = gridDim.x;
-    if (tid < 64) a.bins_part[(size_t)tid * nblk + bid] = bins[tid];
+    if (tid < 64) a.bins_part[(size_t)tid * nblk + bins_slot(bid, nblk)] = bins[tid];
   } else {
     const int oy = py / 2 + 1;
     c2<T>* dst = S + (size_t)kx * NOUT * oy;
