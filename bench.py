@@ -49,8 +49,8 @@ PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
 # sources with this digest; see profiles/passes_256cube_traffic.md.
-MEASURED_TRAFFIC = {"digest": "b30b2998b7b02209", "n": 128,
-                    "bytes": {"inv_z": 170.0e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 110.0e6,
+MEASURED_TRAFFIC = {"digest": "1aa75ca38983bf9d", "n": 128,
+                    "bytes": {"inv_z": 170.0e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 103.7e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
 
 
