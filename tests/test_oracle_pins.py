@@ -594,6 +594,45 @@ def test_model_example_v0_closed_form():
     assert -ex["A0"] / (4 * math.pi) * v == pytest.approx(ref, rel=1e-15)
 
 
+def _model_example_cells():
+    # Sec. 6 geometry on a grid where (0, 0, 1.5) is a cell centre: R = [-10, 10]^2 x [1, 2]
+    # on 5 x 5 x 3 cells (h = 4, hz = 1/3), Y five layer thicknesses above R (D = 15).
+    # The oracle's coordinates start at R's corner, so the model example's are the
+    # oracle's shifted by (-10, -10, +1).
+    mg = inputs.model_geometry(5, 3)
+    g = Geom(mg["nx"], mg["ny"], mg["nz"], h=mg["h"], D=mg["D"], hz=mg["hz"])
+    return g, np.array([-10.0, -10.0, 1.0])
+
+
+def test_sources_are_the_model_example_cross():
+    # Sec. 6: sources at (0,0,z0), (+-8,0,z0), (0,+-8,z0) for z0 = 3 and 5.  A lateral
+    # offset of 0.4 (n - 1) cells, a height off by a cell or a swapped axis fails here.
+    g, shift = _model_example_cells()
+    with open(os.path.join(GOLDEN, "model_example.json")) as fh:
+        ex = json.load(fh)
+    got = sources(g) + shift
+    ref = np.array(ex["sources"], dtype=np.float64)
+    key = lambda a: sorted(map(tuple, np.round(a, 12)))  # noqa: E731
+    assert key(got) == key(ref)
+    assert np.max(np.abs(got - ref)) < 1e-12  # same order: centre, -x, +x, -y, +y per height
+
+
+def test_v0_at_model_example_point_closed_form():
+    # V0 = -(A0/4pi) sum_l 1/|x - x_l| (Sec. 2) with A0 = 1 (g = e^-t, Sec. 6) at the
+    # cell centre (0, 0, 1.5): distances 1.5 and 3.5 to the centres of the two
+    # heights and sqrt(64 + 1.5^2), sqrt(64 + 3.5^2) to the four lateral points.
+    g, shift = _model_example_cells()
+    zc = (np.arange(g.nz) + 0.5) * g.hv + shift[2]
+    xc = (np.arange(g.nx) + 0.5) * g.h + shift[0]
+    k, i = int(np.argmin(np.abs(zc - 1.5))), int(np.argmin(np.abs(xc)))
+    assert abs(zc[k] - 1.5) < 1e-14 and abs(xc[i]) < 1e-14
+    ref = -(1 / (4 * math.pi)) * (1 / 1.5 + 4 / math.sqrt(64 + 1.5 ** 2) + 1 / 3.5 + 4 / math.sqrt(64 + 3.5 ** 2))
+    V = v0(g)
+    assert abs(V[k, i, i] - ref) < 1e-14 * abs(ref)
+    # linear in A0
+    assert abs(v0(g, A0=2.5)[k, i, i] - 2.5 * ref) < 1e-14 * abs(ref)
+
+
 def test_v0_negative_and_harmonic_in_R():
     # V0 = -(A0/4pi) sum 1/|x - x_l| < 0 (Sec. 2) and harmonic away from the sources.
     g = Geom(12, 12, 8)
@@ -653,6 +692,26 @@ def test_radial_energy_parseval():
     fh = np.fft.fftn(pad(g, F))
     E = features.radial_energy(fh)
     assert E.sum() == pytest.approx(np.prod(g.pshape) * np.sum(F * F), rel=1e-12)
+
+
+def test_features_values_on_a_hand_built_spectrum():
+    # 8^3 spectrum with |f^|^2 = 4 at k = 0 (bin 0), 9 at k = (0,0,1) and at its mirror
+    # (0,0,7): radius sqrt(u/3) with u = (2/8)^2, 64 sqrt(1/48) = 9.24 -> bin 9, and 1 at
+    # the corner (4,4,4) (radius 1 -> bin 63).  Mean bin energy (4 + 18 + 1)/64;
+    # empty bins give log10(1e-30) = -30; x_64 = log10(delta/||F||).
+    fh = np.zeros((8, 8, 8), complex)
+    fh[0, 0, 0] = 2.0
+    fh[0, 0, 1] = 3.0
+    fh[0, 0, 7] = 3.0j
+    fh[4, 4, 4] = -1.0
+    x, E = features.features(fh, 0.5, 20.0)
+    ref = np.full(65, -30.0)
+    ref[0] = math.log10(4 * 64 / 23)
+    ref[9] = math.log10(18 * 64 / 23)
+    ref[63] = math.log10(64 / 23)
+    ref[64] = math.log10(0.025)
+    assert np.max(np.abs(x - ref)) < 1e-13
+    assert E[0] == 4 and E[9] == 18 and E[63] == 1 and E.sum() == 23
 
 
 # ---------------------------------------------------------------- MLP reference
