@@ -106,6 +106,7 @@ def test_predictor_forward_matches_oracle(fr3d):
     y = torch.empty(200, dtype=torch.float32, device="cuda")
     c.predictor_forward(torch.tensor(X, device="cuda"), y)
     yo, _ = mlp.forward(p32, X.astype(np.float64), bf16=True)
+    print(f"[predictor] forward rel_l2 {rel_l2(host(y), yo):.3e}", flush=True)
     assert rel_l2(host(y), yo) < 2e-3
     # normalisation and de-normalisation are applied around the network
     nm = identity_norm()
@@ -174,6 +175,8 @@ def test_predictor_gradients_match_oracle(fr3d):
     yo, cache = mlp.forward(p32, X.astype(np.float64), bf16=True)
     go = mlp.backward(p32, cache, t.astype(np.float64), bf16=True)
     gg = unflat(host(grad))
+    for name, _ in mlp.PARAM_SHAPES:
+        print(f"[predictor] gradient {name} rel_l2 {rel_l2(gg[name], go[name]):.3e}", flush=True)
     for name, _ in mlp.PARAM_SHAPES:
         assert rel_l2(gg[name], go[name]) < 2e-3, name
     assert float(host(loss)[0]) == pytest.approx(mlp.loss(yo, t), rel=2e-3)
