@@ -261,6 +261,29 @@ fr3d_status fr3d_solve_group(int32_t n, fr3d_ctx* const* ctxs, const void* const
 fr3d_status fr3d_recover_c(fr3d_ctx* ctx, const void* zeta_dev, const void* V0_dev, double c0,
                            void* c_dev, int64_t* n_clamped);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * recovery of fr3d_recover_c without a context, without any allocation and
+ * without a host synchronisation.  c = (1/c0^2 - zeta/V0)^(-1/2) over n
+ * cells with the same clamp as fr3d_recover_c (identical c, identical
+ * count); precision 32 (float arrays) or 64 (double arrays); zeta_dev,
+ * V0_dev, c_dev: n device values each, any layout (elementwise), owned by
+ * the caller; n_clamped_dev: one device int64 that receives the number of
+ * clamped cells, or NULL to skip the count.  Work is enqueued on hip_stream
+ * (a hipStream_t, NULL = the null stream) of the current device.
+ * Workspace: the per-workgroup partial counts live in a static device array
+ * of 2048 doubles (16 KiB), one per device, held until the process ends;
+ * every call on a device shares it, so calls that overlap on one device
+ * (concurrent streams or host threads) race -- serialise them.  Nothing in
+ * it needs clearing (each call writes every partial it reads).
+ * FR3D_E_INVALID: precision not 32 or 64, n < 0 or n > FR3D_NOALLOC_MAX_CELLS,
+ * a null array with n > 0, c0 not finite and > 0.  FR3D_E_DEVICE: the
+ * current device is not a gfx950, its workspace address could not be
+ * obtained, or a launch failed.  n = 0 writes a count of 0. */
+#define FR3D_NOALLOC_MAX_CELLS (((int64_t)1) << 40)
+fr3d_status fr3d_recover_c_noalloc(int32_t precision, int64_t n, const void* zeta_dev, const void* V0_dev, double c0,
+                                   void* c_dev, int64_t* n_clamped_dev, void* hip_stream);
+
 /* V0 on R's cell centres for the geometry's ten point sources (Sec. 6):
  * V0(x) = -(A0/4 pi) sum_l 1/|x - x_l|.  The sources form the model example's
  * cross (lateral centre and +-0.4 n along x and y) at heights nz + G/4 and

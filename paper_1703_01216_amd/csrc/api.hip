@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -70,6 +71,17 @@ __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, 
   }
   cl = block_sum<NT>(cl, red);
   if (threadIdx.x == 0) part[blockIdx.x] = cl;
+}
+
+// The clamped-cell count: the sum of k_recover's nblk partials in a fixed
+// order (one workgroup), as an integer (every partial is a whole number
+// below 2^53, so the FP64 sum is exact).
+__global__ void k_clamp_count(const double* __restrict__ part, int nblk, int64_t* out) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += NT) s += part[k];
+  s = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) *out = (int64_t)s;
 }
 
 // out[j] = sum over k < nblk of part[k*stride + j] for j < nout (one workgroup, fixed order).
@@ -912,12 +924,16 @@ bool need(fr3d_ctx* c, bool kernel, bool data) {
 
 long long ncells(fr3d_ctx* c) { return (long long)c->g.nx * c->g.ny * c->g.nz; }
 
+// Workgroups of a recovery over n cells (grid-stride beyond), one clamp-count partial each.
+constexpr int RECOVER_MAX_BLOCKS = 2048;
+unsigned recover_blocks(long long n) { return (unsigned)std::min<long long>((n + NT - 1) / NT, RECOVER_MAX_BLOCKS); }
+
 fr3d_status launch_recover(fr3d_ctx* c, Lane& L, const void* zeta, const void* V0, double c0, void* cout,
                            bool count) {
   const long long n = ncells(c);
   double* part = (double*)L.norm_part;  // >= 2 nz ny doubles
   const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
-  const unsigned nb = (unsigned)std::min<long long>((n + NT - 1) / NT, 2048);
+  const unsigned nb = recover_blocks(n);
   if (c->esz == 8)
     hipLaunchKernelGGL(k_recover<double>, dim3(nb), dim3(NT), 0, L.stream, (const double*)zeta, (const double*)V0,
                        ic2, fl, (double*)cout, n, part);
@@ -1551,6 +1567,69 @@ fr3d_status fr3d_recover_c(fr3d_ctx* c, const void* zeta, const void* V0, double
   if (ncl) {
     HIPCHK(c, hipStreamSynchronize(L.stream));
     *ncl = (int64_t)L.scal_host[0];
+  }
+  return FR3D_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ no-allocation recovery
+// Scratch of fr3d_recover_c_noalloc: the per-workgroup clamp-count partials
+// (16 KiB).  Each device holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name in host code is not a device
+// address).
+static __device__ __align__(256) double scratch[RECOVER_MAX_BLOCKS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's scratch address, looked up once per device with that
+// device current; null if the device is not a usable gfx950 or the lookup fails.
+double* noalloc_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (noalloc_ptr[dev]) return noalloc_ptr[dev];
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return nullptr;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+  noalloc_ptr[dev] = (double*)ptr;
+  return noalloc_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+fr3d_status fr3d_recover_c_noalloc(int32_t precision, int64_t n, const void* zeta, const void* V0, double c0,
+                                   void* cout, int64_t* ncl_dev, void* stream) {
+  if (precision != 32 && precision != 64) return FR3D_E_INVALID;
+  if (n < 0 || n > FR3D_NOALLOC_MAX_CELLS) return FR3D_E_INVALID;
+  if (n > 0 && (!zeta || !V0 || !cout)) return FR3D_E_INVALID;
+  if (!(c0 > 0) || !std::isfinite(c0)) return FR3D_E_INVALID;
+  double* part = noalloc_scratch();
+  if (!part) return FR3D_E_DEVICE;
+  const hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = recover_blocks(n);
+  const double ic2 = 1.0 / (c0 * c0), fl = 1e-6 / (c0 * c0);
+  if (nb > 0) {
+    if (precision == 64)
+      hipLaunchKernelGGL(k_recover<double>, dim3(nb), dim3(NT), 0, st, (const double*)zeta, (const double*)V0, ic2,
+                         fl, (double*)cout, (long long)n, part);
+    else
+      hipLaunchKernelGGL(k_recover<float>, dim3(nb), dim3(NT), 0, st, (const float*)zeta, (const float*)V0, ic2, fl,
+                         (float*)cout, (long long)n, part);
+    if (hipGetLastError() != hipSuccess) return FR3D_E_DEVICE;
+  }
+  if (ncl_dev) {
+    hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(NT), 0, st, (const double*)part, (int)nb, ncl_dev);
+    if (hipGetLastError() != hipSuccess) return FR3D_E_DEVICE;
   }
   return FR3D_OK;
 }

@@ -32,7 +32,7 @@ EXPORTED = [
     "fr3d_solve_per_frequency", "fr3d_load_kernel_samples", "fr3d_set_diagnostics", "fr3d_get_singular_values",
     "fr3d_predictor_set_calibration", "fr3d_solve_alpha_dev", "fr3d_solve_discrepancy_dev",
     "fr3d_predictor_set", "fr3d_predictor_get", "fr3d_predictor_forward", "fr3d_predictor_train_step",
-    "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile",
+    "fr3d_predictor_save", "fr3d_predictor_load", "fr3d_set_tile", "fr3d_recover_c_noalloc",
 ]
 PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 TUNING_PATH = os.path.join(HERE, "data", "tuning.json")
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "fr3d_solve_alpha_dev": (I32, [P, D, P, P]),
         "fr3d_solve_discrepancy_dev": (I32, [P, ctypes.POINTER(DpOpts), P, P]),
         "fr3d_recover_c": (I32, [P, P, P, D, P, ctypes.POINTER(I64)]),
+        "fr3d_recover_c_noalloc": (I32, [I32, I64, P, P, D, P, P, P]),
         "fr3d_source_potential": (I32, [P, D, P]),
         "fr3d_apply_operator": (I32, [P, P, P]),
         "fr3d_add_noise": (I32, [P, P, P, D, ctypes.POINTER(D)]),
@@ -456,6 +457,28 @@ class Context:
         n = ctypes.c_int64()
         self._chk(self._lib.fr3d_get_timing(self._ctx, int(pass_id), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def recover_c_noalloc(zeta, V0, c0, c_out, n_clamped=None, stream=None):
+    """fr3d_recover_c_noalloc: the recovery of c with no context, no device
+    allocation and no host synchronisation.  zeta, V0, c_out: contiguous cuda
+    tensors of one dtype (float32 or float64) and size; n_clamped: a one-element
+    int64 cuda tensor that receives the clamped-cell count, or None.  Enqueued
+    on `stream` (default: torch's current stream)."""
+    import torch
+    ts = (zeta, V0, c_out)
+    if any(t is None or not t.is_cuda or not t.is_contiguous() for t in ts) or \
+            len({t.dtype for t in ts}) != 1 or len({t.numel() for t in ts}) != 1 or \
+            zeta.dtype not in (torch.float32, torch.float64):
+        raise ValueError("zeta, V0, c_out must be contiguous cuda tensors of one float dtype and size")
+    if n_clamped is not None and (not n_clamped.is_cuda or n_clamped.dtype != torch.int64 or n_clamped.numel() < 1):
+        raise ValueError("n_clamped must be an int64 cuda tensor")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    prec = 64 if zeta.dtype == torch.float64 else 32
+    s = lib().fr3d_recover_c_noalloc(prec, zeta.numel(), _ptr(zeta), _ptr(V0), float(c0), _ptr(c_out),
+                                     _ptr(n_clamped), ctypes.c_void_p(st.cuda_stream))
+    if s != OK:
+        raise Fr3dError(s, lib().fr3d_status_string(s).decode())
 
 
 def solve_group(ctxs, F_list, deltas, zetas, opts: DpOpts | None = None, V0_list=None, c0=1.0, c_list=None, **kw):

@@ -57,6 +57,14 @@ def test_null_arguments_rejected(lib):
     assert lib.fr3d_destroy(None) == fr3d.E_INVALID
     assert lib.fr3d_set_data(None, None, 0.0) == fr3d.E_INVALID
     assert lib.fr3d_solve_alpha(None, 1.0, None, None) == fr3d.E_INVALID
+    # the context-free recovery checks its arguments before touching a device
+    one = ctypes.c_void_p(1)
+    assert lib.fr3d_recover_c_noalloc(16, 8, one, one, 1.0, one, None, None) == fr3d.E_INVALID
+    assert lib.fr3d_recover_c_noalloc(32, -1, one, one, 1.0, one, None, None) == fr3d.E_INVALID
+    assert lib.fr3d_recover_c_noalloc(32, (1 << 40) + 1, one, one, 1.0, one, None, None) == fr3d.E_INVALID
+    assert lib.fr3d_recover_c_noalloc(64, 8, None, one, 1.0, one, None, None) == fr3d.E_INVALID
+    assert lib.fr3d_recover_c_noalloc(64, 8, one, one, 0.0, one, None, None) == fr3d.E_INVALID
+    assert lib.fr3d_recover_c_noalloc(64, 8, one, one, float("nan"), one, None, None) == fr3d.E_INVALID
 
 
 def test_create_without_gpu_reports_device_error(lib):
