@@ -3,7 +3,7 @@
 * Batch: every item's zeta and report equal the single-solve results bit for bit
   (the lanes run the same kernels on their own streams).
 * Predictor: BF16-MFMA/FP32 forward and gradients against the BF16-emulating
-  FP64 oracle on identical weights and inputs (<= 2e-3 relative L2 per
+  FP64 oracle on identical weights and inputs (<= 1e-3 relative L2 per
   tensor); Adam against its formula; checkpoint round trip; the seeded search
   takes the oracle rule's decisions (FP64 path).
 """
@@ -107,7 +107,7 @@ def test_predictor_forward_matches_oracle(fr3d):
     c.predictor_forward(torch.tensor(X, device="cuda"), y)
     yo, _ = mlp.forward(p32, X.astype(np.float64), bf16=True)
     print(f"[predictor] forward rel_l2 {rel_l2(host(y), yo):.3e}", flush=True)
-    assert rel_l2(host(y), yo) < 2e-3
+    assert rel_l2(host(y), yo) < 1e-3
     # normalisation and de-normalisation are applied around the network
     nm = identity_norm()
     nm[:65] = 0.5
@@ -116,7 +116,7 @@ def test_predictor_forward_matches_oracle(fr3d):
     c.predictor_set(flat, nm)
     c.predictor_forward(torch.tensor(X, device="cuda"), y)
     yo2, _ = mlp.forward(p32, (X.astype(np.float64) - 0.5) / 2.0, bf16=True)
-    assert rel_l2(host(y), -4.0 + 1.5 * yo2) < 2e-3
+    assert rel_l2(host(y), -4.0 + 1.5 * yo2) < 1e-3
 
 
 def test_seed_matches_oracle_network(fr3d):
@@ -178,8 +178,8 @@ def test_predictor_gradients_match_oracle(fr3d):
     for name, _ in mlp.PARAM_SHAPES:
         print(f"[predictor] gradient {name} rel_l2 {rel_l2(gg[name], go[name]):.3e}", flush=True)
     for name, _ in mlp.PARAM_SHAPES:
-        assert rel_l2(gg[name], go[name]) < 2e-3, name
-    assert float(host(loss)[0]) == pytest.approx(mlp.loss(yo, t), rel=2e-3)
+        assert rel_l2(gg[name], go[name]) < 1e-3, name
+    assert float(host(loss)[0]) == pytest.approx(mlp.loss(yo, t), rel=1e-3)
     # lr = 0 leaves the parameters alone
     p_after, _ = c.predictor_get()
     assert np.array_equal(p_after, flat)
