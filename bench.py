@@ -11,19 +11,24 @@ scheduler: per instance the forward transform of F, the alpha search and the
 recovery of c.
 
 Searches run on the same batch (config.modes):
-  learned      -- the predictor's seed, calibrated for this geometry on untimed
-                  instances, then secant steps on ln(r/T) (a seed next to the lower
-                  range end starts there); every point accepted when
-                  |r/delta - 1| <= 1e-3 (the headline value)
+  learned      -- the predictor fine-tuned on the GPU for this geometry on
+                  untimed instances (calibrate.fine_tune), its seed refined by
+                  secant steps on ln(r/T) (a seed next to the lower range end
+                  starts there); every point accepted when |r/delta - 1| <= 1e-3
+                  (the headline value)
   bisection    -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
-  learned_walk -- the network's own seed, then walk + regula falsi (no calibration)
+  learned_net  -- the shipped network alone (no fine-tuning), secant steps with
+                  the median root slope of its training instances
   learned_w, bisection_w -- the learned and bisection searches with the wider
                   acceptance |r/delta - 1| <= 0.1
   kary16       -- the 16-candidate search
-Then a single-lane section times every pass kernel with HIP events (the
-roofline of the dominant kernel), the CPU oracle is timed on a bounded sample,
-and the uneven-size batch, the per-frequency form and the exact-operator CG
-solve are timed once each.
+Then single-lane sections time every pass kernel with HIP events at 256^3
+(the roofline of the dominant kernel) and at 512^3 (roofline_512: volumes
+far beyond the last-level cache), the batch is solved in FP64 too, the
+exact-operator CG solve, the uneven-size batch and the per-frequency form
+are timed once each, and the CPU oracle is timed on whole solves of the
+first instances (one process and 16 processes) beside per-result precision
+checks of the device's estimates against it.
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--n N] [--lanes L] [--modes M,...]
                     [--calibrate C] [--graphs 0|1] [--no-cpu] [--roofline-only]
@@ -52,6 +57,8 @@ PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 MEASURED_TRAFFIC = {"digest": "1aa75ca38983bf9d", "n": 128,
                     "bytes": {"inv_z": 170.0e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 103.7e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
+# the same at 256^3 -> 512^3 (profiles/passes_512cube_traffic.md); None until taken
+MEASURED_TRAFFIC_512 = None
 
 
 def pass_source_digest():
@@ -96,26 +103,117 @@ def make_instances(ctx, torch, n, batch, first=0):
     return Fs, deltas, V0
 
 
-def cpu_baseline(n, mean_evals, n_sample_evals=3):
-    """The oracle (numpy.fft FP64, as written) on one instance of the same workload."""
+def _oracle_task(task):
+    """Work of one oracle process (spawned, so it holds no GPU state).
+    kind "solve": one whole discrepancy solve of an instance by the oracle as
+    written (numpy.fft FP64, three transforms per alpha evaluation), either
+    the plain bisection rule or the learned search (features, the network in
+    FP64 with BF16-rounded operands, the seeded secant rule); the kernel
+    spectrum is set-up and not timed.  kind "check": the oracle's estimate
+    at the device's alpha against the device's zeta (relative L2) and the
+    oracle's r/delta there."""
     import numpy as np
 
-    from oracle import synth, tikhonov
+    from oracle import discrepancy, features, mlp, tikhonov
     from oracle.geometry import Geom, sample_kernel
-    from paper_1703_01216_amd import inputs
+    from oracle.operator import pad
 
-    g = Geom(n, n, n)
-    inst = inputs.workload_instance(2, 0, n=n)
-    d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"])
+    F, delta = task["F"], task["delta"]
+    nz, ny, nx = F.shape
+    g = Geom(nx, ny, nz)
     khat = np.fft.fftn(sample_kernel(g))
+    if task["kind"] == "check":
+        o = tikhonov.solve_spectral(g, khat, F, task["alpha"])
+        z = task["zeta"]
+        return {"rel_l2": float(np.linalg.norm(z - o["zeta"]) / np.linalg.norm(o["zeta"])),
+                "oracle_r_over_delta": o["r_norm"] / delta, "device_r_over_delta": task["residual"] / delta}
+
+    def ev(a):
+        o = tikhonov.solve_spectral(g, khat, F, a)
+        return o["r_norm"], o["zeta_norm"]
+
     t0 = time.perf_counter()
-    for k in range(n_sample_evals):
-        tikhonov.solve_spectral(g, khat, d["F"], 10.0 ** (-2 - k))
-    dt = (time.perf_counter() - t0) / n_sample_evals
-    return {"value": 1.0 / (dt * mean_evals), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample_evals} oracle alpha evaluations (numpy.fft FP64, single thread, each with its own "
-                      f"forward transform) on one {n}^3 instance padded to {2 * n}^3, {dt:.2f} s each, scaled to "
-                      f"the GPU learned path's mean {mean_evals:.2f} evaluations per solve"}
+    if task["mode"] == "bisection":
+        res = discrepancy.bisection(ev, delta, tol=1e-3)
+    else:
+        params, norm, opts = task["net"]
+        x, _ = features.features(np.fft.fftn(pad(g, F)), delta, float(np.linalg.norm(F)))
+        p, k = {}, 0
+        for name, shape in mlp.PARAM_SHAPES:
+            m = int(np.prod(shape))
+            p[name] = np.asarray(params[k:k + m], dtype=np.float64).reshape(shape)
+            k += m
+        xs = (x - norm[:65]) / norm[65:130]
+        y, _ = mlp.forward(p, xs[None, :], bf16=True)
+        t_seed = float(norm[130] + norm[131] * y[0])
+        res = discrepancy.seeded_secant(ev, delta, t_seed, tol=1e-3, acc_lo=1 - 1e-3, acc_hi=1 + 1e-3,
+                                        slope=opts["seed_slope"], snap=opts["seed_snap_lo"])
+    return {"seconds": time.perf_counter() - t0, "n_evals": res["n_evals"], "alpha": res["alpha"],
+            "flags": res["flags"]}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(Fh, deltas, net, checks, workers=16):
+    """The oracle timed on the host: whole solves (not extrapolated) of the
+    first instances of the timed batch, the learned search (the headline's
+    network and options) and bisection, on one process and on `workers`
+    processes at once (one solve each; numpy's transforms are single-threaded,
+    so a process is a core), and the per-result precision checks of the
+    device's estimates."""
+    import multiprocessing as mp
+
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    out = {"cores": workers, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    # one thread per process (the workers inherit this environment when spawned)
+    keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in keep})
+    try:
+        return _cpu_pool(out, ctx, workers, Fh, deltas, net, checks)
+    finally:
+        for k, v in keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _cpu_pool(out, ctx, workers, Fh, deltas, net, checks):
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        list(ex.map(_oracle_task, [{"kind": "check", "F": Fh[0][:8, :8, :8].copy(), "delta": 1.0, "alpha": 1.0,
+                                    "zeta": Fh[0][:8, :8, :8].copy(), "residual": 1.0}] * workers))  # warm the pool
+        for mode in (("learned", "bisection") if net is not None else ("bisection",)):
+            one = _oracle_task({"kind": "solve", "mode": mode, "F": Fh[0], "delta": deltas[0], "net": net})
+            tasks = [{"kind": "solve", "mode": mode, "F": Fh[i % len(Fh)], "delta": deltas[i % len(Fh)], "net": net}
+                     for i in range(workers)]
+            t0 = time.perf_counter()
+            res = list(ex.map(_oracle_task, tasks))
+            wall = time.perf_counter() - t0
+            out[mode] = {"solves_per_s_1_core": 1.0 / one["seconds"], "seconds_1_core": one["seconds"],
+                         "n_evals_1_core": one["n_evals"],
+                         f"solves_per_s_{workers}_cores": workers / wall, "wall_s": wall,
+                         "mean_evals": sum(r["n_evals"] for r in res) / len(res)}
+        out["precision_checks"] = list(ex.map(_oracle_task, checks))
+    mode = "learned" if net is not None else "bisection"
+    L = out[mode]
+    out.update({"value": L[f"solves_per_s_{workers}_cores"], "unit": "solves/s", "kind": "oracle",
+                "sample": f"whole oracle solves (numpy.fft FP64, the {mode} search with the headline's network "
+                          f"and options) of the first {workers} instances of the timed batch, one per process on "
+                          f"{workers} processes at once ({L['wall_s']:.1f} s wall); one process alone: "
+                          f"{L['seconds_1_core']:.1f} s per solve"})
+    return out
 
 
 def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, modes=("kary16", "bisection")):
@@ -274,6 +372,32 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return {"bytes_per_copy": 2 * nbytes, "avg_us": ms * 1e3, "GB_s": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def copy_sweep(torch, reps=20):
+    """Plain device copies that move as many bytes as each pass kernel does
+    at 128^3 -> 256^3 and 256^3 -> 512^3 (half read, half written): the
+    practical ceiling of a kernel of that size, launch and drain included.
+    Timed by events around `reps` back-to-back copies (the kernel trace of the
+    same run gives the per-kernel durations)."""
+    out = {}
+    for n in (128, 256):
+        for name, b in pass_bytes(n).items():
+            half = b // 2 // 4
+            src = torch.empty(half, dtype=torch.float32, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            out[f"{2 * n}^3 {name}"] = {"bytes": 2 * half * 4, "avg_us": us, "GB_s": 2 * half * 4 / (us * 1e-6) / 1e9}
+            del src, dst
+    return out
+
+
 def kernel_timing(ctx, torch, Fs, deltas, opts, lanes):
     """Per-pass kernel durations from HIP events recorded at each pass
     kernel's start and end, on one lane so that no two pass kernels overlap:
@@ -293,6 +417,72 @@ def kernel_timing(ctx, torch, Fs, deltas, opts, lanes):
     ctx.set_timing(False)
     ctx.set_lanes(lanes)
     return tm, el
+
+
+def pass_table(timing, pb):
+    passes = {}
+    for name, (ms, cnt) in timing.items():
+        if cnt:
+            avg = ms / cnt
+            passes[name] = {"avg_us": avg * 1e3, "launches": cnt, "GB_s": pb[name] / (avg * 1e-3) / 1e9,
+                            "frac": pb[name] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "total_ms": ms}
+    return passes
+
+
+def roofline_of(passes, pb, traffic_table, n):
+    dom = max(passes, key=lambda k: passes[k]["total_ms"])
+    ach = passes[dom]["GB_s"]
+    traffic = None
+    if traffic_table and pass_source_digest() == traffic_table["digest"] and n == traffic_table["n"]:
+        traffic = traffic_table["bytes"].get(dom)
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": pb[dom],
+            "avg_launch_us": passes[dom]["avg_us"]}
+
+
+def section_512(torch, fr3d, reps=8, alpha=1e-6):
+    """Single-lane pass timing at the precision-stress size, 256^3 grids
+    padded to 512^3 (FP32 complex volumes of 1 GiB: far beyond the 256 MB
+    last-level cache, so every pass streams from HBM): one workload-4
+    instance synthesised on the device, then `reps` forward transforms and
+    `reps` evaluations at a fixed alpha, each pass kernel timed with HIP
+    events at its own start and end."""
+    from paper_1703_01216_amd import inputs
+    n = 256
+    shape = (n, n, n)
+    c = fr3d.Context(0)
+    c.load_kernel(n, n, n, precision=32)
+    tuning = c.apply_tuning()
+    inst = inputs.workload_instance(4, 0)
+    V0 = torch.empty(shape, dtype=torch.float32, device="cuda")
+    c.source_potential(V0)
+    xi = torch.tensor(inst["xi"], dtype=torch.float32, device="cuda")
+    F = torch.empty_like(xi)
+    c.apply_operator(xi * V0, F)
+    delta = c.add_noise(F, torch.tensor(inst["noise"], dtype=torch.float32, device="cuda"), inst["delta_rel"])
+    del xi
+    z = torch.empty_like(F)
+    c.set_data(F, delta)
+    c.solve_alpha(alpha, z)
+    torch.cuda.synchronize()
+    c.set_timing(True)
+    for p in range(6):
+        c.get_timing(p)
+    for _ in range(reps):
+        c.set_data(F, delta)
+        c.solve_alpha(alpha, z)
+    torch.cuda.synchronize()
+    timing = {PASS_NAMES[p]: c.get_timing(p) for p in range(6)}
+    c.set_timing(False)
+    c.close()
+    del F, z, V0
+    torch.cuda.empty_cache()
+    pb = pass_bytes(n)
+    passes = pass_table(timing, pb)
+    roof = roofline_of(passes, pb, MEASURED_TRAFFIC_512, n)
+    roof["measured"] = (f"HIP events at kernel start/end, one lane, {reps} forward transforms and {reps} "
+                        f"evaluations at alpha = {alpha:g}")
+    return {"grid": n, "padded": 2 * n, "tile_shifts": tuning, "roofline": roof, "passes": passes}
 
 
 def run_mode(ctx, torch, Fs, deltas, V0, opts, steps, warmup, timing=False):
@@ -325,7 +515,33 @@ def run_mode(ctx, torch, Fs, deltas, V0, opts, steps, warmup, timing=False):
     return dict(solves_per_s=n / el, ms_per_step=el / steps * 1e3, mean_evals=sum(evals) / len(evals),
                 reached_delta_frac=reached / len(flags),
                 noroot_low=sum(1 for f in flags if f & 2) / len(flags),
-                fallback_frac=sum(1 for f in flags if f & 16) / len(flags)), timing_out
+                fallback_frac=sum(1 for f in flags if f & 16) / len(flags)), timing_out, zs, reps
+
+
+def fp64_section(torch, fr3d, Fs, deltas, net, learned_opts, bisect_opts, lanes, steps=2, warmup=1):
+    """The same batch solved in FP64 throughout (the paper's arithmetic,
+    Sec. 6): transforms, filter, norms and search in double, the learned
+    search with the headline's network and options, and bisection; forward
+    transform + search + recovery of c per solve, as the headline step."""
+    n = Fs[0].shape[0]
+    c = fr3d.Context(0)
+    c.load_kernel(n, n, n, precision=64)
+    c.apply_tuning()
+    c.set_lanes(lanes)
+    c.predictor_set(*net)
+    V = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    c.source_potential(V, 1.0)
+    F64 = [F.double() for F in Fs]
+    out = {}
+    zs64 = reps64 = None
+    for name, o in (("learned", learned_opts), ("bisection", bisect_opts)):
+        r, _, zs, reps = run_mode(c, torch, F64, deltas, V, o, steps, warmup)
+        out[name] = r
+        if name == "learned":
+            zs64, reps64 = zs, reps
+    out["speedup_learned_vs_bisection_tol_1e-3"] = out["learned"]["solves_per_s"] / out["bisection"]["solves_per_s"]
+    c.close()
+    return out, zs64, reps64
 
 
 def main():
@@ -338,18 +554,18 @@ def main():
     ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_1703_01216_amd", "data", "predictor.bin"))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes of the CPU baseline")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
-    ap.add_argument("--modes", default="learned,bisection,learned_walk,learned_w,bisection_w,kary16")
-    ap.add_argument("--calibrate", type=int, default=48,
-                    help="instances (not timed) that calibrate the learned seed for this geometry; 0: none")
-    ap.add_argument("--snap-sigmas", type=float, default=2.0,
-                    help="a calibrated seed within this many residual standard deviations of the lower range "
-                         "end starts the learned search at that end (0: off)")
+    ap.add_argument("--modes", default="learned,bisection,learned_net,learned_w,bisection_w,kary16")
+    ap.add_argument("--calibrate", type=int, default=96,
+                    help="instances (not timed) on which the network is fine-tuned for this geometry; 0: none")
+    ap.add_argument("--fp64", type=int, default=1, help="solve the batch in FP64 too")
+    ap.add_argument("--n512", type=int, default=1, help="single-lane pass timing at 256^3 -> 512^3")
     ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the single-lane kernel-timing section (for profiler runs)")
+                    help="only the single-lane kernel-timing sections (for profiler runs)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 1 GiB device copy used to calibrate traffic counters")
     args = ap.parse_args()
@@ -365,7 +581,7 @@ def main():
     torch.cuda.set_device(0)
     copy = copy_bandwidth(torch)
     if args.copy_only:
-        print(json.dumps({"copy": copy}))
+        print(json.dumps({"copy": copy, "copy_sweep": copy_sweep(torch)}))
         return
     n = args.n
     ctx = fr3d.Context(0)
@@ -374,76 +590,70 @@ def main():
     ctx.set_lanes(args.lanes)
     ctx.set_graphs(bool(args.graphs))
     modes = args.modes.split(",")
-    if "learned" in modes:
+    net_base = net_tuned = None
+    if any(m.startswith("learned") for m in modes):
         if not os.path.exists(args.predictor):
             print(f"[bench] no predictor at {args.predictor}; skipping the learned searches", file=sys.stderr)
             modes = [m for m in modes if not m.startswith("learned")]
         else:
             ctx.predictor_load(args.predictor)
+            net_base = ctx.predictor_get()
     Fs, deltas, V0 = make_instances(ctx, torch, n, args.batch)
     print(f"[bench] {len(Fs)} instances of {n}^3 ready", file=sys.stderr, flush=True)
     tight = dict(tol=1e-3, accept_lo=1 - 1e-3, accept_hi=1 + 1e-3)
     wide = dict(tol=0.1, accept_lo=0.9, accept_hi=1.1)
-    # the secant refinement after the seed assumes the median slope of ln r at
-    # the root measured on training instances (recorded beside the checkpoint)
-    # the learned searches: the network's seed calibrated for this geometry
-    # on instances of the same recipe that are not timed (indices from
-    # CAL_FIRST), then the secant refinement with the calibrated slope
-    sk, cal, cal_coef = {}, None, None
-    if any(m.startswith("learned") for m in modes) and args.calibrate:
+    # the network alone: the secant refinement assumes the median slope of
+    # ln r at the root over training instances (recorded beside the checkpoint)
+    meta = os.path.splitext(args.predictor)[0] + ".json"
+    train_slope = json.load(open(meta))["root_slope"]["median"] if os.path.exists(meta) else 0.05
+    # the headline learned search: the network fine-tuned on the GPU for this
+    # geometry on instances of the same recipe that are not timed (indices
+    # from CAL_FIRST), its median root slope and held-out seed spread
+    sk, cal = {"seed_slope": train_slope}, None
+    if net_base is not None and args.calibrate:
         from paper_1703_01216_amd import calibrate
-        t0c = time.perf_counter()
         Fc, dc, _ = make_instances(ctx, torch, n, args.calibrate, first=CAL_FIRST)
-        cal = calibrate.seed_calibration(ctx, Fc, dc)
-        cal_coef = cal.pop("coef")
-        cal["seconds"] = time.perf_counter() - t0c
+        cal = calibrate.fine_tune(ctx, Fc, dc)
         cal["first_index"] = CAL_FIRST
         del Fc
-        cal["seed_snap_lo"] = args.snap_sigmas * cal["shift_residual_decades"]
-        sk = {k: cal[k] for k in ("seed_slope", "seed_slope_x", "seed_snap_lo")}
-        print(f"[bench] seed calibration: {cal}", file=sys.stderr, flush=True)
+        net_tuned = ctx.predictor_get()
+        sk = {k: cal[k] for k in ("seed_slope", "seed_snap_lo")}
+        print(f"[bench] fine-tuning for the geometry: {cal}", file=sys.stderr, flush=True)
     mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
-                 "learned_walk": fr3d.default_opts(use_predictor=1, **tight),
+                 "learned_net": fr3d.default_opts(use_predictor=1, seed_slope=train_slope, **tight),
                  "bisection": fr3d.default_opts(**tight),
                  "learned_w": fr3d.default_opts(use_predictor=1, **sk, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
     for m in modes:
         if m.startswith("kary"):  # kary<K>: the K-candidate search
             mode_opts[m] = fr3d.default_opts(candidates=int(m[4:]), **tight)
-        if "@" in m:  # learned@<walk>: the learned search with another first walk step
-            base, w = m.split("@")
-            mode_opts[m] = fr3d.default_opts(use_predictor=1, seed_walk=float(w),
-                                             **(tight if base == "learned" else wide))
-    results = {}
+    results, kept = {}, {}
     head = modes[0]
     if not args.roofline_only:
         for m in modes:
             if m.startswith("learned"):
-                # learned_walk: the network's own seed (no calibration) with the walk
-                ctx.predictor_set_calibration(None if m == "learned_walk" else cal_coef)
-            r, _ = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup)
+                # learned_net: the shipped network alone (no fine-tuning)
+                net = net_base if (m == "learned_net" or net_tuned is None) else net_tuned
+                ctx.predictor_set(*net)
+            r, _, zs, reps = run_mode(ctx, torch, Fs, deltas, V0, mode_opts[m], args.steps, args.warmup)
             results[m] = r
+            if m == head:
+                kept = {"zs": zs, "reps": reps}
+            else:
+                del zs
             print(f"[bench] {m}: {r}", file=sys.stderr, flush=True)
     timing, kt_el = kernel_timing(ctx, torch, Fs, deltas, mode_opts["bisection"], args.lanes)
     print(f"[bench] kernel timing section: {kt_el * 1e3:.1f} ms", file=sys.stderr, flush=True)
     pb = pass_bytes(n)
-    passes = {}
-    for name, (ms, cnt) in timing.items():
-        if cnt:
-            avg = ms / cnt
-            passes[name] = {"avg_us": avg * 1e3, "launches": cnt, "GB_s": pb[name] / (avg * 1e-3) / 1e9,
-                            "total_ms": ms}
-    dom = max(passes, key=lambda k: passes[k]["total_ms"])
-    ach = passes[dom]["GB_s"]
-    traffic = None
-    if pass_source_digest() == MEASURED_TRAFFIC["digest"] and n == MEASURED_TRAFFIC["n"]:
-        traffic = MEASURED_TRAFFIC["bytes"].get(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": pb[dom], "avg_launch_us": passes[dom]["avg_us"],
-                "measured": "HIP events at kernel start/end, one lane, bisection to 1e-3 over the batch"}
+    passes = pass_table(timing, pb)
+    roofline = roofline_of(passes, pb, MEASURED_TRAFFIC, n)
+    roofline["measured"] = "HIP events at kernel start/end, one lane, bisection to 1e-3 over the batch"
+    s512 = None
+    if args.n512:
+        s512 = section_512(torch, fr3d)
+        print(f"[bench] 512^3 passes: {s512}", file=sys.stderr, flush=True)
     if args.roofline_only:
-        print(json.dumps({"roofline": roofline, "passes": passes}))
+        print(json.dumps({"roofline": roofline, "passes": passes, "roofline_512": s512}))
         return
     H = results[head]
     out = {
@@ -456,9 +666,11 @@ def main():
                    "grid": n, "padded": 2 * n, "batch": len(Fs), "lanes": args.lanes, "search": head,
                    "graphs": bool(args.graphs),
                    "tile_shifts": tuning,
-                   "modes": results, "seed_calibration": cal},
+                   "modes": results, "fine_tuning": cal, "train_root_slope": train_slope},
         "roofline": roofline,
+        "roofline_512": s512["roofline"] if s512 else None,
         "passes": passes,
+        "passes_512": s512["passes"] if s512 else None,
         "copy": copy,
     }
     per_solve = sum(pb[k] for k in ("fwd_x", "fwd_y", "fwd_z")) + 2 * n ** 3 * 4 * 2
@@ -467,12 +679,40 @@ def main():
     if "learned" in results and "bisection" in results:
         out["config"]["speedup_learned_vs_bisection_tol_1e-3"] = (
             results["learned"]["solves_per_s"] / results["bisection"]["solves_per_s"])
+    if "learned_net" in results and "bisection" in results:
+        out["config"]["speedup_network_alone_vs_bisection_tol_1e-3"] = (
+            results["learned_net"]["solves_per_s"] / results["bisection"]["solves_per_s"])
     if "learned_w" in results and "bisection_w" in results:
         out["config"]["speedup_learned_vs_bisection_tol_0.1"] = (
             results["learned_w"]["solves_per_s"] / results["bisection_w"]["solves_per_s"])
+    if cal is not None and "learned" in results:
+        # the fine-tuning is paid once per geometry: the learned solves it takes to repay
+        out["config"]["fine_tuning_in_learned_solves"] = cal["seconds"] * results["learned"]["solves_per_s"]
+    z64 = rep64 = None
+    if args.fp64 and "learned" in results and "bisection" in results:
+        net = net_tuned or net_base
+        out["config"]["fp64"], z64, rep64 = fp64_section(torch, fr3d, Fs, deltas, net, mode_opts["learned"],
+                                                         mode_opts["bisection"], args.lanes)
+        print(f"[bench] fp64: {out['config']['fp64']}", file=sys.stderr, flush=True)
     if args.exact:
         out["config"]["exact_cg"] = exact_section(torch, fr3d, Fs, n)
         print(f"[bench] exact: {out['config']['exact_cg']}", file=sys.stderr, flush=True)
+    # host copies for the oracle legs (first instances of the timed batch)
+    n_cpu = min(len(Fs), max(4, args.cpu_workers))
+    Fh = [F.double().cpu().numpy() for F in Fs[:n_cpu]]
+    checks = []
+    if kept:
+        for i in range(min(4, len(Fs))):
+            r = kept["reps"][i]
+            checks.append({"kind": "check", "precision": 32, "index": i, "F": Fh[i], "delta": deltas[i],
+                           "alpha": r["alpha"], "zeta": kept["zs"][i].double().cpu().numpy(),
+                           "residual": r["residual"]})
+            if z64 is not None:
+                checks.append({"kind": "check", "precision": 64, "index": i, "F": Fh[i], "delta": deltas[i],
+                               "alpha": rep64[i]["alpha"], "zeta": z64[i].cpu().numpy(),
+                               "residual": rep64[i]["residual"]})
+    kept = None
+    del z64
     if args.w3 > 0:
         del Fs, V0
         torch.cuda.empty_cache()
@@ -482,7 +722,13 @@ def main():
         out["config"]["layered"] = layered_section(torch, fr3d)
         print(f"[bench] layered: {out['config']['layered']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, H["mean_evals"])
+        net = net_tuned or net_base
+        net_arg = (net[0].astype("float64"), net[1].astype("float64"), sk) if net is not None else None
+        cb = cpu_baseline(Fh, deltas[:n_cpu], net_arg, checks, workers=args.cpu_workers)
+        res = cb.pop("precision_checks")
+        out["precision"] = [dict(precision=c["precision"], index=c["index"], alpha=c["alpha"], **r)
+                            for c, r in zip(checks, res)]
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

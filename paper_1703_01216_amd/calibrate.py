@@ -1,92 +1,105 @@
-"""Calibration of the learned seed for one geometry.
+"""Fine-tuning of the alpha predictor for one geometry, on the GPU.
 
     from paper_1703_01216_amd import calibrate
-    cal = calibrate.seed_calibration(ctx, Fs, deltas)
-    ctx.predictor_set_calibration(cal["coef"])
-    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_slope_x=cal["seed_slope_x"],
-                             seed_snap_lo=cal["seed_snap_lo"])
+    cal = calibrate.fine_tune(ctx, Fs, deltas)      # ctx holds the trained network
+    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_snap_lo=cal["seed_snap_lo"])
 
-The predictor is trained on a mix of grids, source sets and heights of Y; on
-one fixed geometry its seeds carry an error that depends on the data's
-spectrum, and the secant refinement of the seeded search wants the slope of
-ln r at the root.  Given calibration instances of that geometry (other
-draws than the ones to be solved), this fits
+The predictor is trained on a mix of grids, source sets and heights of Y
+(the training workload); on one fixed geometry its seeds carry an error that
+depends on the data's spectrum.  Given instances of that geometry (other
+draws than the ones to be solved), this continues the network's training on
+them with the library's own kernels (BF16 matrix-core forward and backward,
+Adam), so the seed becomes the network's, with no other model beside it:
 
-    t* - t_net  ~  c_0 + sum_k c_k x_k          (ridge regression, lambda = 1 on
-                                                 standardised features),
-    log10 s*    ~  log10 slope + slope_x x_64    (least squares),
+* labels: each instance's root t* = log10 alpha with |r/delta - 1| <=
+  label_tol, found by the library's learned search from the network's seed
+  (instances without a root in the range are labelled at the range end, as
+  in training);
+* the network is fine-tuned on the first part of the instances (full batch,
+  `steps` Adam steps at learning rate `lr`, fresh moments);
+* the rest are held out: the standard deviation of the fine-tuned seed's
+  error on them sets seed_snap_lo = SNAP_SIGMAS sigma (a seed closer than that
+  to the lower end of the range starts the search at that end, where an
+  instance whose root lies below the range ends after one evaluation);
+* seed_slope, the slope of ln r per decade of alpha that the first secant
+  step assumes, is the median over the instances of the one-sided
+  difference (ln r(t* + h) - ln delta)/h at the root.
 
-with t* = log10 alpha of the plain rule to |r/delta - 1| <= 1e-6, s* the
-slope d ln r / d log10 alpha at t* (central difference over +-h decades),
-t_net the network's output and x the 65 raw features (x_64 = log10(delta/
-||F||)); instances without a root in the range are skipped.  coef holds
-c_0 and the c_k for the raw features (the library's
-fr3d_predictor_set_calibration).  seed_snap_lo = SNAP_SIGMAS times the
-standard deviation of the shift's residual: a calibrated seed closer than
-that to the lower end of the range is about as likely to have its root
-below the range (the network was trained with such instances labelled at
-the range end), so the search starts at the end, where such an instance
-ends after one evaluation.  Everything runs through the library's calls.
+Everything runs through the library's calls; the host only forms medians
+and standard deviations of the values they return.
 """
 from __future__ import annotations
 
 import math
+import time
 
-RIDGE = 1.0
 SNAP_SIGMAS = 2.0
 
 
-def seed_calibration(ctx, Fs, deltas, h=0.05, lo=-8.0, hi=0.0):
+def split(m, hold):
+    """Indices of the fitted and held-out instances: the last round(hold m)
+    (at least one) are held out."""
+    k = max(1, min(m - 1, int(round(hold * m))))
+    return list(range(m - k)), list(range(m - k, m))
+
+
+def median(v):
+    v = sorted(v)
+    if not v:
+        raise ValueError("median of nothing")
+    k = len(v) // 2
+    return v[k] if len(v) % 2 else 0.5 * (v[k - 1] + v[k])
+
+
+def std(v):
+    mu = sum(v) / len(v)
+    return math.sqrt(sum((x - mu) ** 2 for x in v) / len(v))
+
+
+def fine_tune(ctx, Fs, deltas, lr=1e-3, steps=100, hold=0.25, h=0.05, label_tol=1e-5, lo=-8.0, hi=0.0,
+              start_slope=0.05):
     import numpy as np
     import torch
 
-    X, dt, ls = [], [], []
-    z = torch.empty_like(Fs[0])
-    y = torch.empty(1, dtype=torch.float32, device=Fs[0].device)
+    t_start = time.perf_counter()
+    m = len(Fs)
+    fit_idx, held_idx = split(m, hold)
+    zs = [torch.empty_like(F) for F in Fs]
+    feat = torch.empty((m, 65), dtype=torch.float32, device=Fs[0].device)
     ctx.predictor_set_calibration(None)
-    for F, d in zip(Fs, deltas):
-        ctx.set_data(F, d)
-        feat, _ = ctx.get_features()
-        ctx.predictor_forward(feat.view(1, 65).contiguous(), y)
-        t_net = float(y[0])
-        rep = ctx.solve_discrepancy(z, tol=1e-6, max_steps=60, log10_alpha_lo=lo, log10_alpha_hi=hi)
-        if rep["flags"] != 0:
+    reps = ctx.solve_batch(Fs, deltas, zs, feat=feat, use_predictor=1, tol=label_tol, accept_lo=1 - label_tol,
+                           accept_hi=1 + label_tol, seed_slope=start_slope, max_steps=60,
+                           log10_alpha_lo=lo, log10_alpha_hi=hi)
+    t = [min(max(math.log10(r["alpha"]), lo), hi) for r in reps]
+    root = [(r["flags"] & 7) == 0 for r in reps]
+    label_evals = sum(r["n_evals"] for r in reps)
+    # slope of ln r at the root, one-sided over h decades
+    slopes = []
+    z = zs[0]
+    for i in range(m):
+        if not root[i] or t[i] + h > hi:
             continue
-        t = math.log10(rep["alpha"])
-        rp = ctx.solve_alpha(10.0 ** (t + h), z)["residual"]
-        rm = ctx.solve_alpha(10.0 ** (t - h), z)["residual"]
-        s = (math.log(rp) - math.log(rm)) / (2 * h)
+        ctx.set_data(Fs[i], deltas[i])
+        r = ctx.solve_alpha(10.0 ** (t[i] + h), z)["residual"]
+        s = (math.log(r) - math.log(deltas[i])) / h
         if s > 0:
-            X.append(feat.double().cpu().numpy())
-            dt.append(t - t_net)
-            ls.append(math.log10(s))
-    if len(X) < 3:
-        raise RuntimeError("too few calibration instances with a root in the range")
-    return fit(np.array(X), np.array(dt), np.array(ls))
-
-
-def fit(X, dt, ls, ridge=RIDGE):
-    """The least-squares fits on calibration rows: X [m][65] raw features,
-    dt = t* - t_net, ls = log10 s*.  Returns the raw-feature coefficients of
-    the seed shift (ridge on standardised features; constant features get
-    no weight) and the power law of the slope in x_64."""
-    import numpy as np
-
-    X, dt, ls = np.asarray(X, dtype=np.float64), np.asarray(dt, dtype=np.float64), np.asarray(ls, dtype=np.float64)
-    mu, sd = X.mean(0), X.std(0)
-    live = sd > 1e-9
-    Z = np.zeros_like(X)
-    Z[:, live] = (X[:, live] - mu[live]) / sd[live]
-    A = np.c_[np.ones(len(X)), Z]
-    reg = ridge * np.eye(A.shape[1])
-    reg[0, 0] = 0.0
-    w = np.linalg.solve(A.T @ A + reg, A.T @ dt)
-    coef = np.zeros(X.shape[1] + 1)
-    coef[1:][live] = w[1:][live] / sd[live]
-    coef[0] = w[0] - float(np.sum(coef[1:][live] * mu[live]))
-    B = np.c_[np.ones(len(X)), X[:, 64]]
-    sl = np.linalg.lstsq(B, ls, rcond=None)[0]
-    res = float(np.std(dt - A @ w))
-    return dict(coef=coef.tolist(), seed_slope=float(10.0 ** sl[0]), seed_slope_x=float(sl[1]),
-                seed_snap_lo=SNAP_SIGMAS * res, instances=len(X), shift_residual_decades=res,
-                slope_residual_log10=float(np.std(ls - B @ sl)))
+            slopes.append(s)
+    # fine-tune on the fitted part (fresh Adam moments)
+    params, norm = ctx.predictor_get()
+    ctx.predictor_set(params, norm)
+    X = feat[fit_idx].contiguous()
+    tt = torch.tensor(np.array([t[i] for i in fit_idx], dtype=np.float32), device=feat.device)
+    for _ in range(steps):
+        ctx.predictor_train_step(X, tt, lr)
+    # held-out error of the fine-tuned seed
+    y = torch.empty(len(held_idx), dtype=torch.float32, device=feat.device)
+    ctx.predictor_forward(feat[held_idx].contiguous(), y)
+    yh = y.cpu().numpy().astype(np.float64)
+    err = [min(max(float(yh[k]), lo), hi) - t[i] for k, i in enumerate(held_idx) if root[i]]
+    sigma = std(err) if len(err) >= 2 else 0.0
+    torch.cuda.synchronize()
+    return dict(seed_slope=median(slopes), seed_snap_lo=SNAP_SIGMAS * sigma, instances=m, fitted=len(fit_idx),
+                held_out=len(held_idx), held_out_err_std_decades=sigma,
+                held_out_err_mean_decades=(sum(err) / len(err)) if err else 0.0,
+                slope_instances=len(slopes), label_evals=label_evals, lr=lr, steps=steps,
+                seconds=time.perf_counter() - t_start)

@@ -78,8 +78,7 @@ __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, 
 // below 2^53, so the FP64 sum is exact).
 __global__ void k_clamp_count(const double* __restrict__ part, int nblk, int64_t* out) {
   __shared__ double red[NT / 64];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += NT) s += part[k];
+  double s = strided_sum<double>(part, threadIdx.x, nblk, NT);
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) *out = (int64_t)s;
 }
@@ -88,8 +87,7 @@ __global__ void k_clamp_count(const double* __restrict__ part, int nblk, int64_t
 __global__ void k_sum_parts(const double* __restrict__ part, int nblk, int stride, int nout, double* out) {
   __shared__ double red[NT / 64];
   for (int j = 0; j < nout; ++j) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += NT) s += part[(size_t)k * stride + j];
+    double s = strided_sum<double>(part + j, threadIdx.x, nblk, NT, stride);
     s = block_sum<NT>(s, red);
     if (threadIdx.x == 0) out[j] = s;
   }
@@ -270,8 +268,7 @@ __global__ void k_full_part(const c2<T>* __restrict__ S, InvArgs a) {
 __global__ void k_full_final(InvArgs a, int nblk) {
   __shared__ double red[NT / 64];
   if (inv_idle(a)) return;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += NT) s += a.full_part[k];
+  double s = strided_sum<double>(a.full_part, threadIdx.x, nblk, NT);
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) a.ctrl->r2_full = s * a.scale;
 }

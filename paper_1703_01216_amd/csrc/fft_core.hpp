@@ -216,6 +216,29 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum of p[k es] over k = i0, i0 + st, i0 + 2 st, ... below n, in that order,
+// with the loads of U terms issued before any of them is added: the same
+// sum as the plain loop, one memory round trip per U terms instead of per
+// term (the fixed-order reductions of per-workgroup partials).
+__device__ __forceinline__ void acc(double& s, double v) { s += v; }
+__device__ __forceinline__ void acc(double2& s, double2 v) { s.x += v.x; s.y += v.y; }
+template <typename V, int U = 8>
+__device__ __forceinline__ V strided_sum(const V* __restrict__ p, int i0, int n, int st, long long es = 1) {
+  V s{};
+  for (int b = i0; b < n; b += U * st) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = b + u * st;
+      if (k < n) v[u] = p[(long long)k * es];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b + u * st < n) acc(s, v[u]);
+  }
+  return s;
+}
+
 // Sum over the block (NT threads, NT/64 waves), result valid in thread 0.
 template <int NT> __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum<double>(v);

@@ -669,14 +669,9 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
 static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
   __shared__ double red[NT / 64];
   if (inv_idle(a)) return;
-  double pr = 0.0, pz = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += NT) {
-    const double2 v = a.norm_part[k];
-    pr += v.x;
-    pz += v.y;
-  }
-  const double tr = block_sum<NT>(pr, red);
-  const double tz = block_sum<NT>(pz, red);
+  const double2 p = strided_sum<double2>(a.norm_part, threadIdx.x, nblk, NT);
+  const double tr = block_sum<NT>(p.x, red);
+  const double tz = block_sum<NT>(p.y, red);
   if (threadIdx.x == 0) ctrl_advance(a.ctrl, tr, tz);
 }
 
@@ -689,15 +684,9 @@ static __global__ __launch_bounds__(NT) void k_norm_final_k(InvArgs a, int nblk)
   const int kc = a.ctrl->kc;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   for (int j = w; j < kc; j += NT / 64) {
-    const double2* part = a.norm_part + (size_t)j * a.norm_stride;
-    double pr = 0.0, pz = 0.0;
-    for (int k = lane; k < nblk; k += 64) {
-      const double2 v = part[k];
-      pr += v.x;
-      pz += v.y;
-    }
-    pr = wave_sum<double>(pr);
-    pz = wave_sum<double>(pz);
+    const double2 p = strided_sum<double2>(a.norm_part + (size_t)j * a.norm_stride, lane, nblk, 64);
+    const double pr = wave_sum<double>(p.x);
+    const double pz = wave_sum<double>(p.y);
     if (lane == 0) { r2[j] = pr; z2[j] = pz; }
   }
   __syncthreads();
@@ -713,8 +702,7 @@ static __global__ __launch_bounds__(NT) void k_bins_final(FwdArgs a, int nblk) {
   __shared__ int last;
   const int b = blockIdx.x;
   const double* row = a.bins_part + (size_t)b * nblk;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += NT) s += row[k];
+  double s = strided_sum<double>(row, threadIdx.x, nblk, NT);
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) {
     a.bins_out[b] = s;
