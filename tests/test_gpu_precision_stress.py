@@ -25,7 +25,8 @@ def fr3d():
     return m
 
 
-def test_workload4_fp32_fp64_oracle(fr3d):
+@pytest.fixture(scope="module")
+def w4():
     from paper_1703_01216_amd import inputs
     t0 = time.time()
     inst = inputs.workload_instance(4, 0)
@@ -33,6 +34,12 @@ def test_workload4_fp32_fp64_oracle(fr3d):
     d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"])
     khat = np.fft.fftn(sample_kernel(g))
     print(f"oracle synthesis {time.time() - t0:.1f}s", flush=True)
+    return g, d, khat
+
+
+def test_workload4_fp32_fp64_oracle(fr3d, w4):
+    t0 = time.time()
+    g, d, khat = w4
     out = {}
     for prec in (64, 32):
         c = fr3d.Context()
@@ -68,3 +75,35 @@ def test_workload4_fp32_fp64_oracle(fr3d):
         assert d32 <= 1e-3 + 1e-5
     else:
         assert rep32["alpha"] == rep64["alpha"]
+
+
+def test_workload4_search_with_wider_range(fr3d, w4):
+    # with delta = 0.5% the root lies below the configured range (the test
+    # above ends at its lower end); over log10 alpha in [-14, 0] both
+    # precisions bisect to a root: the oracle's residual at each device alpha
+    # meets the rule, FP64 and FP32 agree with the oracle there, and the two
+    # alphas are close (the FP32 rounding moves the residual by ~1e-6)
+    g, d, khat = w4
+    res = {}
+    for prec in (64, 32):
+        print(f"[workload4-wide] precision {prec}", flush=True)
+        c = fr3d.Context()
+        c.load_kernel(256, 256, 256, precision=prec)
+        dt = torch.float64 if prec == 64 else torch.float32
+        F = torch.tensor(d["F"], dtype=dt, device="cuda")
+        c.set_data(F, d["delta"])
+        z = torch.empty_like(F)
+        rep = c.solve_discrepancy(z, log10_alpha_lo=-14.0)
+        res[prec] = (rep, z.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64))
+        c.close()
+        del F, z
+        torch.cuda.empty_cache()
+    for prec, (rep, z, Fh) in res.items():
+        o = tikhonov.solve_spectral(g, khat, Fh, rep["alpha"])
+        e = rel_l2(z, o["zeta"])
+        print(f"[workload4-wide] fp{prec}: alpha={rep['alpha']:.6e} flags={rep['flags']} evals={rep['n_evals']} "
+              f"oracle r/delta={o['r_norm'] / d['delta']:.6f} rel_l2={e:.2e}", flush=True)
+        assert rep["flags"] == 0 and rep["n_evals"] > 3
+        assert abs(o["r_norm"] / d["delta"] - 1) <= 1e-3 + (1e-12 if prec == 64 else 1e-5)
+        assert e < (1e-10 if prec == 64 else 1e-5)
+    assert abs(np.log10(res[32][0]["alpha"] / res[64][0]["alpha"])) < 0.05
