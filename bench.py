@@ -69,21 +69,24 @@ def pass_source_digest():
     return hashlib.sha256(src).hexdigest()[:16]
 
 
-def pass_bytes(n, esz=4):
-    """Algorithmic bytes of each pass for a cubic n^3 grid padded to P = 2n:
-    reads of the nonzero inputs plus writes of the kept outputs (complex =
-    2 esz; the kernel-spectrum octant is FP64 complex)."""
-    P = 2 * n
-    kx = P // 2 + 1
+def pass_bytes(n, esz=4, shape=None):
+    """Algorithmic bytes of each pass for an n^3 grid (or shape = (nz, ny, nx))
+    padded to P = 2n per axis: reads of the nonzero inputs plus writes of the
+    kept outputs (complex = 2 esz; the kernel-spectrum octant is FP64
+    complex)."""
+    nz, ny, nx = shape or (n, n, n)
+    Pz, Py = 2 * nz, 2 * ny
+    kx = nx + 1
     c = 2 * esz
-    octant = kx * (P // 2 + 1) * (P // 2 + 1) * 16
+    cells = nx * ny * nz
+    octant = kx * (Pz // 2 + 1) * (Py // 2 + 1) * 16
     return {
-        "fwd_x": n ** 3 * esz + kx * n * n * c,
-        "fwd_y": kx * n * n * c + kx * n * P * c,
-        "fwd_z": kx * n * P * c + kx * P * P * c,
-        "inv_z": kx * P * P * c + octant + kx * n * P * 2 * c,
-        "inv_y": kx * n * P * 2 * c + kx * n * n * 2 * c,
-        "inv_x": kx * n * n * 2 * c + n ** 3 * esz,
+        "fwd_x": cells * esz + kx * nz * ny * c,
+        "fwd_y": kx * nz * ny * c + kx * nz * Py * c,
+        "fwd_z": kx * nz * Py * c + kx * Pz * Py * c,
+        "inv_z": kx * Pz * Py * c + octant + kx * nz * Py * 2 * c,
+        "inv_y": kx * nz * Py * 2 * c + kx * nz * ny * 2 * c,
+        "inv_x": kx * nz * ny * 2 * c + cells * esz,
     }
 
 
@@ -216,14 +219,18 @@ def _cpu_pool(out, ctx, workers, Fh, deltas, net, checks):
     return out
 
 
-def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, modes=("kary16", "bisection")):
+def workload3_section(torch, fr3d, n_inst=64, steps=2, warmup=1, graphs=(False, True), modes=("kary16", "bisection")):
     """Batched solves of the uneven-size workload: n_inst instances (each axis
     from {64, 96, 128, 192}), each under the four source sets q (one context
-    and stream per (shape, q)), all scheduled together by the group solver;
-    K-candidate search (16 alphas per step) and bisection, both to 1e-3."""
+    and stream per (instance, q)), all scheduled together by the group solver
+    (the 16-candidate search borrows its workspaces from a pool of a few
+    slots); the 16-candidate search and bisection, both to 1e-3, with and
+    without the lanes' evaluations replayed as HIP graphs.  Then the latency of
+    one solve alone (one context, one lane) with each search, per grid size."""
     from paper_1703_01216_amd import inputs
     tight = dict(tol=1e-3, accept_lo=1 - 1e-3, accept_hi=1 + 1e-3)
     ctxs, Fs, deltas, shapes = [], [], [], []
+    t0 = time.perf_counter()
     for i in range(n_inst):
         r = inputs.workload_params(3, i)
         shape = r["shape"]
@@ -234,7 +241,6 @@ def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, mo
                 c = fr3d.Context(0, stream=st)
                 c.load_kernel(nx, ny, nz, q=q, precision=32)
                 c.apply_tuning()
-                c.set_graphs(graphs)
                 V = torch.empty(shape, dtype=torch.float32, device="cuda")
                 c.source_potential(V)
                 xi = inputs.xi_torch(shape, r["inclusions"])
@@ -246,22 +252,90 @@ def workload3_section(torch, fr3d, n_inst=8, steps=2, warmup=1, graphs=False, mo
             Fs.append(F)
             shapes.append(shape)
     torch.cuda.synchronize()
-    out = {"instances": n_inst, "items": len(Fs), "shapes": sorted(set(shapes)), "graphs": graphs}
+    cells = sum(s[0] * s[1] * s[2] for s in shapes)
+    out = {"instances": n_inst, "items": len(Fs), "distinct_shapes": len(set(shapes)),
+           "setup_s": time.perf_counter() - t0, "cells_per_item_mean": cells / len(Fs)}
+    zs = [torch.empty_like(F) for F in Fs]
     for m in modes:
         o = fr3d.default_opts(candidates=int(m[4:]), **tight) if m.startswith("kary") else fr3d.default_opts(**tight)
-        zs = [torch.empty_like(F) for F in Fs]
-        for _ in range(warmup):
-            fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        evals = []
-        for _ in range(steps):
-            reps = fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
-            evals += [r["n_evals"] for r in reps]
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[m] = {"solves_per_s": len(Fs) * steps / el, "mean_evals": sum(evals) / len(evals),
-                  "alpha_evals_per_s": sum(evals) / el}
+        for gr in graphs:
+            for c in ctxs:
+                c.set_graphs(gr)
+            for _ in range(warmup):
+                fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            evals = []
+            for _ in range(steps):
+                reps = fr3d.solve_group(ctxs, Fs, deltas, zs, opts=o)
+                evals += [r["n_evals"] for r in reps]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row = {"solves_per_s": len(Fs) * steps / el, "mean_evals": sum(evals) / len(evals),
+                   "alpha_evals_per_s": sum(evals) / el, "ms_per_step": el / steps * 1e3}
+            if not m.startswith("kary"):
+                # algorithmic bytes of the forward transform, the evaluations and
+                # the recovery of every item over the time
+                tot = 0
+                for k, shp in enumerate(shapes):
+                    pb = pass_bytes(0, shape=shp)
+                    tot += sum(pb[p] for p in ("fwd_x", "fwd_y", "fwd_z"))
+                    tot += evals[k] * sum(pb[p] for p in ("inv_z", "inv_y", "inv_x"))
+                row["aggregate_GB_s"] = tot * steps / el / 1e9
+            out[f"{m}{'_graphs' if gr else ''}"] = row
+    for c in ctxs:
+        c.set_graphs(False)
+    # latency of a single solve, per grid size (the first item of each cubic-ish size)
+    lat = {}
+    for n in (64, 128, 192):
+        k = next((i for i, s in enumerate(shapes) if max(s) == n and min(s) == n), None)
+        if k is None:
+            k = next((i for i, s in enumerate(shapes) if max(s) == n), None)
+        if k is None:
+            continue
+        row = {"shape": list(shapes[k])}
+        c = ctxs[k]
+        for m in modes:
+            o = fr3d.default_opts(candidates=int(m[4:]), **tight) if m.startswith("kary") else fr3d.default_opts(**tight)
+            c.set_data(Fs[k], deltas[k])
+            c.solve_discrepancy(zs[k], opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                c.set_data(Fs[k], deltas[k])
+                rep = c.solve_discrepancy(zs[k], opts=o)
+            torch.cuda.synchronize()
+            row[m] = {"ms": (time.perf_counter() - t0) / 5 * 1e3, "n_evals": rep["n_evals"]}
+        lat[f"max_axis_{n}"] = row
+    # small cubic grids, where an evaluation cannot fill the GPU
+    for n in (32, 64):
+        shape = (n, n, n)
+        c = fr3d.Context(0)
+        c.load_kernel(n, n, n, q=0, precision=32)
+        c.apply_tuning()
+        V = torch.empty(shape, dtype=torch.float32, device="cuda")
+        c.source_potential(V)
+        r = inputs.workload_params(3, 0)
+        xi = inputs.xi_torch(shape, inputs.inclusion_params(shape, r["seed"]))
+        F = torch.empty_like(xi)
+        c.apply_operator(xi * V, F)
+        dl = c.add_noise(F, inputs.noise_torch(shape, r["seed"]), 0.02)
+        z = torch.empty_like(F)
+        row = {"shape": list(shape)}
+        for m in modes:
+            o = fr3d.default_opts(candidates=int(m[4:]), **tight) if m.startswith("kary") else fr3d.default_opts(**tight)
+            c.set_data(F, dl)
+            c.solve_discrepancy(z, opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                c.set_data(F, dl)
+                rep = c.solve_discrepancy(z, opts=o)
+            torch.cuda.synchronize()
+            row[m] = {"ms": (time.perf_counter() - t0) / 10 * 1e3, "n_evals": rep["n_evals"]}
+        lat[f"cube_{n}"] = row
+        c.close()
+    out["single_solve_latency"] = lat
     for c in ctxs:
         c.close()
     return out
@@ -561,7 +635,7 @@ def main():
                     help="instances (not timed) on which the network is fine-tuned for this geometry; 0: none")
     ap.add_argument("--fp64", type=int, default=1, help="solve the batch in FP64 too")
     ap.add_argument("--n512", type=int, default=1, help="single-lane pass timing at 256^3 -> 512^3")
-    ap.add_argument("--w3", type=int, default=8, help="instances of the uneven-size batched workload (0: skip)")
+    ap.add_argument("--w3", type=int, default=64, help="instances of the uneven-size batched workload (0: skip)")
     ap.add_argument("--layered", type=int, default=1, help="time the per-frequency z-system form at the paper's size")
     ap.add_argument("--exact", type=int, default=1, help="time the exact-operator CG solve on one instance")
     ap.add_argument("--roofline-only", action="store_true",
@@ -716,7 +790,7 @@ def main():
     if args.w3 > 0:
         del Fs, V0
         torch.cuda.empty_cache()
-        out["config"]["workload3"] = workload3_section(torch, fr3d, n_inst=args.w3, graphs=bool(args.graphs))
+        out["config"]["workload3"] = workload3_section(torch, fr3d, n_inst=args.w3)
         print(f"[bench] workload3: {out['config']['workload3']}", file=sys.stderr, flush=True)
     if args.layered:
         out["config"]["layered"] = layered_section(torch, fr3d)

@@ -307,6 +307,12 @@ struct Lane {
   double2* knorm = nullptr;     // K-candidate norm partials
   int kcap = 0;                 // candidates the K-candidate workspaces hold
   int kmax = 0;                 // K of the lane's current search (0: not a K-candidate search)
+  // while a group solve lends the lane a pooled K-candidate workspace, its own
+  // (if any) is kept here
+  bool kpooled = false;
+  void* own_kwork = nullptr;
+  double2* own_knorm = nullptr;
+  int own_kcap = 0;
   hipGraphExec_t gexec = nullptr;  // captured evaluation (valid for gkmax and gsh)
   int gkmax = -1;
   int gsh[6] = {0, 0, 0, 0, 0, 0};
@@ -359,6 +365,13 @@ struct fr3d_ctx {
   double* cg_host = nullptr;  // pinned
   double* pf_part = nullptr;  // per-system partials of the per-frequency alpha search
   size_t pf_cap = 0;
+  // K-candidate workspaces a group solve with this context first lends to the
+  // lanes of all its contexts (fr3d_solve_group): a few slots, each sized for
+  // the largest geometry of the group, so the memory does not grow with the
+  // number of contexts
+  std::vector<void*> pool_kw;
+  std::vector<double2*> pool_kn;
+  size_t pool_kw_bytes = 0, pool_kn_bytes = 0;
   bool graphs = false;              // replay each lane's evaluation as a captured HIP graph
   bool diag = false;                // form the full-box residual of every single evaluation
   hipStream_t cap_stream = nullptr; // stream the graphs are captured on
@@ -409,8 +422,15 @@ void free_lane_geometry(Lane& L) {
   dfree(L.work);
   dfree(L.bins_part);
   dfree(L.norm_part);
+  if (L.kpooled) {  // a lent workspace belongs to the pool
+    L.kwork = L.own_kwork;
+    L.knorm = L.own_knorm;
+    L.kpooled = false;
+  }
   dfree(L.kwork);
   dfree(L.knorm);
+  L.own_kwork = nullptr;
+  L.own_knorm = nullptr;
   L.kcap = 0;
   L.kmax = 0;
   if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
@@ -784,6 +804,7 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
 
 fr3d_status ensure_kwork(fr3d_ctx* c, Lane& L, int K) {
   if (L.kcap >= K) return FR3D_OK;
+  if (L.kpooled) return fail(c, FR3D_E_STATE, "lent K-candidate workspace holds fewer than %d candidates", K);
   dfree(L.kwork);
   dfree(L.knorm);
   L.kcap = 0;
@@ -823,6 +844,10 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
     v.state = ST_KARY;
     v.kmax = d.candidates;
     v.steps = 0;
+    const size_t nB = (size_t)c->kxn * c->g.nz * c->py;
+    v.kw1 = L.kwork;
+    v.kw2 = (char*)L.kwork + (size_t)d.candidates * nB * 4 * c->esz;
+    v.knorm = L.knorm;
   }
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, L.stream, L.ctrl, v);
   LCHK(c, hipGetLastError());
@@ -1059,6 +1084,8 @@ fr3d_status fr3d_destroy(fr3d_ctx* c) {
   }
   for (auto& e : c->ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (auto& p : c->pool_kw) dfree(p);
+  for (auto& p : c->pool_kn) dfree(p);
   dfree(c->cg_buf);
   dfree(c->pf_part);
   dfree(c->cg_part);
@@ -1385,10 +1412,37 @@ struct Items {
   fr3d_report* reps;
 };
 
-fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_dp_opts& d) {
+// Pooled K-candidate workspaces of a group solve: an item starts only when a
+// slot is free and holds it until its lane is idle again.
+struct KLend {
+  fr3d_ctx* owner;
+  int K;
+  std::vector<int> free_slots;
+};
+
+void lend(KLend* kl, Lane& L, int slot) {
+  L.own_kwork = L.kwork;
+  L.own_knorm = L.knorm;
+  L.own_kcap = L.kcap;
+  L.kwork = kl->owner->pool_kw[slot];
+  L.knorm = kl->owner->pool_kn[slot];
+  L.kcap = kl->K;
+  L.kpooled = true;
+}
+
+void give_back(Lane& L) {
+  L.kwork = L.own_kwork;
+  L.knorm = L.own_knorm;
+  L.kcap = L.own_kcap;
+  L.own_kwork = nullptr;
+  L.own_knorm = nullptr;
+  L.kpooled = false;
+}
+
+fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_dp_opts& d, KLend* kl = nullptr) {
   const int ns = (int)slots.size();
   enum { IDLE, SEARCH, RECOVER };
-  std::vector<int> item(ns, -1), state(ns, IDLE), launched(ns, 0), limit(ns, 0);
+  std::vector<int> item(ns, -1), state(ns, IDLE), launched(ns, 0), limit(ns, 0), held(ns, -1);
   std::vector<char> started(it.n, 0);
   int done = 0, scan = 0;
   fr3d_status s = FR3D_OK;
@@ -1404,6 +1458,12 @@ fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_d
         for (int k = scan; k < it.n; ++k)
           if (!started[k] && ctx_of(k) == c) { i = k; break; }
         if (i < 0) continue;
+        if (kl) {  // the item needs a pooled workspace
+          if (kl->free_slots.empty()) continue;
+          held[l] = kl->free_slots.back();
+          kl->free_slots.pop_back();
+          lend(kl, L, held[l]);
+        }
         started[i] = 1;
         while (scan < it.n && started[scan]) ++scan;
         item[l] = i;
@@ -1448,10 +1508,24 @@ fr3d_status run_schedule(std::vector<Slot>& slots, const Items& it, const fr3d_d
         it.reps[i].n_clamped = (int64_t)L.scal_host[0];
       }
       state[l] = IDLE;
+      if (held[l] >= 0) {
+        give_back(L);
+        kl->free_slots.push_back(held[l]);
+        held[l] = -1;
+      }
       done += 1;
     }
     if (!progressed && s == FR3D_OK) std::this_thread::yield();
   }
+  if (kl)  // after an error: lanes still holding a slot wait for their work, then return it
+    for (int l = 0; l < ns; ++l)
+      if (held[l] >= 0) {
+        Lane& L = slots[l].c->lanes[slots[l].lane];
+        (void)hipStreamSynchronize(L.stream);
+        give_back(L);
+        kl->free_slots.push_back(held[l]);
+        held[l] = -1;
+      }
   if (s != FR3D_OK && bad && it.ctx0 && bad != it.ctx0) it.ctx0->err = bad->err;
   return s;
 }
@@ -1545,7 +1619,37 @@ fr3d_status fr3d_solve_group(int32_t n, fr3d_ctx* const* ctxs, const void* const
     for (int l = 0; l < nl; ++l) slots.push_back({c, l});
   }
   Items it{n, ctxs, c0x, F, deltas, zetas, V0s, c0, c_out, nullptr, reps};
-  s = run_schedule(slots, it, d);
+  KLend kl{c0x, d.candidates, {}};
+  if (d.candidates) {
+    // pooled K-candidate workspaces (slots on ctxs[0], reused by later calls)
+    size_t kwb = 0, knb = 0;
+    for (fr3d_ctx* c : distinct) {
+      const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny, nB = (size_t)c->kxn * c->g.nz * c->py;
+      kwb = std::max(kwb, (size_t)d.candidates * (nA + nB) * 4 * c->esz);
+      knb = std::max(knb, (size_t)d.candidates * c->norm_part_n * sizeof(double2));
+    }
+    const int want = std::max(1, std::min((int)slots.size(), env_int("FR3D_GROUP_KSLOTS", 8)));
+    if (c0x->pool_kw_bytes < kwb || c0x->pool_kn_bytes < knb) {
+      for (fr3d_ctx* c : distinct)
+        for (auto& L : c->lanes) (void)hipStreamSynchronize(L.stream);
+      for (auto& p : c0x->pool_kw) dfree(p);
+      for (auto& p : c0x->pool_kn) dfree(p);
+      c0x->pool_kw.clear();
+      c0x->pool_kn.clear();
+      c0x->pool_kw_bytes = kwb;
+      c0x->pool_kn_bytes = knb;
+    }
+    while ((int)c0x->pool_kw.size() < want) {
+      void* w = nullptr;
+      double2* k = nullptr;
+      HIPCHK(c0x, hipMalloc(&w, c0x->pool_kw_bytes));
+      c0x->pool_kw.push_back(w);
+      HIPCHK(c0x, hipMalloc(&k, c0x->pool_kn_bytes));
+      c0x->pool_kn.push_back(k);
+    }
+    for (int k = 0; k < want; ++k) kl.free_slots.push_back(want - 1 - k);
+  }
+  s = run_schedule(slots, it, d, d.candidates ? &kl : nullptr);
   for (size_t k = 0; k < distinct.size(); ++k) fence_lanes(distinct[k], nls[k], false);
   if (s != FR3D_OK)
     for (fr3d_ctx* c : distinct)

@@ -86,6 +86,9 @@ struct Ctrl {
   int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer
   double ct[KMAX];          // log10 alpha of each candidate
   double ca[KMAX];          // filter alpha of each candidate
+  void* kw1;                // K-candidate workspaces of the search: K slices of W1,
+  void* kw2;                // K slices of W2 and K arrays of norm partials (the
+  double2* knorm;           // K-candidate kernels take them from here)
   void* out;                // zeta of the search (device, nz*ny*nx), written by the x pass
 };
 

@@ -131,6 +131,7 @@ __global__ __launch_bounds__(LNT) void k_lay_filter(const c2<T>* __restrict__ B,
     cb = blockIdx.y * a.kb;
     ce = min(cb + a.kb, a.ctrl->kc);
     if (cb >= ce) return;
+    W1 = (c4<T>*)a.ctrl->kw1;  // the search's K-candidate workspace
   }
   const int M = la.M, L = 2 * M - 1;
   const int f = blockIdx.x;

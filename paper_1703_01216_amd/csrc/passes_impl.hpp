@@ -374,6 +374,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     cb = blockIdx.y * a.kb;
     ce = min(cb + a.kb, a.ctrl->kc);
     if (cb >= ce) return;
+    W1 = (c4<T>*)a.ctrl->kw1;  // the search's K-candidate workspace
   }
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
@@ -560,9 +561,11 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
   __shared__ c2<T> tw[P];
   if (inv_idle(a)) return;
   const int cand = a.kmode ? (int)blockIdx.y : 0;  // candidate of a K-candidate step
-  if (a.kmode && cand >= a.ctrl->kc) return;
-  W1 += (size_t)cand * a.w1_stride;
-  W2 += (size_t)cand * a.w2_stride;
+  if (a.kmode) {
+    if (cand >= a.ctrl->kc) return;
+    W1 = (const c4<T>*)a.ctrl->kw1 + (size_t)cand * a.w1_stride;
+    W2 = (c4<T>*)a.ctrl->kw2 + (size_t)cand * a.w2_stride;
+  }
   const int tid = threadIdx.x;
   const long long nrows = (long long)a.kx_n * a.nz;
   const long long row0 = (long long)blockIdx.x * C;
@@ -617,8 +620,10 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   __shared__ double red[NT / 64];
   if (inv_idle(a)) return;
   const int cand = a.kmode ? (int)blockIdx.z : 0;  // candidate of a K-candidate step
-  if (a.kmode && cand >= a.ctrl->kc) return;
-  W2 += (size_t)cand * a.w2_stride;
+  if (a.kmode) {
+    if (cand >= a.ctrl->kc) return;
+    W2 = (const c4<T>*)a.ctrl->kw2 + (size_t)cand * a.w2_stride;
+  }
   const int tid = threadIdx.x;
   const int z = blockIdx.y;
   const int y0 = blockIdx.x * C;
@@ -660,7 +665,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     const double sz = block_sum<NT>(zz, red);
     const double sr = block_sum<NT>(rr, red);
-    if (tid == 0) a.norm_part[(size_t)cand * a.norm_stride + bid] = make_double2(sr, sz);
+    if (tid == 0) (a.kmode ? a.ctrl->knorm : a.norm_part)[(size_t)cand * a.norm_stride + bid] = make_double2(sr, sz);
   }
 }
 
@@ -684,7 +689,7 @@ static __global__ __launch_bounds__(NT) void k_norm_final_k(InvArgs a, int nblk)
   const int kc = a.ctrl->kc;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   for (int j = w; j < kc; j += NT / 64) {
-    const double2 p = strided_sum<double2>(a.norm_part + (size_t)j * a.norm_stride, lane, nblk, 64);
+    const double2 p = strided_sum<double2>(a.ctrl->knorm + (size_t)j * a.norm_stride, lane, nblk, 64);
     const double pr = wave_sum<double>(p.x);
     const double pz = wave_sum<double>(p.y);
     if (lane == 0) { r2[j] = pr; z2[j] = pz; }

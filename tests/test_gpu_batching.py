@@ -93,9 +93,14 @@ def test_kary_options_rejected(fr3d):
 GROUP = [((16, 24, 32), 0), ((24, 16, 16), 1), ((32, 32, 24), 2), ((16, 24, 32), 3), ((24, 16, 16), 1)]
 
 
-@pytest.mark.parametrize("K", [0, 16])
-def test_group_equals_single(fr3d, K):
-    say(f"[group] K={K}")
+@pytest.mark.parametrize("K,slots,graphs", [(0, None, False), (16, None, False), (16, 1, False), (16, 2, True)])
+def test_group_equals_single(fr3d, K, slots, graphs, monkeypatch):
+    # with K candidates the group borrows its workspaces from a pool of `slots`
+    # (fewer than the lanes: items wait for a free slot); results are the
+    # single solves' bit for bit, with and without graph replay
+    say(f"[group] K={K} slots={slots} graphs={graphs}")
+    if slots is not None:
+        monkeypatch.setenv("FR3D_GROUP_KSLOTS", str(slots))
     ctxs, Fs, deltas, V0s, keyed = [], [], [], [], {}
     for i, (shape, q) in enumerate(GROUP):
         nz, ny, nx = shape
@@ -120,15 +125,24 @@ def test_group_equals_single(fr3d, K):
         cc = torch.empty_like(F)
         rep["n_clamped"] = c.recover_c(z, V, 1.0, cc)
         single.append((rep, z, cc))
-    zs = [torch.empty_like(F) for F in Fs]
-    cs = [torch.empty_like(F) for F in Fs]
-    reps = fr3d.solve_group(ctxs, Fs, deltas, zs, V0_list=V0s, c0=1.0, c_list=cs, candidates=K)
-    torch.cuda.synchronize()
-    for (r1, z1, c1), r2, z2, c2 in zip(single, reps, zs, cs):
-        assert np.array_equal(host(z1), host(z2))
-        assert np.array_equal(host(c1), host(c2))
-        for k in ("alpha", "residual", "zeta_norm", "n_evals", "flags", "n_clamped"):
-            assert r1[k] == r2[k]
+    for c in set(ctxs):
+        c.set_graphs(graphs)
+    for rnd in range(2):
+        zs = [torch.empty_like(F) for F in Fs]
+        cs = [torch.empty_like(F) for F in Fs]
+        reps = fr3d.solve_group(ctxs, Fs, deltas, zs, V0_list=V0s, c0=1.0, c_list=cs, candidates=K)
+        torch.cuda.synchronize()
+        for (r1, z1, c1), r2, z2, c2 in zip(single, reps, zs, cs):
+            assert np.array_equal(host(z1), host(z2)), rnd
+            assert np.array_equal(host(c1), host(c2)), rnd
+            for k in ("alpha", "residual", "zeta_norm", "n_evals", "flags", "n_clamped"):
+                assert r1[k] == r2[k]
+    # a single K-candidate search on a context afterwards uses its own workspace again
+    if K:
+        z = torch.empty_like(Fs[0])
+        ctxs[0].set_data(Fs[0], deltas[0])
+        r = ctxs[0].solve_discrepancy(z, candidates=K)
+        assert np.array_equal(host(z), host(single[0][1])) and r["n_evals"] == single[0][0]["n_evals"]
     assert fr3d.solve_group([], [], [], []) == []
 
 
