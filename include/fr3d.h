@@ -390,11 +390,15 @@ fr3d_status fr3d_predictor_load(fr3d_ctx* ctx, const char* path);
  * non-finite values, FR3D_E_STATE without a network; synchronises. */
 fr3d_status fr3d_predictor_set_calibration(fr3d_ctx* ctx, const double* coef, int64_t n);
 
-/* Tile size of a pass (ids as for timing): shift 0 = a 32 KiB LDS tile of
- * pencils, 1 = half, 2 = quarter (row passes 0, 1, 4); for the inverse z
- * pass (3) shift 2 is the half tile of ky columns with u^ and r^ transformed
- * together as one 32 KiB tile.  Lengths below 64 always use shift 0.
- * Results do not depend on it beyond rounding; the autotuner picks it. */
+/* Tile size and radix plan of a pass (ids as for timing): shift 0 = a 32 KiB
+ * LDS tile of pencils, 1 = half, 2 = quarter (row passes 0, 1, 4); for the
+ * inverse z pass (3) shift 2 is the half tile of ky columns with u^ and r^
+ * transformed together as one 32 KiB tile.  Lengths below 64 always use
+ * shift 0.  shift + 4 v selects radix plan variant v (0 default; 1, 2 other
+ * orders of the stage radices) for the FP32 transforms of lengths 192
+ * (16.4.3, 8.8.3, 4.16.3), 384 (16.8.3, 8.16.3, 3.16.8) and 512 (8.8.8,
+ * 16.8.4, 16.16.2); other lengths and FP64 use plan 0.  Results do not depend
+ * on either beyond rounding; the autotuner picks both. */
 fr3d_status fr3d_set_tile(fr3d_ctx* ctx, int32_t pass, int32_t shift);
 
 /* Regularising filter of every later evaluation (Sec. 5 names Tikhonov,

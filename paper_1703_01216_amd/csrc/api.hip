@@ -2128,7 +2128,9 @@ fr3d_status fr3d_set_tile(fr3d_ctx* c, int32_t pass, int32_t shift) {
   if (!c) return FR3D_E_INVALID;
   if (pass < 0 || pass > 5) return fail(c, FR3D_E_INVALID, "pass must be in [0, 5]");
   const int maxsh = (pass == 0 || pass == 1 || pass == 3 || pass == 4) ? 2 : 1;
-  if (shift < 0 || shift > maxsh) return fail(c, FR3D_E_INVALID, "tile shift of pass %d must be in [0, %d]", pass, maxsh);
+  if (shift < 0 || (shift & 3) > maxsh || (shift >> 2) > 2)
+    return fail(c, FR3D_E_INVALID, "tile shift of pass %d must be in [0, %d] plus 4 v with a plan variant v in [0, 2]",
+                pass, maxsh);
   c->tile_sh[pass] = shift;
   return FR3D_OK;
 }

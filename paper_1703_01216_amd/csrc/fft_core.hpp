@@ -111,28 +111,38 @@ template <int R, int DIR, typename T> __device__ __forceinline__ void dftR(c2<T>
 }
 
 // ---------------------------------------------------------------- radix plans
-// Stage radices of each supported length, largest first.
-template <int P> struct Plan;
-#define FR3D_PLAN(P_, N_, R0, R1, R2)                          \
-  template <> struct Plan<P_> {                                 \
+// Stage radices of each supported length, largest first (variant 0), and
+// alternative orders of the three-stage lengths 192, 384 and 512 (variants 1
+// and 2), among which the autotuner chooses per pass.
+template <int P, int V = 0> struct Plan {  // a length without that variant: the default plan
+  static constexpr int nst = Plan<P, 0>::nst, r0 = Plan<P, 0>::r0, r1 = Plan<P, 0>::r1, r2 = Plan<P, 0>::r2;
+};
+#define FR3D_PLAN(P_, V_, N_, R0, R1, R2)                      \
+  template <> struct Plan<P_, V_> {                             \
     static constexpr int nst = N_;                              \
     static constexpr int r0 = R0, r1 = R1, r2 = R2;             \
   };
-FR3D_PLAN(4, 1, 4, 1, 1)
-FR3D_PLAN(6, 2, 3, 2, 1)
-FR3D_PLAN(8, 1, 8, 1, 1)
-FR3D_PLAN(12, 2, 4, 3, 1)
-FR3D_PLAN(16, 1, 16, 1, 1)
-FR3D_PLAN(24, 2, 8, 3, 1)
-FR3D_PLAN(32, 2, 8, 4, 1)
-FR3D_PLAN(48, 2, 16, 3, 1)
-FR3D_PLAN(64, 2, 8, 8, 1)
-FR3D_PLAN(96, 3, 8, 4, 3)
-FR3D_PLAN(128, 2, 16, 8, 1)
-FR3D_PLAN(192, 3, 16, 4, 3)
-FR3D_PLAN(256, 2, 16, 16, 1)
-FR3D_PLAN(384, 3, 16, 8, 3)
-FR3D_PLAN(512, 3, 8, 8, 8)
+FR3D_PLAN(4, 0, 1, 4, 1, 1)
+FR3D_PLAN(6, 0, 2, 3, 2, 1)
+FR3D_PLAN(8, 0, 1, 8, 1, 1)
+FR3D_PLAN(12, 0, 2, 4, 3, 1)
+FR3D_PLAN(16, 0, 1, 16, 1, 1)
+FR3D_PLAN(24, 0, 2, 8, 3, 1)
+FR3D_PLAN(32, 0, 2, 8, 4, 1)
+FR3D_PLAN(48, 0, 2, 16, 3, 1)
+FR3D_PLAN(64, 0, 2, 8, 8, 1)
+FR3D_PLAN(96, 0, 3, 8, 4, 3)
+FR3D_PLAN(128, 0, 2, 16, 8, 1)
+FR3D_PLAN(192, 0, 3, 16, 4, 3)
+FR3D_PLAN(192, 1, 3, 8, 8, 3)
+FR3D_PLAN(192, 2, 3, 4, 16, 3)
+FR3D_PLAN(256, 0, 2, 16, 16, 1)
+FR3D_PLAN(384, 0, 3, 16, 8, 3)
+FR3D_PLAN(384, 1, 3, 8, 16, 3)
+FR3D_PLAN(384, 2, 3, 3, 16, 8)
+FR3D_PLAN(512, 0, 3, 8, 8, 8)
+FR3D_PLAN(512, 1, 3, 16, 8, 4)
+FR3D_PLAN(512, 2, 3, 16, 16, 2)
 #undef FR3D_PLAN
 
 // ---------------------------------------------------------------- LDS tile transform
@@ -193,9 +203,9 @@ __device__ __forceinline__ void stockham_stage(c2<T>* lds, const c2<T>* tw, int 
 
 // Full transform of the tile; the tile must be in LDS and synchronised on entry.
 // tw: the P-entry table e^{-2 pi i m/P} (LDS or global).
-template <typename T, int P, int NC, int LD, int NT, bool COLFAST, int DIR>
+template <typename T, int P, int NC, int LD, int NT, bool COLFAST, int DIR, int V = 0>
 __device__ __forceinline__ void tile_fft(c2<T>* lds, const c2<T>* tw, int tid) {
-  using PL = Plan<P>;
+  using PL = Plan<P, V>;
   stockham_stage<T, P, NC, LD, NT, COLFAST, DIR, PL::r0, 1>(lds, tw, tid);
   if constexpr (PL::nst > 1) stockham_stage<T, P, NC, LD, NT, COLFAST, DIR, PL::r1, PL::r0>(lds, tw, tid);
   if constexpr (PL::nst > 2)

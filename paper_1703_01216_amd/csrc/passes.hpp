@@ -110,7 +110,8 @@ __device__ __forceinline__ bool inv_idle(const InvArgs& a) {
 struct Launch {
   hipStream_t s;
   hipEvent_t e0, e1;
-  int sh;  // tile-size variant: 0 = 32 KiB tile, 1 = half, 2 = quarter (row passes)
+  int sh;  // tile-size variant (0 = 32 KiB tile, 1 = half, 2 = quarter (row passes)) + 4 x the radix
+           // plan variant (0-2; FP32 lengths 192, 384 and 512)
 };
 
 // Each returns hipSuccess or the launch error; P is the transform length of

@@ -7,6 +7,8 @@
 #pragma once
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "passes.hpp"
 
 namespace fr3d {
@@ -35,9 +37,10 @@ __device__ __forceinline__ bool wrap_offset(int a, int n, int p, int& off) {
   return false;
 }
 
-template <typename T, int P, bool GEN, int SH>
+template <typename T, int P, bool GEN, int SHV>
 __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __restrict__ A, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   constexpr int C = TileC<T, P, SH>::C;  // complex pencils per tile = C, real rows = 2C
   constexpr int LD = RowLD<P>::value;
   constexpr int N = P / 2;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
   }
   for (int m = tid + NT; m < P; m += NT) tw[m] = twg[m];
   __syncthreads();
-  tile_fft<T, P, C, LD, NT, false, -1>(lds, tw, tid);
+  tile_fft<T, P, C, LD, NT, false, -1, PV>(lds, tw, tid);
   const int kxn = P / 2 + 1;
   for (int e = tid; e < kxn * 2 * C; e += NT) {
     const int yl = e % (2 * C), kx = e / (2 * C);
@@ -111,9 +114,10 @@ __global__ __launch_bounds__(NT) void k_fx(const T* __restrict__ F, c2<T>* __res
 
 // ============================================================ forward y pass
 // Complex transform along y of every row (kx, z); rows are contiguous.
-template <typename T, int P, bool PRUNE, int SH>
+template <typename T, int P, bool PRUNE, int SHV>
 __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* __restrict__ B, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = RowLD<P>::value;
   constexpr int NIN = PRUNE ? P / 2 : P;
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
     }
   }
   __syncthreads();
-  tile_fft<T, P, C, LD, NT, false, -1>(lds, tw, tid);
+  tile_fft<T, P, C, LD, NT, false, -1, PV>(lds, tw, tid);
   c2<T>* dst = B + row0 * P;
   for (int e = tid; e < rows * P; e += NT) dst[e] = lds[(e / P) * LD + rsw(e % P)];
 }
@@ -160,9 +164,10 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
 // 128 B line of a bin's row of partials is written from one XCD's L2.
 __device__ __forceinline__ int bins_slot(int w, int nblk) { return (w & 7) * (nblk >> 3) + (w >> 3); }
 
-template <typename T, int P, int MODE, int SH>
+template <typename T, int P, int MODE, int SHV>
 __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* __restrict__ S, FwdArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = C;
   constexpr int NIN = MODE == 0 ? P / 2 : P;
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     for (int e = tid; e < C * (P - NIN); e += NT) lds[NIN * LD + e] = mk<T>(0, 0);
   }
   __syncthreads();
-  tile_fft<T, P, C, LD, NT, true, -1>(lds, tw, tid);
+  tile_fft<T, P, C, LD, NT, true, -1, PV>(lds, tw, tid);
   if constexpr (MODE == 0) {
     c2<T>* dst = S + (size_t)kx * P * py;
     const double w = (kx == 0 || 2 * kx == a.bg.px) ? 1.0 : 2.0;
@@ -351,9 +356,10 @@ __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& 
   return tile < ntile;
 }
 
-template <typename T, int P, int MODE, int SH, bool KM>
+template <typename T, int P, int MODE, int SHV, bool KM>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   // SH = 2 (joint variant, Tikhonov mode): C ky columns of the half tile, u^
   // and r^ side by side as 2C pencils, transformed together.
   constexpr bool JOINT = SH == 2 && MODE == 0;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     }
     __syncthreads();
     if constexpr (JOINT) {
-      tile_fft<T, P, 2 * C, LD, NT, true, +1>(lds, tw, tid);
+      tile_fft<T, P, 2 * C, LD, NT, true, +1, PV>(lds, tw, tid);
       c4<T>* dst = W1 + (KM ? (size_t)cand * a.w1_stride : 0) + (size_t)kx * NOUT * py;
 #pragma unroll
       for (int i = 0; i < PO::n; ++i) {
@@ -506,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       }
       continue;
     }
-    tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+    tile_fft<T, P, C, LD, NT, true, +1, PV>(lds, tw, tid);
     c2<T> uo[PO::n];
 #pragma unroll
     for (int i = 0; i < PO::n; ++i) {
@@ -531,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       }
     }
     __syncthreads();
-    if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+    if constexpr (MODE == 0) tile_fft<T, P, C, LD, NT, true, +1, PV>(lds, tw, tid);
     c4<T>* dst = W1 + (KM ? (size_t)cand * a.w1_stride : 0) + (size_t)kx * NOUT * py;
 #pragma unroll
     for (int i = 0; i < PO::n; ++i) {
@@ -548,9 +554,10 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
 
 // ============================================================ inverse y pass
 // Rows (kx, z) of (u, r) pairs: both transformed along y, y < ny written.
-template <typename T, int P, int SH>
+template <typename T, int P, int SHV>
 __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* __restrict__ W2, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   constexpr int C = TileC<T, P, SH + 1>::C;  // rows per tile (two pencils each)
   constexpr int NC = 2 * C;
   constexpr int LD = RowLD<P>::value;
@@ -588,7 +595,7 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
     lds[(2 * r + 1) * LD + rsw(y)] = mk<T>(v[i].z, v[i].w);
   }
   __syncthreads();
-  tile_fft<T, P, NC, LD, NT, false, +1>(lds, tw, tid);
+  tile_fft<T, P, NC, LD, NT, false, +1, PV>(lds, tw, tid);
   c4<T>* dst = W2 + row0 * NOUT;
   for (int e = tid; e < rows * NOUT; e += NT) {
     const int r = e / NOUT, y = e % NOUT;
@@ -606,9 +613,10 @@ __global__ __launch_bounds__(NT) void k_iy(const c4<T>* __restrict__ W1, c4<T>* 
 // zeta = Re/P^3 on R (MODE 0 and 1) and accumulates ||zeta||^2 and
 // ||r||^2 = sum (Im/P^3)^2 in FP64; the last workgroup sums the partials in
 // a fixed order and advances the alpha search (MODE 0).
-template <typename T, int P, int MODE, int SH>
+template <typename T, int P, int MODE, int SHV>
 __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __restrict__ out, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
+  constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   constexpr int C = TileC<T, P, SH>::C;
   constexpr int LD = C + 1;
   constexpr int NOUT = P / 2;
@@ -647,7 +655,7 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
     if (kx > 0 && kx < P / 2) lds[(P - kx) * LD + col] = mk<T>(v[i].x + v[i].w, v[i].z - v[i].y);
   }
   __syncthreads();
-  tile_fft<T, P, C, LD, NT, true, +1>(lds, tw, tid);
+  tile_fft<T, P, C, LD, NT, true, +1, PV>(lds, tw, tid);
   const T sc = (T)a.scale;
   double zz = 0.0, rr = 0.0;
   if (a.ctrl) out = (T*)a.ctrl->out;  // a search writes the zeta its control block names
@@ -752,24 +760,48 @@ static inline hipError_t go(K kern, dim3 g, const Launch& L, Args... args) {
   return hipGetLastError();
 }
 
-// Tile variants: SH = 0 (32 KiB tile), 1 (half), 2 (quarter); the smaller
-// tiles are compiled for P >= 64 only (smaller lengths always use SH = 0).
-template <int P> constexpr int eff_sh(int sh) { return P >= 64 ? sh : 0; }
-#define FR3D_SH(p, sh, EXPR0, EXPR1, EXPR2) \
-  (eff_sh<p>(sh) == 2 ? (EXPR2) : eff_sh<p>(sh) == 1 ? (EXPR1) : (EXPR0))
+// Compiled variants of a pass kernel: the tile shift (0 = 32 KiB tile, 1 =
+// half, 2 = quarter; lengths below 64 only 0) and, for the FP32 transforms of
+// lengths 192, 384 and 512, the radix plan variant (0-2), encoded as the
+// template argument SHV = shift + 4 variant.  A launch's Launch::sh holds the
+// same encoding; `pick` maps it to a compiled instance and calls f with it.
+template <int V> using IC = std::integral_constant<int, V>;
+template <typename T, int p> constexpr bool plan_variants() { return sizeof(T) == 4 && (p == 192 || p == 384 || p == 512); }
+
+template <int NSH, int V, typename F> static inline hipError_t pick_sh(int sh, F&& f) {
+  if constexpr (NSH > 2) {
+    if (sh >= 2) return f(IC<2 + 4 * V>{});
+  }
+  if constexpr (NSH > 1) {
+    if (sh >= 1) return f(IC<1 + 4 * V>{});
+  }
+  return f(IC<4 * V>{});
+}
+
+// NSH: the tile shifts the pass has (a larger request takes the largest)
+template <typename T, int p, int NSH, typename F> static inline hipError_t pick(int shv, F&& f) {
+  if constexpr (p < 64) {
+    return f(IC<0>{});
+  } else {
+    const int sh = shv & 3, pv = shv >> 2;
+    if constexpr (plan_variants<T, p>()) {
+      if (pv == 1) return pick_sh<NSH, 1>(sh, f);
+      if (pv == 2) return pick_sh<NSH, 2>(sh, f);
+    }
+    return pick_sh<NSH, 0>(sh, f);
+  }
+}
 
 template <typename T>
 hipError_t launch_fx(int P, bool gen, const T* F, c2<T>* A, const FwdArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
-    const int sh = eff_sh<p>(L.sh);                                                                              \
-    const int C = sh == 2 ? TileC<T, p, s2>::C : sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;               \
-    dim3 g(cdiv(a.ny_in, 2 * C), a.nz_in);                                                                       \
     if (gen) return go(k_fx<T, p, true, 0>, dim3(cdiv(a.ny_in, 2 * TileC<T, p, 0>::C), a.nz_in), L, F, A, a, tw); \
-    return FR3D_SH(p, sh, go(k_fx<T, p, false, 0>, g, L, F, A, a, tw), go(k_fx<T, p, false, s1>, g, L, F, A, a, tw), \
-                   go(k_fx<T, p, false, s2>, g, L, F, A, a, tw));                                                \
+    return pick<T, p, 3>(L.sh, [&](auto v) {                                                                     \
+      constexpr int S = decltype(v)::value;                                                                      \
+      return go(k_fx<T, p, false, S>, dim3(cdiv(a.ny_in, 2 * TileC<T, p, S & 3>::C), a.nz_in), L, F, A, a, tw);  \
+    });                                                                                                          \
   }
     FR3D_SIZES(X)
 #undef X
@@ -784,13 +816,11 @@ hipError_t launch_fy(int P, bool prune, const c2<T>* A, c2<T>* B, const FwdArgs&
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
-    const int sh = eff_sh<p>(L.sh);                                                                              \
-    const int C = sh == 2 ? TileC<T, p, s2>::C : sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;               \
-    dim3 g(cdiv(nrows, C));                                                                                      \
     if (!prune) return go(k_fy<T, p, false, 0>, dim3(cdiv(nrows, TileC<T, p, 0>::C)), L, A, B, a, tw);           \
-    return FR3D_SH(p, sh, go(k_fy<T, p, true, 0>, g, L, A, B, a, tw), go(k_fy<T, p, true, s1>, g, L, A, B, a, tw), \
-                   go(k_fy<T, p, true, s2>, g, L, A, B, a, tw));                                                 \
+    return pick<T, p, 3>(L.sh, [&](auto v) {                                                                     \
+      constexpr int S = decltype(v)::value;                                                                      \
+      return go(k_fy<T, p, true, S>, dim3(cdiv(nrows, TileC<T, p, S & 3>::C)), L, A, B, a, tw);                   \
+    });                                                                                                          \
   }
     FR3D_SIZES(X)
 #undef X
@@ -804,18 +834,20 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
     if (mode != 0) {                                                                                             \
       dim3 g1(cdiv(a.py / 2 + 1, TileC<T, p, 0>::C), a.kx_n);                                                    \
       return go(k_fz<T, p, 1, 0>, g1, L, B, S, a, tw);                                                           \
     }                                                                                                            \
-    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
-    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
-    const long long npr = (cdiv(a.py, C) + 1) / 2;                                                               \
-    dim3 g(16 * cdiv((long long)a.kx_n * npr, 8));                                                               \
-    hipError_t e = sh == 1 ? go(k_fz<T, p, 0, s1>, g, L, B, S, a, tw) : go(k_fz<T, p, 0, 0>, g, L, B, S, a, tw);  \
+    int nblk = 0;                                                                                                \
+    hipError_t e = pick<T, p, 2>(L.sh, [&](auto v) {                                                             \
+      constexpr int SV = decltype(v)::value;                                                                     \
+      const long long npr = (cdiv(a.py, TileC<T, p, SV & 3>::C) + 1) / 2;                                        \
+      dim3 g(16 * cdiv((long long)a.kx_n * npr, 8));                                                             \
+      nblk = (int)g.x;                                                                                           \
+      return go(k_fz<T, p, 0, SV>, g, L, B, S, a, tw);                                                           \
+    });                                                                                                          \
     if (e != hipSuccess) return e;                                                                               \
-    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, (int)g.x);                                   \
+    hipLaunchKernelGGL(k_bins_final, dim3(64), dim3(NT), 0, L.s, a, nblk);                                       \
     return hipGetLastError();                                                                                    \
   }
     FR3D_SIZES(X)
@@ -825,28 +857,36 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
   }
 }
 
+// grid of the inverse z pass: pairs of full tiles, or groups of four half tiles
+template <typename T, int p, int SH> static inline dim3 iz_grid(const InvArgs& a) {
+  const int C = TileC<T, p, SH >= 1 ? 1 : 0>::C;
+  const long long ntile = cdiv(a.py, C);
+  const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);
+  const long long ngroups = (long long)a.kx_n * (((ntile + 1) / 2 + 1) / 2);
+  return dim3(SH >= 1 ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));
+}
+
 template <typename T>
 hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
-    const int sh0 = eff_sh<p>(L.sh);                                                                             \
-    const int sh = mode != 0 ? (sh0 >= 1 ? 1 : 0) : sh0;  /* 2 = joint u/r variant (filter mode only) */        \
-    const int C = sh >= 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
-    const long long ntile = cdiv(a.py, C);                                                                       \
-    const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);                                              \
-    const long long ngroups = (long long)a.kx_n * (((ntile + 1) / 2 + 1) / 2);                                   \
-    dim3 g(sh >= 1 ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));                                             \
     if (mode != 0)                                                                                               \
-      return sh == 1 ? go(k_iz<T, p, 1, s1, false>, g, L, S, W1, a, tw) : go(k_iz<T, p, 1, 0, false>, g, L, S, W1, a, tw); \
-    if (a.kmode) {                                                                                               \
-      g.y = cdiv(a.kmax, a.kb);                                                                                  \
-      return FR3D_SH(p, sh, go(k_iz<T, p, 0, 0, true>, g, L, S, W1, a, tw), go(k_iz<T, p, 0, s1, true>, g, L, S, W1, a, tw), \
-                     go(k_iz<T, p, 0, s2, true>, g, L, S, W1, a, tw));                                           \
-    }                                                                                                            \
-    return FR3D_SH(p, sh, go(k_iz<T, p, 0, 0, false>, g, L, S, W1, a, tw), go(k_iz<T, p, 0, s1, false>, g, L, S, W1, a, tw), \
-                   go(k_iz<T, p, 0, s2, false>, g, L, S, W1, a, tw));                                            \
+      return pick<T, p, 2>(L.sh, [&](auto v) {                                                                   \
+        constexpr int SV = decltype(v)::value;                                                                   \
+        return go(k_iz<T, p, 1, SV, false>, iz_grid<T, p, SV & 3>(a), L, S, W1, a, tw);                          \
+      });                                                                                                        \
+    if (a.kmode)                                                                                                 \
+      return pick<T, p, 3>(L.sh, [&](auto v) {                                                                   \
+        constexpr int SV = decltype(v)::value;                                                                   \
+        dim3 g = iz_grid<T, p, SV & 3>(a);                                                                       \
+        g.y = cdiv(a.kmax, a.kb);                                                                                \
+        return go(k_iz<T, p, 0, SV, true>, g, L, S, W1, a, tw);                                                  \
+      });                                                                                                        \
+    return pick<T, p, 3>(L.sh, [&](auto v) {                                                                     \
+      constexpr int SV = decltype(v)::value;                                                                     \
+      return go(k_iz<T, p, 0, SV, false>, iz_grid<T, p, SV & 3>(a), L, S, W1, a, tw);                            \
+    });                                                                                                          \
   }
     FR3D_SIZES(X)
 #undef X
@@ -861,12 +901,11 @@ hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const 
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0, s2 = p >= 64 ? 2 : 0;                                                    \
-    const int sh = eff_sh<p>(L.sh);                                                                              \
-    const int C = sh == 2 ? TileC<T, p, s2 + 1>::C : sh == 1 ? TileC<T, p, s1 + 1>::C : TileC<T, p, 1>::C;       \
-    dim3 g(cdiv(nrows, C), a.kmode ? a.kmax : 1);                                                               \
-    return FR3D_SH(p, sh, go(k_iy<T, p, 0>, g, L, W1, W2, a, tw), go(k_iy<T, p, s1>, g, L, W1, W2, a, tw),        \
-                   go(k_iy<T, p, s2>, g, L, W1, W2, a, tw));                                                     \
+    return pick<T, p, 3>(L.sh, [&](auto v) {                                                                     \
+      constexpr int S = decltype(v)::value;                                                                      \
+      dim3 g(cdiv(nrows, TileC<T, p, (S & 3) + 1>::C), a.kmode ? a.kmax : 1);                                    \
+      return go(k_iy<T, p, S>, g, L, W1, W2, a, tw);                                                             \
+    });                                                                                                          \
   }
     FR3D_SIZES(X)
 #undef X
@@ -880,13 +919,13 @@ hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a,
   switch (P) {
 #define X(p)                                                                                                     \
   case p: {                                                                                                      \
-    constexpr int s1 = p >= 64 ? 1 : 0;                                                                          \
-    const int sh = eff_sh<p>(L.sh) >= 1 ? 1 : 0;                                                                 \
-    const int C = sh == 1 ? TileC<T, p, s1>::C : TileC<T, p, 0>::C;                                              \
-    dim3 g(cdiv(a.ny, C), a.nz, a.kmode ? a.kmax : 1);                                                           \
-    if (mode != 0) return sh == 1 ? go(k_ix<T, p, 1, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 1, 0>, g, L, W2, out, a, tw); \
-    hipError_t e = sh == 1 ? go(k_ix<T, p, 0, s1>, g, L, W2, out, a, tw) : go(k_ix<T, p, 0, 0>, g, L, W2, out, a, tw); \
-    if (e != hipSuccess) return e;                                                                               \
+    dim3 g;                                                                                                      \
+    hipError_t e = pick<T, p, 2>(L.sh, [&](auto v) {                                                             \
+      constexpr int S = decltype(v)::value;                                                                      \
+      g = dim3(cdiv(a.ny, TileC<T, p, S & 3>::C), a.nz, a.kmode ? a.kmax : 1);                                   \
+      return mode != 0 ? go(k_ix<T, p, 1, S>, g, L, W2, out, a, tw) : go(k_ix<T, p, 0, S>, g, L, W2, out, a, tw); \
+    });                                                                                                          \
+    if (e != hipSuccess || mode != 0) return e;                                                                  \
     if (a.kmode) hipLaunchKernelGGL(k_norm_final_k, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));             \
     else hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(NT), 0, L.s, a, (int)(g.x * g.y));                       \
     return hipGetLastError();                                                                                    \

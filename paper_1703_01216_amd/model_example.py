@@ -85,13 +85,23 @@ def run(n=256, nz=51, amplitude=1e-8, precision=64, filt=(2, 1), seed=0, log10_a
     wx = np.where((np.arange(kxn) == 0) | (np.arange(kxn) == kxn - 1), 1, 2)
     wy = np.where((np.arange(pyh) == 0) | (np.arange(pyh) == pyh - 1), 1, 2)
     w = (wx[:, None] * wy[None, :]).ravel()
-    kv = kept.ravel()
-    order = np.argsort(kv, kind="stable")
-    cw = np.cumsum(w[order]) / w.sum()
-    quant = lambda q: int(kv[order][np.searchsorted(cw, q)])  # noqa: E731
-    svs = {"kept_p10": quant(0.1), "kept_median": quant(0.5), "kept_p90": quant(0.9), "kept_max": int(kv.max()),
-           "frac_kept_15_25": float(w[(kv >= 15) & (kv <= 25)].sum() / w.sum()),
-           "s_lowest_frequency": sv[0, 0].cpu().tolist()}
+    def counts(k):
+        kv = k.ravel()
+        order = np.argsort(kv, kind="stable")
+        cw = np.cumsum(w[order]) / w.sum()
+        quant = lambda q: int(kv[order][np.searchsorted(cw, q)])  # noqa: E731
+        return {"p10": quant(0.1), "median": quant(0.5), "p90": quant(0.9), "max": int(kv.max()),
+                "frac_15_25": float(w[(kv >= 15) & (kv <= 25)].sum() / w.sum())}
+
+    kc = counts(kept)
+    svs = {"kept_p10": kc["p10"], "kept_median": kc["median"], "kept_p90": kc["p90"], "kept_max": kc["max"],
+           "frac_kept_15_25": kc["frac_15_25"], "s_lowest_frequency": sv[0, 0].cpu().tolist()}
+    # the same counts at the paper's fixed thresholds (Sec. 6: 1e-12 ... 1e-13),
+    # relative to each system's largest value and to the largest of all systems
+    svh = sv.cpu().numpy()
+    for thr in (1e-12, 1e-13):
+        svs[f"kept_rel_own_{thr:g}"] = counts((svh >= thr * svh[..., :1]).sum(axis=2))
+        svs[f"kept_rel_max_{thr:g}"] = counts((svh >= thr * svh.max()).sum(axis=2))
     out = dict(geometry=g, precision=precision, filter=list(filt), amplitude=amplitude, delta=delta, tau=tau,
                alpha=rep["alpha"], flags=rep["flags"], n_evals=rep["n_evals"],
                r_over_delta=rep["residual"] / delta if delta > 0 else None,

@@ -6,7 +6,8 @@
   fixed alpha and at the search's alpha, element by element against the FP64
   oracle.
 * Transform length 192 (n = 96, radix plan 16 x 4 x 3) on every axis, cubic
-  and anisotropic, FP32 and FP64, default and tuned tiles.
+  and anisotropic, FP32 and FP64, default and tuned tiles; the alternative
+  radix plans of lengths 192, 384 and 512 on every axis.
 * The uneven-size batched workload: every instance the benchmark solves
   (shapes from {64, 96, 128, 192} per axis, so lengths 128, 192, 256 and 384),
   under the group solver with 16 candidates per step, each item's estimate
@@ -129,6 +130,35 @@ def test_length_192(fr3d, shape, precision, tiles):
     check_estimate(c, g, khat, Fh, 1e-3, zeta, rep, precision)
     rep = c.solve_discrepancy(zeta)
     check_estimate(c, g, khat, Fh, rep["alpha"], zeta, rep, precision)
+
+
+PLAN_SHAPES = [(96, 12, 16), (16, 96, 24), (24, 16, 96), (192, 8, 12), (8, 192, 12), (12, 8, 192),
+               (256, 8, 12), (8, 256, 12), (12, 8, 256)]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("shape", PLAN_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_radix_plan_variants(fr3d, shape, variant):
+    # the alternative radix plans of lengths 192, 384 and 512 (FP32) on each
+    # axis, with every tile shift of each pass drawn at random: spectrum and
+    # estimate against the oracle
+    nx, ny, nz = shape
+    say(f"[plans] shape {shape} variant {variant}")
+    g = geom(nx, ny, nz)
+    d = instance(g, 900 + nx + 5 * ny + 11 * nz, 0.02, recipe="inclusions")
+    c = fr3d.Context()
+    c.load_kernel(nx, ny, nz, precision=32)
+    rg = np.random.default_rng(nx * 7 + ny * 3 + nz + variant)
+    for p in range(6):
+        c.set_tile(p, int(rg.integers(0, 3 if p in (0, 1, 3, 4) else 2)) + 4 * variant)
+    Fd = dev(d["F"], 32)
+    Fh = host(Fd)
+    c.set_data(Fd, d["delta"])
+    check_spectrum(c, g, Fh, 32)
+    khat = np.fft.fftn(sample_kernel(g))
+    zeta = torch.empty_like(Fd)
+    rep = c.solve_alpha(1e-3, zeta)
+    check_estimate(c, g, khat, Fh, 1e-3, zeta, rep, 32)
 
 
 @pytest.mark.parametrize("index", range(8))
