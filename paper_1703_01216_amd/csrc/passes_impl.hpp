@@ -296,8 +296,8 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 }
 
 // ============================================================ inverse z pass
-// Reads f^ for C ky-columns of one kx plane and all kz, forms per point (FP64
-// coefficients from the octant of k^, rounded to T):
+// Reads f^ for C ky-columns of one kx plane and all kz, forms per point (the
+// coefficients in T's precision from the FP64 octant of k^):
 //   MODE 0: u^ = conj(k^) f^ g(s),  r^ = -e(s) f^   with s = |k^|^2 and the
 //           regularising filter (Sec. 4-5):
 //             Tikhonov           g = 1/(s + a),                 e = a/(s + a)
@@ -308,11 +308,15 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
 // as (u, r) pairs.
 //
 // 1/x for normal positive x: the hardware estimate refined by two Newton
-// steps r <- r + r (1 - x r), within an ulp of the quotient.
+// steps r <- r + r (1 - x r), within an ulp of the quotient (FP32: one step).
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = fma(r, fma(-x, r, 1.0), r);
   return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recipf(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // Octant reuse: rows kz and P-kz need the same octant entry (conjugated), so
@@ -396,7 +400,34 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   // filter of one point: u and r from f^ and the (possibly conjugated) k^
   auto filt = [&](double aa, c2<T> f, double2 kk, c2<T>& u, c2<T>& r) {
     const double fx = (double)f.x, fy = (double)f.y;
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 0 && sizeof(T) == 4) {
+      // FP32 transforms filter in FP32: the coefficients from the FP64
+      // spectrum rounded to FP32 (relative error ~1e-7, the order of the
+      // transforms' own rounding); the TSVD cut is decided in FP64
+      const float kxf = (float)kk.x, kyf = (float)kk.y, aaf = (float)aa;
+      const float sf = fmaf(kxf, kxf, kyf * kyf);
+      float gu, cr;
+      if (a.filt == 0) {
+        gu = recipf(sf + aaf);
+        cr = -aaf * gu;
+      } else if (a.filt == 1) {
+        const float d = recipf(sf + aaf), q = aaf * d;
+        float qp = 1.0f, sum = 1.0f;
+        for (int j = 1; j < a.order; ++j) {
+          qp *= q;
+          sum += qp;
+        }
+        gu = d * sum;
+        cr = -(qp * q);
+      } else {
+        const bool keep = kk.x * kk.x + kk.y * kk.y >= aa;
+        gu = keep ? recipf(sf) : 0.0f;
+        cr = keep ? 0.0f : -1.0f;
+      }
+      const float cx = kxf * gu, cy = -kyf * gu;  // conj(k^) g
+      u = mk<T>((T)(f.x * cx - f.y * cy), (T)(f.x * cy + f.y * cx));
+      r = mk<T>((T)(f.x * cr), (T)(f.y * cr));
+    } else if constexpr (MODE == 0) {
       const double s = kk.x * kk.x + kk.y * kk.y;
       double gu, cr;
       if (a.filt == 0) {
