@@ -13,9 +13,12 @@ recovery of c.
 Searches run on the same batch (config.modes):
   learned      -- the predictor fine-tuned on the GPU for this geometry on
                   untimed instances (calibrate.fine_tune), its seed refined by
-                  secant steps on ln(r/T) (a seed next to the lower range end
-                  starts there); every point accepted when |r/delta - 1| <= 1e-3
-                  (the headline value)
+                  secant steps on ln(r/T), the first with the slope of the
+                  whole-box residual at the seed (formed by the seed's own
+                  evaluation) times the calibrated ratio (a seed next to the
+                  lower range end starts there); every point accepted when
+                  |r/delta - 1| <= 1e-3 (the headline value)
+  learned_fixed -- the same with the calibrated median slope for the first step
   bisection    -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
   learned_net  -- the shipped network alone (no fine-tuning), secant steps with
                   the median root slope of its training instances
@@ -150,7 +153,9 @@ def _oracle_task(task):
         y, _ = mlp.forward(p, xs[None, :], bf16=True)
         t_seed = float(norm[130] + norm[131] * y[0])
         res = discrepancy.seeded_secant(ev, delta, t_seed, tol=1e-3, acc_lo=1 - 1e-3, acc_hi=1 + 1e-3,
-                                        slope=opts["seed_slope"], snap=opts["seed_snap_lo"])
+                                        slope=opts["seed_slope"], snap=opts.get("seed_snap_lo", 0.0),
+                                        slope_ratio=opts.get("seed_slope_ratio", 0.0),
+                                        slope_at=lambda t: tikhonov.full_box_slope(g, khat, F, 10.0 ** t))
     return {"seconds": time.perf_counter() - t0, "n_evals": res["n_evals"], "alpha": res["alpha"],
             "flags": res["flags"]}
 
@@ -630,7 +635,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes of the CPU baseline")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
-    ap.add_argument("--modes", default="learned,bisection,learned_net,learned_w,bisection_w,kary16")
+    ap.add_argument("--modes", default="learned,bisection,learned_fixed,learned_net,learned_w,bisection_w,kary16")
     ap.add_argument("--calibrate", type=int, default=96,
                     help="instances (not timed) on which the network is fine-tuned for this geometry; 0: none")
     ap.add_argument("--fp64", type=int, default=1, help="solve the batch in FP64 too")
@@ -691,10 +696,12 @@ def main():
         cal["first_index"] = CAL_FIRST
         del Fc
         net_tuned = ctx.predictor_get()
-        sk = {k: cal[k] for k in ("seed_slope", "seed_snap_lo")}
+        sk = {k: cal[k] for k in ("seed_slope", "seed_snap_lo", "seed_slope_ratio")}
         print(f"[bench] fine-tuning for the geometry: {cal}", file=sys.stderr, flush=True)
     mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
                  "learned_net": fr3d.default_opts(use_predictor=1, seed_slope=train_slope, **tight),
+                 # the fine-tuned seed with the fixed median slope for the first step
+                 "learned_fixed": fr3d.default_opts(use_predictor=1, **{**sk, "seed_slope_ratio": 0.0}, **tight),
                  "bisection": fr3d.default_opts(**tight),
                  "learned_w": fr3d.default_opts(use_predictor=1, **sk, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}

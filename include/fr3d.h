@@ -96,6 +96,11 @@ typedef struct {
                                             log10(delta/||F||), the noise feature); default 0 */
   double seed_snap_lo;                   /* >= 0: a seed below log10_alpha_lo + seed_snap_lo (decades)
                                             starts the search at log10_alpha_lo; default 0 (off) */
+  double seed_slope_ratio;               /* > 0 (3D form, Tikhonov filter, secant refinement): the first
+                                            step's slope is seed_slope_ratio times the slope of the
+                                            full-box residual d ln ||C u - E_Y F|| / d log10 alpha at the
+                                            seed, formed exactly by the seed's evaluation; seed_slope
+                                            when that is not positive; default 0 (off) */
 } fr3d_dp_opts;
 
 typedef struct {

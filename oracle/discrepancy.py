@@ -32,7 +32,11 @@ Seeded search (a predicted t0 from the alpha predictor; not in the paper):
   Secant refinement (``seeded_secant``): after the seed, steps on
   g = ln(r/T): the first with an assumed slope of g per decade, later ones
   through the last two points, regula falsi (Illinois) whenever a step would
-  leave a known bracket; range ends and the step limit as above.
+  leave a known bracket; range ends and the step limit as above.  With a
+  slope ratio c > 0 the assumed slope becomes c times the whole-box
+  residual's slope d ln ||r_box|| / d log10 alpha at the seed, when that is
+  positive (the residual on Y is a part of the whole-box one and its slope
+  follows it closely on one geometry).
 
 K-candidate search (K alphas per step, log-spaced in the current bracket; not
 in the paper -- the batched form of the same rule):
@@ -176,7 +180,7 @@ def seeded(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=
 
 
 def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, acc_lo=0.9, acc_hi=1.1,
-                  tau=1.0, h_op=0.0, mu=0.0, slope=0.03, snap=0.0):
+                  tau=1.0, h_op=0.0, mu=0.0, slope=0.03, snap=0.0, slope_at=None, slope_ratio=0.0):
     """Seeded search refined by secant steps on g(t) = ln(r / T) (a proposal
     for the learned path; the paper has no predictor).  From the seed the
     first step is Newton's with the assumed slope ``slope`` of g per decade
@@ -187,7 +191,9 @@ def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, 
     A point at hi below the target ends with NOROOT_HIGH, one at lo above it
     with NOROOT_LOW; after max_steps steps the answer is the upper bracket
     end (MAXITER), evaluated if it was not the last point.  The first point
-    is the seed as in ``_start``."""
+    is the seed as in ``_start``.  With ``slope_ratio`` > 0 and
+    ``slope_at(t)`` (the whole-box residual's slope at t) positive at the
+    seed, the assumed slope is ``slope_ratio * slope_at(seed)`` instead."""
     ev = _Counter(evaluate, delta, tau, h_op, mu)
 
     def ok(ratio):
@@ -205,6 +211,10 @@ def seeded_secant(evaluate, delta, t0, lo=-8.0, hi=0.0, max_steps=40, tol=1e-3, 
     if ok(ratio):
         return out(t, 0)
     flags = PRED_FALLBACK
+    if slope_ratio > 0 and slope_at is not None:
+        sf = slope_at(t)
+        if sf > 0:
+            slope = slope_ratio * sf
     g = lg(ratio)
     a = b = ga = gb = None
     side = 0

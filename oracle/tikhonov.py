@@ -103,6 +103,23 @@ def solve_spectral(g: Geom, khat, F, alpha: float, relative: bool = False, metho
     )
 
 
+def full_box_slope(g: Geom, khat, F, alpha: float, relative: bool = False) -> float:
+    """Slope d ln ||C zeta_pad - E_Y F|| / d log10 alpha of the whole-box
+    Tikhonov residual (used by the learned search's first secant step; not in
+    the paper).  The residual spectrum is -e f^ with e = a / (s + a), and
+    de / d ln a = e (1 - e), so by Parseval
+
+        d ln ||r_box|| / d ln a = sum e^2 (1 - e) |f^|^2 / sum e^2 |f^|^2,
+
+    times ln 10 per decade of alpha."""
+    a = alpha_abs(khat, alpha, relative)
+    fhat = np.fft.fftn(pad(g, np.asarray(F, dtype=np.float64)))
+    s = (khat * khat.conj()).real
+    e = a / (s + a)
+    q = e * e * (fhat * fhat.conj()).real
+    return float(np.log(10.0) * np.sum(q * (1.0 - e)) / np.sum(q))
+
+
 def circulant_matrix(k):
     """C[p, q] = k[(p - q) mod P] over the flattened P^3 box (x fastest)."""
     P = k.shape

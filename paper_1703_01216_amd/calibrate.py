@@ -2,7 +2,8 @@
 
     from paper_1703_01216_amd import calibrate
     cal = calibrate.fine_tune(ctx, Fs, deltas)      # ctx holds the trained network
-    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_snap_lo=cal["seed_snap_lo"])
+    opts = fr3d.default_opts(use_predictor=1, seed_slope=cal["seed_slope"], seed_snap_lo=cal["seed_snap_lo"],
+                             seed_slope_ratio=cal["seed_slope_ratio"])
 
 The predictor is trained on a mix of grids, source sets and heights of Y
 (the training workload); on one fixed geometry its seeds carry an error that
@@ -23,7 +24,12 @@ Adam), so the seed becomes the network's, with no other model beside it:
   instance whose root lies below the range ends after one evaluation);
 * seed_slope, the slope of ln r per decade of alpha that the first secant
   step assumes, is the median over the instances of the one-sided
-  difference (ln r(t* + h) - ln delta)/h at the root.
+  difference (ln r(t* + h) - ln delta)/h at the root;
+* seed_slope_ratio, the factor from the slope of the whole-box residual
+  (which each seed evaluation forms exactly) to that of the residual on Y,
+  is the median over the instances of the ratio of the two one-sided
+  differences at the root (the whole-box residual from the library's
+  diagnostics).
 
 Everything runs through the library's calls; the host only forms medians
 and standard deviations of the values they return.
@@ -74,16 +80,24 @@ def fine_tune(ctx, Fs, deltas, lr=1e-3, steps=100, hold=0.25, h=0.05, label_tol=
     root = [(r["flags"] & 7) == 0 for r in reps]
     label_evals = sum(r["n_evals"] for r in reps)
     # slope of ln r at the root, one-sided over h decades
-    slopes = []
+    slopes, ratios = [], []
     z = zs[0]
-    for i in range(m):
-        if not root[i] or t[i] + h > hi:
-            continue
-        ctx.set_data(Fs[i], deltas[i])
-        r = ctx.solve_alpha(10.0 ** (t[i] + h), z)["residual"]
-        s = (math.log(r) - math.log(deltas[i])) / h
-        if s > 0:
-            slopes.append(s)
+    ctx.set_diagnostics(True)
+    try:
+        for i in range(m):
+            if not root[i] or t[i] + h > hi:
+                continue
+            ctx.set_data(Fs[i], deltas[i])
+            r1 = ctx.solve_alpha(10.0 ** (t[i] + h), z)
+            r0 = ctx.solve_alpha(10.0 ** t[i], z)
+            s = (math.log(r1["residual"]) - math.log(deltas[i])) / h
+            sf = (math.log(r1["residual_full_box"]) - math.log(r0["residual_full_box"])) / h
+            if s > 0:
+                slopes.append(s)
+                if sf > 0:
+                    ratios.append(s / sf)
+    finally:
+        ctx.set_diagnostics(False)
     # fine-tune on the fitted part (fresh Adam moments)
     params, norm = ctx.predictor_get()
     ctx.predictor_set(params, norm)
@@ -98,7 +112,10 @@ def fine_tune(ctx, Fs, deltas, lr=1e-3, steps=100, hold=0.25, h=0.05, label_tol=
     err = [min(max(float(yh[k]), lo), hi) - t[i] for k, i in enumerate(held_idx) if root[i]]
     sigma = std(err) if len(err) >= 2 else 0.0
     torch.cuda.synchronize()
-    return dict(seed_slope=median(slopes), seed_snap_lo=SNAP_SIGMAS * sigma, instances=m, fitted=len(fit_idx),
+    return dict(seed_slope=median(slopes), seed_snap_lo=SNAP_SIGMAS * sigma,
+                seed_slope_ratio=median(ratios) if ratios else 0.0,
+                slope_ratio_spread=(std(ratios) / median(ratios)) if len(ratios) >= 2 else 0.0,
+                instances=m, fitted=len(fit_idx),
                 held_out=len(held_idx), held_out_err_std_decades=sigma,
                 held_out_err_mean_decades=(sum(err) / len(err)) if err else 0.0,
                 slope_instances=len(slopes), label_evals=label_evals, lr=lr, steps=steps,

@@ -313,6 +313,7 @@ struct Lane {
   void* own_kwork = nullptr;
   double2* own_knorm = nullptr;
   int own_kcap = 0;
+  bool slope_next = false;         // the next evaluation is a seed that forms the full-box slope
   hipGraphExec_t gexec = nullptr;  // captured evaluation (valid for gkmax and gsh)
   int gkmax = -1;
   int gsh[6] = {0, 0, 0, 0, 0, 0};
@@ -673,7 +674,9 @@ LayArgs lay_args(fr3d_ctx* c) {
   return la;
 }
 
-template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out, bool adj = false) {
+// slope: the seed of a secant search with a slope ratio, whose z pass also
+// writes the partial sums of the full-box slope
+template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out, bool adj = false, bool slope = false) {
   const bool dbl = sizeof(T) == 8;
   void *twx, *twy, *twz;
   fr3d_status st;
@@ -683,6 +686,13 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
   Bufs<T> b = bufs<T>(c, L);
   InvArgs a = inv_args(c, L, mode == 0);
   a.adj = adj ? 1 : 0;
+  // the slope partials go to the z-pass bin partials, free between the
+  // forward pass's features and the next data set
+  if (slope && mode == 0 && !c->layered && c->filt == 0 && L.kmax == 0) {
+    a.slope_part = (double2*)L.bins_part;
+    if (!iz_slope_map<T>(c->pz, c->tile_sh[3], a) || (size_t)a.slope_n * 2 > c->bins_part_n * 64)
+      return fail(c, FR3D_E_INVALID, "z pass of length %d: no slope partials", c->pz);
+  }
   if (mode == 0 && L.kmax > 0) {
     // K-candidate step (runs only while the search is in that state)
     const size_t nA = (size_t)c->kxn * c->g.nz * c->g.ny, nB = (size_t)c->kxn * c->g.nz * c->py;
@@ -733,8 +743,9 @@ fr3d_status set_data_lane(fr3d_ctx* c, Lane& L, const void* F, double delta) {
   return FR3D_OK;
 }
 
-fr3d_status enqueue_eval(fr3d_ctx* c, Lane& L) {
-  return c->esz == 8 ? inverse<double>(c, L, 0, (double*)nullptr) : inverse<float>(c, L, 0, (float*)nullptr);
+fr3d_status enqueue_eval(fr3d_ctx* c, Lane& L, bool slope = false) {
+  return c->esz == 8 ? inverse<double>(c, L, 0, (double*)nullptr, false, slope)
+                     : inverse<float>(c, L, 0, (float*)nullptr, false, slope);
 }
 
 // One evaluation of the lane's search (zeta goes where its control block
@@ -742,6 +753,10 @@ fr3d_status enqueue_eval(fr3d_ctx* c, Lane& L) {
 // (kernels only: every argument is fixed for the lane's geometry, the search
 // state lives in the control block) and replayed.
 fr3d_status eval_lane(fr3d_ctx* c, Lane& L) {
+  if (L.slope_next) {  // the seed that forms the full-box slope: launched on its own
+    L.slope_next = false;
+    return enqueue_eval(c, L, true);
+  }
   if (!c->graphs || c->timing) return enqueue_eval(c, L);
   if (!L.gexec || L.gkmax != L.kmax || std::memcmp(L.gsh, c->tile_sh, sizeof(L.gsh))) {
     if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
@@ -792,7 +807,8 @@ fr3d_status check_opts(fr3d_ctx* c, const fr3d_dp_opts* o, fr3d_dp_opts* d) {
       !std::isfinite(d->log10_alpha_hi) || d->max_steps < 0 || d->max_steps > 200 || !(d->tol >= 0) ||
       !(d->tau > 0) || !(d->h_op >= 0) || !(d->mu >= 0) || !(d->accept_lo <= d->accept_hi) ||
       !(d->seed_walk > 0) || !std::isfinite(d->seed_walk) || !(d->seed_slope >= 0) || !std::isfinite(d->seed_slope) || !std::isfinite(d->seed_slope_x) ||
-      !(d->seed_snap_lo >= 0) || !std::isfinite(d->seed_snap_lo))
+      !(d->seed_snap_lo >= 0) || !std::isfinite(d->seed_snap_lo) || !(d->seed_slope_ratio >= 0) ||
+      !std::isfinite(d->seed_slope_ratio))
     return fail(c, FR3D_E_INVALID, "bad search options");
   if (d->candidates != 0 && (d->candidates < 2 || d->candidates > KMAX || d->use_predictor || d->max_steps < 1))
     return fail(c, FR3D_E_INVALID, "candidates must be 2..%d, without use_predictor, with max_steps >= 1", KMAX);
@@ -833,6 +849,10 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
   v.slope = d.seed_slope;
   v.slope_x = d.seed_slope_x;
   v.snap = d.seed_snap_lo;
+  v.slope_ratio =
+      (!d.candidates && d.use_predictor && d.seed_slope > 0 && c->filt == 0 && !c->layered) ? d.seed_slope_ratio : 0.0;
+  L.slope_next = v.slope_ratio > 0;  // the next evaluation is the seed
+  v.slope_full = -1.0;
   v.state = ST_HI;
   v.t = v.hi;
   v.alpha_abs = std::pow(10.0, v.hi) * v.a_scale;
@@ -872,6 +892,7 @@ fr3d_status start_search(fr3d_ctx* c, Lane& L, const fr3d_dp_opts& d, void* zeta
 
 fr3d_status fixed_search(fr3d_ctx* c, Lane& L, double alpha, void* zeta) {
   L.kmax = 0;
+  L.slope_next = false;
   Ctrl v = ctrl_base(c, L);
   v.out = zeta;
   v.state = ST_FIXED;
@@ -932,7 +953,8 @@ fr3d_status enqueue_search(fr3d_ctx* c, int max_evals, fr3d_report* rep_dev) {
   Lane& L = c->lanes[0];
   fr3d_status s;
   for (int i = 0; i < max_evals; ++i)
-    if ((s = enqueue_eval(c, L))) return s;
+    if ((s = enqueue_eval(c, L, i == 0 && L.slope_next))) return s;
+  L.slope_next = false;
   hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, L.stream, (const Ctrl*)L.ctrl, rep_dev);
   LCHK(c, hipGetLastError());
   return FR3D_OK;
@@ -1035,6 +1057,7 @@ void fr3d_dp_opts_default(fr3d_dp_opts* o) {
   o->seed_slope = 0.0;
   o->seed_slope_x = 0.0;
   o->seed_snap_lo = 0.0;
+  o->seed_slope_ratio = 0.0;
   o->candidates = 0;
 }
 

@@ -27,7 +27,10 @@
 // first with the assumed slope of g per decade, later ones through the last
 // two points (the assumed slope when that is not positive); a step that
 // would leave a known bracket becomes the regula falsi point (Illinois);
-// NOROOT at a range end, MAXITER after max_steps steps (answer b).
+// NOROOT at a range end, MAXITER after max_steps steps (answer b).  With a
+// slope ratio c > 0 the first step assumes c times the whole-box residual's
+// slope d ln ||C u - E_Y F|| / d log10 alpha at the seed (closed form by
+// Parseval, summed by the seed's own z pass) when that is positive.
 // K-candidate search: each step evaluates K alphas at once (the pass kernels
 // take the candidate from the grid), step 1 at K points from lo to hi, later
 // steps at the K interior points of the bracket (spaced (b - a)/(K + 1)).
@@ -81,6 +84,8 @@ struct Ctrl {
   double slope;      // assumed d ln(r/T) / d log10 alpha of the secant refinement (0: walk)
   double slope_x;    // secant slope 10^(slope_x x_64) with the noise feature x_64 of the data
   double snap;       // a seed below lo + snap starts at lo
+  double slope_ratio;  // > 0: the first secant step's slope is slope_ratio x slope_full
+  double slope_full; // d ln r_full / d log10 alpha at the last evaluation (< 0: not formed)
   int32_t have;      // secant refinement: bit 0 a known, bit 1 b known, bit 2 previous point known
   // K-candidate search
   int32_t kc, kmax, pend;   // candidates this step, K, flags of the answer
@@ -206,10 +211,16 @@ __device__ inline void ctrl_secant(Ctrl* c, double rho, double ratio) {
   ctrl_set_t(c, tn);
 }
 
-// Advance after an evaluation at c->t with ||r||^2 = r2 and ||zeta||^2 = z2.
-__device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
+// Whether the evaluation now running forms the full-box slope: the seed of
+// a secant search with slope_ratio > 0.
+__device__ __forceinline__ bool ctrl_wants_slope(const Ctrl* c) { return c->state == ST_SEED && c->slope_ratio > 0; }
+
+// Advance after an evaluation at c->t with ||r||^2 = r2 and ||zeta||^2 = z2
+// (sfull: the full-box slope, or < 0 when not formed).
+__device__ inline void ctrl_advance(Ctrl* c, double r2, double z2, double sfull = -1.0) {
   c->r2 = r2;
   c->z2 = z2;
+  c->slope_full = sfull;
   c->n_evals += 1;
   const double r = sqrt(r2), zn = sqrt(z2);
   const double g = c->tau * c->delta + c->h_op * zn;
@@ -264,6 +275,7 @@ __device__ inline void ctrl_advance(Ctrl* c, double r2, double z2) {
         c->have = 0;
         c->side = 0;
         c->steps = 0;
+        if (c->slope_ratio > 0 && c->slope_full > 0) c->slope = c->slope_ratio * c->slope_full;
         ctrl_secant(c, rho, ratio);
         return;
       }

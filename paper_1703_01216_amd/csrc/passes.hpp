@@ -95,6 +95,16 @@ struct InvArgs {
   // single evaluations with diagnostics: per-workgroup partial sums of the
   // full-box residual (Parseval over the half spectrum); null: not formed
   double* full_part;
+  // the seed evaluation of a secant search with a slope ratio (Tikhonov
+  // filter): per z-pass workgroup (sum w e^2 |f^|^2, sum w e^2 (1 - e) |f^|^2)
+  // over its columns, e = a / (s + a) the residual factor and w the
+  // half-spectrum weight; the x pass's final kernel forms the full-box slope
+  // from the entries of the workgroups that hold a tile.  Set for the seed's
+  // launch only; null otherwise.
+  double2* slope_part;
+  int slope_n;              // z-pass workgroups
+  int slope_ntile;          // column tiles per kx plane of the z pass
+  int slope_quad;           // 1: the z pass maps workgroups by quads (else pairs) of tiles
 };
 
 // Whether an inverse-pass kernel of this launch has nothing to do.
@@ -131,6 +141,11 @@ template <typename T>
 hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& a, const c2<T>* tw, const Launch& L);
 template <typename T>
 hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L);
+// The workgroup map of launch_iz's single-evaluation Tikhonov launch for
+// tile code sh, into a.slope_n, a.slope_ntile and a.slope_quad; false for an
+// unsupported length.
+template <typename T>
+bool iz_slope_map(int P, int sh, InvArgs& a);
 template <typename T>
 hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a, const c2<T>* tw, const Launch& L);
 

@@ -397,8 +397,9 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int oz = P / 2 + 1, oy = py / 2 + 1;
   const c2<T>* src = S + (size_t)kx * P * py;
   const double2* oc = a.oct + (size_t)kx * oz * oy;
-  // filter of one point: u and r from f^ and the (possibly conjugated) k^
-  auto filt = [&](double aa, c2<T> f, double2 kk, c2<T>& u, c2<T>& r) {
+  // filter of one point: u and r from f^ and the (possibly conjugated) k^;
+  // returns the residual factor (r^ = cr f^; 0 for the forward operator)
+  auto filt = [&](double aa, c2<T> f, double2 kk, c2<T>& u, c2<T>& r) -> T {
     const double fx = (double)f.x, fy = (double)f.y;
     if constexpr (MODE == 0 && sizeof(T) == 4) {
       // FP32 transforms filter in FP32: the coefficients from the FP64
@@ -427,6 +428,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const float cx = kxf * gu, cy = -kyf * gu;  // conj(k^) g
       u = mk<T>((T)(f.x * cx - f.y * cy), (T)(f.x * cy + f.y * cx));
       r = mk<T>((T)(f.x * cr), (T)(f.y * cr));
+      return (T)cr;
     } else if constexpr (MODE == 0) {
       const double s = kk.x * kk.x + kk.y * kk.y;
       double gu, cr;
@@ -450,11 +452,23 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const double cx = kk.x * gu, cy = -kk.y * gu;  // conj(k^) g
       u = mk<T>((T)(fx * cx - fy * cy), (T)(fx * cy + fy * cx));
       r = mk<T>((T)(fx * cr), (T)(fy * cr));
+      return (T)cr;
     } else {
       const double kyv = a.adj ? -kk.y : kk.y;  // adjoint: conj(k^), the correlation with K
       u = mk<T>((T)(fx * kk.x - fy * kyv), (T)(fx * kyv + fy * kk.x));
       r = mk<T>(0, 0);
+      return (T)0;
     }
+  };
+  // Tikhonov residual r^ = -e f^ with e = a / (s + a) = -cr: ||r||^2 sums
+  // w e^2 |f^|^2 and its derivative in ln a sums 2 w e^2 (1 - e) |f^|^2.
+  // Summed on every evaluation (a few FMAs; a branch here would split the
+  // unrolled filter loop), reduced only when the slope is wanted.
+  T sa = 0, sb = 0;
+  auto slope_add = [&](c2<T> r, T cr) {
+    const T q = r.x * r.x + r.y * r.y;
+    sa += q;
+    sb += q * (1 + cr);
   };
   // loads: kept in registers across the candidates
   constexpr int TPC = PAIRED ? NT / C : 1;         // threads per column
@@ -501,11 +515,13 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         const int p = j + TPC * i;
         const int r1 = p == 0 ? P / 2 : P - p;
         c2<T> u0, u1;
-        filt(aa, f0[i], k[i], u0, r[2 * i]);
+        const T c0 = filt(aa, f0[i], k[i], u0, r[2 * i]);
         double2 k1 = k[i];
         if (p == 0) k1 = kmid;
         else k1.y = -k1.y;  // row P-p > P/2: conj
-        filt(aa, f1[i], k1, u1, r[2 * i + 1]);
+        const T c1 = filt(aa, f1[i], k1, u1, r[2 * i + 1]);
+        slope_add(r[2 * i], c0);
+        slope_add(r[2 * i + 1], c1);
         lds[p * LD + col] = u0;
         lds[r1 * LD + col] = u1;
         if constexpr (JOINT) {
@@ -520,11 +536,24 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         double2 kk = k[i];
         if (e / C > P / 2) kk.y = -kk.y;
         c2<T> u;
-        filt(aa, f0[i], kk, u, r[i]);
+        const T c0 = filt(aa, f0[i], kk, u, r[i]);
+        slope_add(r[i], c0);
         if (PE::ok(e)) {
           lds[(e / C) * LD + e % C] = u;
           if constexpr (JOINT) lds[(e / C) * LD + C + e % C] = r[i];
         }
+      }
+    }
+    if constexpr (MODE == 0 && !KM) {
+      // the seed of a secant search with a slope ratio (the host passes
+      // slope_part for that launch only): the workgroup's partials, with the
+      // half-spectrum weight w
+      if (a.slope_part && a.filt == 0) {
+        __shared__ double red[NT / 64];
+        const double w = (kx == 0 || kx == a.kx_n - 1) ? 1.0 : 2.0;
+        const double A = block_sum<NT>((double)sa, red);
+        const double B = block_sum<NT>((double)sb, red);
+        if (tid == 0) a.slope_part[blockIdx.x] = make_double2(w * A, w * B);
       }
     }
     __syncthreads();
@@ -710,13 +739,34 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
 
 // Final sum of the x pass's norm partials in a fixed order (one workgroup),
 // then one step of the alpha search.
+// With the z pass's slope partials (seed of a secant search), also the
+// full-box slope d ln ||r|| / d log10 a = ln 10 sum w e^2 (1 - e) |f^|^2 /
+// sum w e^2 |f^|^2.
 static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
   __shared__ double red[NT / 64];
   if (inv_idle(a)) return;
   const double2 p = strided_sum<double2>(a.norm_part, threadIdx.x, nblk, NT);
   const double tr = block_sum<NT>(p.x, red);
   const double tz = block_sum<NT>(p.y, red);
-  if (threadIdx.x == 0) ctrl_advance(a.ctrl, tr, tz);
+  double sfull = -1.0;
+  if (a.slope_part && a.filt == 0 && ctrl_wants_slope(a.ctrl)) {
+    // the entries of workgroups with a tile, each thread over a fixed stride
+    double2 q = make_double2(0.0, 0.0);
+    for (int w = threadIdx.x; w < a.slope_n; w += NT) {
+      int kx, tile;
+      const bool mine = a.slope_quad ? xcd_quad_map(w, a.kx_n, a.slope_ntile, kx, tile)
+                                     : xcd_pair_map(w, a.kx_n, a.slope_ntile, kx, tile);
+      if (mine) {
+        const double2 v = a.slope_part[w];
+        q.x += v.x;
+        q.y += v.y;
+      }
+    }
+    const double A = block_sum<NT>(q.x, red);
+    const double B = block_sum<NT>(q.y, red);
+    if (A > 0) sfull = 2.302585092994045684 * B / A;
+  }
+  if (threadIdx.x == 0) ctrl_advance(a.ctrl, tr, tz, sfull);
 }
 
 // The same for the kc candidates of a K-candidate step: wave w sums the
@@ -926,6 +976,25 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
   }
 }
 
+template <typename T> bool iz_slope_map(int P, int sh, InvArgs& a) {
+  switch (P) {
+#define X(p)                                                                                                     \
+  case p:                                                                                                        \
+    (void)pick<T, p, 3>(sh, [&](auto v) {                                                                        \
+      constexpr int SV = decltype(v)::value;                                                                     \
+      a.slope_n = (int)iz_grid<T, p, SV & 3>(a).x;                                                               \
+      a.slope_ntile = (int)cdiv(a.py, TileC<T, p, (SV & 3) >= 1 ? 1 : 0>::C);                                    \
+      a.slope_quad = (SV & 3) >= 1 ? 1 : 0;                                                                      \
+      return hipSuccess;                                                                                         \
+    });                                                                                                          \
+    return true;
+    FR3D_SIZES(X)
+#undef X
+    default:
+      return false;
+  }
+}
+
 template <typename T>
 hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L) {
   const long long nrows = (long long)a.kx_n * a.nz;
@@ -974,6 +1043,7 @@ hipError_t launch_ix(int P, int mode, const c4<T>* W2, T* out, const InvArgs& a,
   template hipError_t launch_fz<T>(int, int, const c2<T>*, c2<T>*, const FwdArgs&, const c2<T>*, const Launch&);  \
   template hipError_t launch_iz<T>(int, int, const c2<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);  \
   template hipError_t launch_iy<T>(int, const c4<T>*, c4<T>*, const InvArgs&, const c2<T>*, const Launch&);       \
+  template bool iz_slope_map<T>(int, int, InvArgs&);                                                              \
   template hipError_t launch_ix<T>(int, int, const c4<T>*, T*, const InvArgs&, const c2<T>*, const Launch&);
 
 }  // namespace fr3d

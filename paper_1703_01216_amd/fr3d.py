@@ -54,7 +54,8 @@ class DpOpts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("h_op", ctypes.c_double), ("mu", ctypes.c_double),
                 ("use_predictor", ctypes.c_int32), ("seed_walk", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("seed_slope", ctypes.c_double),
-                ("seed_slope_x", ctypes.c_double), ("seed_snap_lo", ctypes.c_double)]
+                ("seed_slope_x", ctypes.c_double), ("seed_snap_lo", ctypes.c_double),
+                ("seed_slope_ratio", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):

@@ -229,14 +229,17 @@ def test_predictor_checkpoint(fr3d, tmp_path):
     assert ei.value.status == fr3d.E_INVALID
 
 
-@pytest.mark.parametrize("bias,slope,tol,shift,snap", [(-3.0, 0.05, 1e-3, 0.0, 0.0), (-6.5, 0.5, 1e-6, 0.0, 0.0),
-                                                        (0.7, 0.2, 1e-3, 0.0, 0.0), (-20.0, 0.03, 1e-3, 0.0, 0.0),
-                                                        (-1.0, 2.0, 1e-9, 0.0, 0.0), (-3.0, 0.3, 1e-6, -0.75, 0.0),
-                                                        (-7.95, 0.3, 1e-6, 0.0, 0.1), (-7.5, 0.3, 1e-6, 0.0, 0.4),
-                                                        (-7.5, 0.3, 1e-6, 0.0, 0.6)])
-def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift, snap):
+@pytest.mark.parametrize("bias,slope,tol,shift,snap,ratio", [
+    (-3.0, 0.05, 1e-3, 0.0, 0.0, 0.0), (-6.5, 0.5, 1e-6, 0.0, 0.0, 0.0), (0.7, 0.2, 1e-3, 0.0, 0.0, 0.0),
+    (-20.0, 0.03, 1e-3, 0.0, 0.0, 0.0), (-1.0, 2.0, 1e-9, 0.0, 0.0, 0.0), (-3.0, 0.3, 1e-6, -0.75, 0.0, 0.0),
+    (-7.95, 0.3, 1e-6, 0.0, 0.1, 0.0), (-7.5, 0.3, 1e-6, 0.0, 0.4, 0.0), (-7.5, 0.3, 1e-6, 0.0, 0.6, 0.0),
+    (-3.0, 5.0, 1e-9, 0.0, 0.0, 0.25), (-6.5, 0.05, 1e-9, 0.0, 0.0, 0.3), (-1.0, 0.5, 1e-9, 0.0, 0.0, 1.0),
+    (-7.95, 0.3, 1e-6, 0.0, 0.1, 0.25), (0.7, 0.2, 1e-6, 0.0, 0.0, 0.25)])
+def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift, snap, ratio):
     # the secant refinement after the seed takes the oracle rule's decisions
-    # (FP64, same evaluations), including the range ends and MAXITER
+    # (FP64, same evaluations), including the range ends and MAXITER; with a
+    # slope ratio the first step's slope comes from the whole-box residual
+    # at the seed
     g = geom(16, 16, 16)
     d = instance(g, 71, 0.02)
     c = fr3d.Context()
@@ -252,7 +255,7 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift, snap):
     kw = dict(tol=tol, accept_lo=1.0, accept_hi=1.0, max_steps=6)
     if shift:
         c.predictor_set_calibration([shift] + [0.0] * 65)
-    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, seed_snap_lo=snap, **kw)
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=slope, seed_snap_lo=snap, seed_slope_ratio=ratio, **kw)
     khat = np.fft.fftn(sample_kernel(g))
 
     def ev(a):
@@ -261,7 +264,9 @@ def test_seeded_secant_matches_rule_fp64(fr3d, bias, slope, tol, shift, snap):
     # a calibration with only an intercept shifts the network's output before
     # the clip to the range
     ref = discrepancy.seeded_secant(ev, d["delta"], bias + shift, tol=tol, acc_lo=1.0, acc_hi=1.0, max_steps=6,
-                                    slope=slope, snap=snap)
+                                    slope=slope, snap=snap, slope_ratio=ratio,
+                                    slope_at=lambda t: tikhonov.full_box_slope(g, khat, d["F"], 10.0 ** t))
+    print("secant", bias, slope, ratio, "evals", rep["n_evals"], ref["n_evals"], flush=True)
     # the first point: the seed, or the lower range end for a seed within the margin
     assert ref["trace"][0][0] == (-8.0 if bias + shift < -8.0 + snap else min(max(bias + shift, -8.0), 0.0))
     assert rep["flags"] == ref["flags"]

@@ -46,6 +46,7 @@ def test_defaults_and_status_strings(lib):
     assert (o.log10_alpha_lo, o.log10_alpha_hi, o.max_steps, o.tol) == (-8.0, 0.0, 40, 1e-3)
     assert (o.accept_lo, o.accept_hi, o.tau, o.h_op, o.mu, o.use_predictor) == (0.9, 1.1, 1.0, 0.0, 0.0, 0)
     assert o.seed_walk == 0.25 and o.candidates == 0 and o.seed_slope == 0.0 and o.seed_slope_x == 0.0 and o.seed_snap_lo == 0.0
+    assert o.seed_slope_ratio == 0.0
     assert lib.fr3d_status_string(0) == b"ok"
     assert lib.fr3d_status_string(1) == b"invalid argument"
     assert lib.fr3d_last_error(None) == b"null context"
@@ -84,7 +85,8 @@ def test_struct_layouts_match_header():
     assert fr3d.Geom.hz.offset == 48
     assert ctypes.sizeof(fr3d.Report) == 64 and fr3d.Report.n_evals.offset == 40 and fr3d.Report.n_clamped.offset == 48
     assert fr3d.Report.residual_full_box.offset == 56
-    assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 120 and fr3d.DpOpts.seed_walk.offset == 80 and fr3d.DpOpts.seed_slope.offset == 96 and fr3d.DpOpts.seed_snap_lo.offset == 112
+    assert fr3d.DpOpts.tol.offset == 24 and ctypes.sizeof(fr3d.DpOpts) == 128 and fr3d.DpOpts.seed_walk.offset == 80 and fr3d.DpOpts.seed_slope.offset == 96 and fr3d.DpOpts.seed_snap_lo.offset == 112
+    assert fr3d.DpOpts.seed_slope_ratio.offset == 120
     assert fr3d.DpOpts.candidates.offset == 88
 
 

@@ -244,6 +244,41 @@ def test_dense_normal_equations_equal_spectral(shape, alpha):
     assert sp["imag_max"] < 1e-12 * np.abs(sp["zeta"]).max()
 
 
+@pytest.mark.parametrize("shape,alpha", [((3, 4, 4), 1e-3), ((3, 4, 6), 1e-5), ((4, 4, 4), 3e-2)])
+def test_full_box_slope_is_the_derivative_of_dense_solves(shape, alpha):
+    # the Parseval form of d ln ||r_box|| / d log10 alpha against a central
+    # difference of the whole-box residual of the assembled normal equations
+    nz, ny, nx = shape
+    g = Geom(nx, ny, nz)
+    k = sample_kernel(g)
+    khat, s, smax = tikhonov.kernel_spectrum(k)
+    F = inputs.rng(8).standard_normal(shape)
+    h = 1e-4
+    lr = [math.log(np.linalg.norm(tikhonov.dense_tikhonov(g, k, F, alpha * smax * 10.0 ** (j * h))["r_full"]))
+          for j in (-1, 1)]
+    fd = (lr[1] - lr[0]) / (2 * h)
+    assert fd > 0
+    assert tikhonov.full_box_slope(g, khat, F, alpha, relative=True) == pytest.approx(fd, rel=1e-6)
+
+
+def test_full_box_slope_closed_forms():
+    # identity kernel: e = a / (1 + a) everywhere, slope ln10 / (1 + a)
+    g = Geom(4, 4, 4)
+    k = np.zeros(g.pshape)
+    k[0, 0, 0] = 1.0
+    khat = np.fft.fftn(k)
+    F = inputs.rng(12).standard_normal(g.shape)
+    for a in (1e-6, 0.3, 7.0):
+        assert tikhonov.full_box_slope(g, khat, F, a) == pytest.approx(math.log(10.0) / (1.0 + a), rel=1e-13)
+    # a kernel without zero modes: r_box -> a k^-2 f^ as a -> 0 (slope ln 10),
+    # and r_box -> f^ (slope 0) as a grows
+    g = Geom(4, 4, 3)
+    khat = np.fft.fftn(sample_kernel(g))
+    F = inputs.rng(9).standard_normal(g.shape)
+    assert tikhonov.full_box_slope(g, khat, F, 1e-14, relative=True) == pytest.approx(math.log(10.0), rel=1e-6)
+    assert 0 < tikhonov.full_box_slope(g, khat, F, 1e8, relative=True) < 1e-6
+
+
 @pytest.mark.parametrize("order", [1, 2, 5])
 @pytest.mark.parametrize("shape,alpha", [((4, 4, 4), 1e-2), ((3, 4, 6), 1e-4)])
 def test_iterated_tikhonov_equals_repeated_normal_equations(shape, alpha, order):
@@ -466,6 +501,32 @@ def test_seeded_secant_steps():
     # a seed inside the window is accepted at once
     res = discrepancy.seeded_secant(ev, delta, t_star + 1e-4, slope=0.5)
     assert res["flags"] == 0 and res["n_evals"] == 1
+
+
+def test_seeded_secant_slope_from_the_whole_box():
+    # with the ratio times the whole-box slope equal to the true slope of the
+    # straight line, the first step lands on the root whatever slope is
+    # assumed; a whole-box slope that is not positive keeps the assumed one
+    tight = dict(tol=1e-9, acc_lo=1.0, acc_hi=1.0)
+    seen = []
+
+    def at(t):
+        seen.append(t)
+        return 0.2 / 0.25
+    res = discrepancy.seeded_secant(_loglinear(-3.2, 0.2), 1.0, -2.1, slope=5.0, slope_at=at, slope_ratio=0.25,
+                                    **tight)
+    assert res["n_evals"] == 2 and res["t"] == pytest.approx(-3.2, abs=1e-12) and seen == [-2.1]
+    base = discrepancy.seeded_secant(_loglinear(-3.2, 0.2), 1.0, -2.1, slope=5.0, **tight)
+    assert base["n_evals"] > 2
+    for at2, ratio in ((lambda t: -1.0, 0.25), (lambda t: 0.0, 0.25), (at, 0.0)):
+        res = discrepancy.seeded_secant(_loglinear(-3.2, 0.2), 1.0, -2.1, slope=5.0, slope_at=at2,
+                                        slope_ratio=ratio, **tight)
+        assert res["trace"] == base["trace"]
+    # a seed accepted at once asks for no slope
+    seen.clear()
+    res = discrepancy.seeded_secant(_loglinear(-3.2, 0.2), 1.0, -3.2, slope=5.0, slope_at=at, slope_ratio=0.25,
+                                    **tight)
+    assert res["n_evals"] == 1 and seen == []
 
 
 def test_seeded_secant_range_ends_and_step_limit():
