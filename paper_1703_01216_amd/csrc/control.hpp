@@ -42,6 +42,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace fr3d {
@@ -67,14 +68,17 @@ constexpr int KMAX = 16;  // candidates per step of the K-candidate search
 enum : int32_t { F_NOROOT_HIGH = 1, F_NOROOT_LOW = 2, F_MAXITER = 4, F_NAN = 8, F_PRED_FALLBACK = 16 };
 
 struct Ctrl {
+  // first: every pass kernel of an evaluation reads these 16 bytes as one
+  // load at its start (ctrl_head)
+  int32_t state, active;
+  double alpha_abs;  // 10^t * a_scale, read by the filter
   // settings
   double a_scale, delta, tau, h_op, mu, tol, acc_lo, acc_hi, lo, hi, walk;
   int32_t max_steps;
   // state
-  int32_t state, active, n_evals, flags, steps;
+  int32_t n_evals, flags, steps;
   double t;          // log10 of the alpha being evaluated (caller units)
   double a, b;       // bracket
-  double alpha_abs;  // 10^t * a_scale, read by the filter
   double r2, z2;     // norms of the last evaluation
   double r2_full;    // full-box ||r||^2 of the last evaluation (diagnostics; < 0: not formed)
   double target;     // T of the last evaluation
@@ -96,6 +100,18 @@ struct Ctrl {
   double2* knorm;           // K-candidate kernels take them from here)
   void* out;                // zeta of the search (device, nz*ny*nx), written by the x pass
 };
+
+static_assert(offsetof(Ctrl, state) == 0 && offsetof(Ctrl, active) == 4 && offsetof(Ctrl, alpha_abs) == 8,
+              "ctrl_head reads the first 16 bytes");
+
+// state, active and alpha_abs in one 16-byte load
+__device__ __forceinline__ void ctrl_head(const Ctrl* c, int32_t& state, int32_t& active, double& alpha_abs) {
+  int4 v;
+  __builtin_memcpy(&v, c, sizeof(v));
+  state = v.x;
+  active = v.y;
+  alpha_abs = __hiloint2double(v.w, v.z);
+}
 
 __device__ __forceinline__ void ctrl_set_t(Ctrl* c, double t) {
   c->t = t;

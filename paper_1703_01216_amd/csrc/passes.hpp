@@ -107,11 +107,18 @@ struct InvArgs {
   int slope_quad;           // 1: the z pass maps workgroups by quads (else pairs) of tiles
 };
 
-// Whether an inverse-pass kernel of this launch has nothing to do.
-__device__ __forceinline__ bool inv_idle(const InvArgs& a) {
+// Whether an inverse-pass kernel of this launch has nothing to do; alpha:
+// the single evaluation's filter alpha (one load with the state).
+__device__ __forceinline__ bool inv_idle(const InvArgs& a, double& alpha) {
+  alpha = 0.0;
   if (!a.ctrl) return false;
-  if (!a.ctrl->active) return true;
-  return (a.ctrl->state == ST_KARY) != (a.kmode != 0);
+  int32_t state, active;
+  ctrl_head(a.ctrl, state, active, alpha);
+  return !active || ((state == ST_KARY) != (a.kmode != 0));
+}
+__device__ __forceinline__ bool inv_idle(const InvArgs& a) {
+  double alpha;
+  return inv_idle(a, alpha);
 }
 
 // ------------------------------------------------------------------ host launchers

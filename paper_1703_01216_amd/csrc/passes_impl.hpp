@@ -377,7 +377,8 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   constexpr bool PAIRED = C <= NT && NT % C == 0 && (P / 2) % (NT / C) == 0;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
-  if (inv_idle(a)) return;
+  double alpha1;  // the single evaluation's alpha
+  if (inv_idle(a, alpha1)) return;
   // candidates [cb, ce) of a K-candidate step, else the single evaluation
   int cb = 0, ce = 1;
   if constexpr (KM) {
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
   for (int cand = cb; cand < ce; ++cand) {
-    const double aa = MODE == 0 ? (KM ? a.ctrl->ca[cand] : a.ctrl->alpha_abs) : 0.0;
+    const double aa = MODE == 0 ? (KM ? a.ctrl->ca[cand] : alpha1) : 0.0;
     if (KM && cand > cb) __syncthreads();  // the previous candidate's stores have read the tile
     c2<T> r[PE::n];
     if constexpr (PAIRED) {
