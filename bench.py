@@ -75,14 +75,15 @@ def pass_source_digest():
 def pass_bytes(n, esz=4, shape=None):
     """Algorithmic bytes of each pass for an n^3 grid (or shape = (nz, ny, nx))
     padded to P = 2n per axis: reads of the nonzero inputs plus writes of the
-    kept outputs (complex = 2 esz; the kernel-spectrum octant is FP64
-    complex)."""
+    kept outputs (complex = 2 esz; the Tikhonov filter reads the kernel
+    spectrum's octant as complex of the same precision: the FP32 path its
+    FP32 rounding, the FP64 path the FP64 octant)."""
     nz, ny, nx = shape or (n, n, n)
     Pz, Py = 2 * nz, 2 * ny
     kx = nx + 1
     c = 2 * esz
     cells = nx * ny * nz
-    octant = kx * (Pz // 2 + 1) * (Py // 2 + 1) * 16
+    octant = kx * (Pz // 2 + 1) * (Py // 2 + 1) * c
     return {
         "fwd_x": cells * esz + kx * nz * ny * c,
         "fwd_y": kx * nz * ny * c + kx * nz * Py * c,

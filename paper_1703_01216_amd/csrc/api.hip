@@ -211,6 +211,12 @@ __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long lon
 }
 
 // Per-block maxima of |k^|^2 over the octant (it covers every value of |k^|).
+// The octant rounded to FP32 (each component to nearest).
+__global__ void k_round_octant(const double2* __restrict__ oct, long long n, float2* __restrict__ o32) {
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    o32[i] = make_float2((float)oct[i].x, (float)oct[i].y);
+}
+
 __global__ void k_smax_part(const double2* __restrict__ oct, long long n, double* part) {
   __shared__ double red[NT];
   double m = 0.0;
@@ -334,6 +340,7 @@ struct fr3d_ctx {
   size_t esz = 4;
   double smax = 0;
   double2* oct = nullptr;
+  float2* oct32 = nullptr;  // FP32 contexts: the octant rounded to FP32 once (the FP32 filter's operand)
   // per-frequency z-systems (Algorithm 1 as in Sec. 5) instead of the 3D embedding
   bool layered = false;
   double *lay_kt = nullptr, *lay_V = nullptr, *lay_lam = nullptr;
@@ -483,6 +490,7 @@ fr3d_status alloc_lane_geometry(fr3d_ctx* c, Lane& L) {
 
 void free_geometry(fr3d_ctx* c) {
   dfree(c->oct);
+  dfree(c->oct32);
   dfree(c->lay_kt);
   dfree(c->lay_V);
   dfree(c->lay_lam);
@@ -636,6 +644,7 @@ InvArgs inv_args(fr3d_ctx* c, Lane& L, bool search) {
   // the per-frequency path inverts a lateral (2D) transform only
   a.scale = c->layered ? 1.0 / ((double)c->px * c->py) : 1.0 / ((double)c->px * c->py * c->pz);
   a.oct = c->oct;
+  a.oct32 = c->oct32;
   a.ctrl = search ? L.ctrl : nullptr;
   a.norm_part = L.norm_part;
   a.filt = c->filt;
@@ -1273,6 +1282,12 @@ fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc
   if (le != hipSuccess) return fail(c, FR3D_E_DEVICE, "kernel spectrum: %s", hipGetErrorString(le));
   c->smax = L0.scal_host[0];
   if (!(c->smax > 0) || !std::isfinite(c->smax)) return fail(c, FR3D_E_DEVICE, "kernel spectrum has no energy");
+  if (c->esz == 4) {
+    HIPCHK(c, hipMalloc(&c->oct32, noct * sizeof(float2)));
+    const unsigned nr = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 4096);
+    hipLaunchKernelGGL(k_round_octant, dim3(nr), dim3(NT), 0, L0.stream, (const double2*)c->oct, (long long)noct, c->oct32);
+    LCHK(c, hipGetLastError());
+  }
   const bool dbl = c->esz == 8;
   if ((st = get_twiddles(c, c->px, dbl, &twx)) || (st = get_twiddles(c, c->py, dbl, &twy)) ||
       (st = get_twiddles(c, c->pz, dbl, &twz)))

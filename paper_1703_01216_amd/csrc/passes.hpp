@@ -78,6 +78,7 @@ struct InvArgs {
   int kx_n, py, pz;
   double scale;             // 1/(Px Py Pz)
   const double2* oct;
+  const float2* oct32;      // the octant rounded to FP32 (FP32 contexts; the FP32 Tikhonov-family filter)
   Ctrl* ctrl;               // null for the forward operator (no search)
   double2* norm_part;       // [x-pass workgroups] (||r||^2, ||zeta||^2) partials
   // K-candidate step (kmode = 1): candidate j filters with ctrl->ca[j] and

@@ -360,9 +360,13 @@ __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& 
   return tile < ntile;
 }
 
-template <typename T, int P, int MODE, int SHV, bool KM>
+// K32: the FP32 Tikhonov-family filter reads the kernel spectrum as FP32
+// (a.oct32, the FP64 octant rounded once), the values it rounds to anyway.
+template <typename T, int P, int MODE, int SHV, bool KM, bool K32 = false>
 __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* __restrict__ W1, InvArgs a,
                                            const c2<T>* __restrict__ twg) {
+  static_assert(!K32 || (sizeof(T) == 4 && MODE == 0), "FP32 spectrum: FP32 filter only");
+  using KT = typename std::conditional<K32, float2, double2>::type;
   constexpr int SH = SHV & 3, PV = SHV >> 2;  // tile shift, radix plan variant
   // SH = 2 (joint variant, Tikhonov mode): C ky columns of the half tile, u^
   // and r^ side by side as 2C pencils, transformed together.
@@ -397,10 +401,12 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
   const c2<T>* src = S + (size_t)kx * P * py;
-  const double2* oc = a.oct + (size_t)kx * oz * oy;
+  const KT* oc;
+  if constexpr (K32) oc = a.oct32 + (size_t)kx * oz * oy;
+  else oc = a.oct + (size_t)kx * oz * oy;
   // filter of one point: u and r from f^ and the (possibly conjugated) k^;
   // returns the residual factor (r^ = cr f^; 0 for the forward operator)
-  auto filt = [&](double aa, c2<T> f, double2 kk, c2<T>& u, c2<T>& r) -> T {
+  auto filt = [&](double aa, c2<T> f, KT kk, c2<T>& u, c2<T>& r) -> T {
     const double fx = (double)f.x, fy = (double)f.y;
     if constexpr (MODE == 0 && sizeof(T) == 4) {
       // FP32 transforms filter in FP32: the coefficients from the FP64
@@ -476,8 +482,9 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   constexpr int UPT = PAIRED ? (P / 2) / TPC : 1;  // row pairs per thread
   constexpr int NF = PAIRED ? UPT : PE::n;
   c2<T> f0[NF], f1[PAIRED ? UPT : 1];
-  double2 k[NF];
-  double2 kmid = make_double2(0.0, 0.0);
+  const KT k0{0, 0};
+  KT k[NF];
+  KT kmid = k0;
   if constexpr (PAIRED) {
     const int col = tid % C, j = tid / C;
     const int ky = ky0 + col;
@@ -489,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const int r1 = p == 0 ? P / 2 : P - p;
       f0[i] = okc ? src[(size_t)p * py + ky] : mk<T>(0, 0);
       f1[i] = okc ? src[(size_t)r1 * py + ky] : mk<T>(0, 0);
-      k[i] = okc ? oc[(size_t)p * oy + my] : make_double2(0.0, 0.0);
+      k[i] = okc ? oc[(size_t)p * oy + my] : k0;
     }
     if (j == 0 && okc) kmid = oc[(size_t)(P / 2) * oy + my];
   } else {
@@ -501,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const int mz = kz <= P / 2 ? kz : P - kz;
       const int my = ky <= py / 2 ? ky : py - ky;
       f0[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
-      k[i] = ok ? oc[(size_t)mz * oy + my] : make_double2(0.0, 0.0);
+      k[i] = ok ? oc[(size_t)mz * oy + my] : k0;
     }
   }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
@@ -517,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
         const int r1 = p == 0 ? P / 2 : P - p;
         c2<T> u0, u1;
         const T c0 = filt(aa, f0[i], k[i], u0, r[2 * i]);
-        double2 k1 = k[i];
+        KT k1 = k[i];
         if (p == 0) k1 = kmid;
         else k1.y = -k1.y;  // row P-p > P/2: conj
         const T c1 = filt(aa, f1[i], k1, u1, r[2 * i + 1]);
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
 #pragma unroll
       for (int i = 0; i < PE::n; ++i) {
         const int e = tid + i * NT;
-        double2 kk = k[i];
+        KT kk = k[i];
         if (e / C > P / 2) kk.y = -kk.y;
         c2<T> u;
         const T c0 = filt(aa, f0[i], kk, u, r[i]);
@@ -958,15 +965,20 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
         constexpr int SV = decltype(v)::value;                                                                   \
         return go(k_iz<T, p, 1, SV, false>, iz_grid<T, p, SV & 3>(a), L, S, W1, a, tw);                          \
       });                                                                                                        \
+    const bool k32 = sizeof(T) == 4 && a.oct32 && a.filt != 2; /* TSVD decides its cut in FP64 */            \
     if (a.kmode)                                                                                                 \
       return pick<T, p, 3>(L.sh, [&](auto v) {                                                                   \
         constexpr int SV = decltype(v)::value;                                                                   \
         dim3 g = iz_grid<T, p, SV & 3>(a);                                                                       \
         g.y = cdiv(a.kmax, a.kb);                                                                                \
+        if constexpr (sizeof(T) == 4)                                                                            \
+          if (k32) return go(k_iz<T, p, 0, SV, true, true>, g, L, S, W1, a, tw);                                 \
         return go(k_iz<T, p, 0, SV, true>, g, L, S, W1, a, tw);                                                  \
       });                                                                                                        \
     return pick<T, p, 3>(L.sh, [&](auto v) {                                                                     \
       constexpr int SV = decltype(v)::value;                                                                     \
+      if constexpr (sizeof(T) == 4)                                                                              \
+        if (k32) return go(k_iz<T, p, 0, SV, false, true>, iz_grid<T, p, SV & 3>(a), L, S, W1, a, tw);           \
       return go(k_iz<T, p, 0, SV, false>, iz_grid<T, p, SV & 3>(a), L, S, W1, a, tw);                            \
     });                                                                                                          \
   }
