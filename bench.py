@@ -56,12 +56,14 @@ CAL_FIRST = 100000  # first instance index of the seed calibration set (disjoint
 PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
-# sources with this digest; see profiles/passes_256cube_traffic.md.
-MEASURED_TRAFFIC = {"digest": "1aa75ca38983bf9d", "n": 128,
-                    "bytes": {"inv_z": 170.0e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 103.7e6,
+# sources with this digest; see profiles/passes_256cube_traffic.md and
+# profiles/passes_512cube_traffic.md.
+MEASURED_TRAFFIC = {"digest": "59cdc3fe6427ff8a", "n": 128,
+                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.3e6, "fwd_z": 103.7e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
-# the same at 256^3 -> 512^3 (profiles/passes_512cube_traffic.md); None until taken
-MEASURED_TRAFFIC_512 = None
+MEASURED_TRAFFIC_512 = {"digest": "59cdc3fe6427ff8a", "n": 256,
+                        "bytes": {"inv_z": 1230.0e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 817.2e6,
+                                  "fwd_y": 404.4e6, "fwd_x": 202.0e6}}
 
 
 def pass_source_digest():
@@ -627,8 +629,8 @@ def fp64_section(torch, fr3d, Fs, deltas, net, learned_opts, bisect_opts, lanes,
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--lanes", type=int, default=8)
