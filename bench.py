@@ -146,7 +146,8 @@ def _oracle_task(task):
         res = discrepancy.bisection(ev, delta, tol=1e-3)
     else:
         params, norm, opts = task["net"]
-        x, _ = features.features(np.fft.fftn(pad(g, F)), delta, float(np.linalg.norm(F)))
+        s = (khat * khat.conj()).real
+        x, _ = features.features(np.fft.fftn(pad(g, F)), delta, float(np.linalg.norm(F)), s, float(s.max()))
         p, k = {}, 0
         for name, shape in mlp.PARAM_SHAPES:
             m = int(np.prod(shape))

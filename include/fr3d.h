@@ -178,8 +178,8 @@ fr3d_status fr3d_load_layered(fr3d_ctx* ctx, const fr3d_geom* geom);
 
 /* Set the data F on Y (nz*ny*nx values, device) and the noise level delta >= 0
  * (absolute, ||F - A zeta|| <= delta).  Runs the zero-padded forward
- * transform (Algorithm 1 step 1 for the data) and its radial energy
- * reduction.  F is not retained. */
+ * transform (Algorithm 1 step 1 for the data) and the predictor features'
+ * energy reduction.  F is not retained. */
 fr3d_status fr3d_set_data(fr3d_ctx* ctx, const void* F_dev, double delta);
 
 /* One alpha evaluation at alpha > 0 (units set by geom.alpha_relative):
@@ -349,7 +349,10 @@ fr3d_status fr3d_add_noise(fr3d_ctx* ctx, void* F_dev, const void* e_dev, double
  *   octant: double2 [Px/2+1][Pz/2+1][Py/2+1]  (k^ at kx, kz, ky)
  *   data spectrum: complex T [Px/2+1][Pz][Py] (f^ at kx, kz, ky; kx <= Px/2)
  *   features: float[65] = log10(E_b/mean E + 1e-30), b < 64, then log10(delta/||F||)
- *   energy: double[64] radial energies E_b over the full spectrum. */
+ *   energy: double[64] E_b = sum of |f^|^2 over the full spectrum's points of level b,
+ *     the level of a point being the number of thresholds s_max 10^((j - 64)/4),
+ *     j = 1..63, that its |k^|^2 reaches (quarter decades below s_max; the
+ *     Tikhonov filter acts on a point through |k^|^2 alone). */
 fr3d_status fr3d_get_octant(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
 fr3d_status fr3d_get_data_spectrum(fr3d_ctx* ctx, void* out_dev, int64_t bytes);
 fr3d_status fr3d_get_features(fr3d_ctx* ctx, float* feat_dev, double* energy_dev);

@@ -18,7 +18,7 @@ Modules
   tikhonov    kernel spectrum, spectral Tikhonov estimator, dense Tikhonov
   discrepancy regularisation-parameter choice by the discrepancy principle
   recovery    xi = zeta / V0 and c (Algorithm 1, step 4)
-  features    radial spectral-energy features for the alpha predictor
+  features    spectral-energy features for the alpha predictor (per kernel-spectrum level)
   mlp         FP64 reference of the alpha-predictor MLP with BF16 emulation
   synth       synthetic data F = A(xi V0) + scaled noise
 """

@@ -1,16 +1,22 @@
-"""Features of the alpha predictor: radial spectral energy of the padded data.
+"""Features of the alpha predictor: spectral energy of the padded data by the
+level of the kernel's spectrum.
 
 Oracle (test infrastructure only).  The paper has no predictor; this is the
 definition the HIP path is checked against.
 
-For every point k of the P^3 spectrum, with signed frequencies
-m_i = k_i (k_i <= P_i/2) or k_i - P_i, the normalised radius is
-rho = sqrt(u/3), u = sum_i (2 m_i / P_i)^2 in [0, 3], and the bin is
-b = min(63, floor(64 rho)).  The bin is decided exactly in integers:
-b is the largest b <= 63 with 3 b^2 L <= 4096 U, where L = lcm(P)^2 and
-U = u L = sum_i 4 m_i^2 (lcm(P)/P_i)^2.
+The Tikhonov filter acts on each spectral point through s = |k^|^2 alone
+(Sec. 3-4: u^ = conj(k^) f^ / (s + alpha)), so the features sort the data's
+energy by that quantity.  With s_max = max s over the P^3 box, the level of
+a point is
 
-E_b = sum over bin b of |f^(k)|^2 (f^ = DFT3 of the zero-padded data),
+    b = number of j in 1..63 with s >= s_max 10^((j - 64)/4),
+
+i.e. floor(4 log10(s / s_max)) + 64 clipped to [0, 63]: quarter-decade
+levels, b = 63 for the points within a quarter decade of s_max and b = 0 for
+s < s_max 1e-15.75 (zeros of the spectrum included).  The thresholds are
+fixed numbers, decided by comparison (no logarithm of s is taken).
+
+E_b = sum over level b of |f^(k)|^2 (f^ = DFT3 of the zero-padded data),
 x_b = log10(E_b / mean_b(E_b) + 1e-30) for b < 64 and x_64 = log10(delta/||F||).
 """
 from __future__ import annotations
@@ -22,33 +28,28 @@ import numpy as np
 NBINS = 64
 
 
-def _signed(p):
-    k = np.arange(p, dtype=np.int64)
-    return np.where(k <= p // 2, k, k - p)
+def thresholds(smax: float):
+    """s_max 10^((j - 64)/4) for j = 1..63, increasing."""
+    return np.array([smax * 10.0 ** ((j - 64) / 4.0) for j in range(1, NBINS)])
 
 
-def bin_index(pshape):
-    """Integer bin of every spectral point, shape pshape (z, y, x)."""
-    pz, py, px = pshape
-    lc = math.lcm(pz, py, px)
-    L = lc * lc
-    mz, my, mx = _signed(pz), _signed(py), _signed(px)
-    U = (4 * mz * mz * (lc // pz) ** 2)[:, None, None] + (4 * my * my * (lc // py) ** 2)[None, :, None] \
-        + (4 * mx * mx * (lc // px) ** 2)[None, None, :]
-    b = np.floor(64.0 * np.sqrt(U / (3.0 * L))).astype(np.int64)
-    b = np.where(3 * (b + 1) ** 2 * L <= 4096 * U, b + 1, b)
-    b = np.where(3 * b * b * L > 4096 * U, b - 1, b)
-    return np.minimum(b, NBINS - 1)
+def level_index(s, smax: float):
+    """Level of every spectral point (same shape as s)."""
+    return np.searchsorted(thresholds(smax), np.asarray(s, dtype=np.float64), side="right").astype(np.int64)
 
 
-def radial_energy(fhat):
-    b = bin_index(fhat.shape)
-    e = (fhat.real ** 2 + fhat.imag ** 2)
+def level_energy(fhat, s, smax: float):
+    b = level_index(s, smax)
+    e = fhat.real ** 2 + fhat.imag ** 2
     return np.bincount(b.ravel(), weights=e.ravel(), minlength=NBINS)[:NBINS]
 
 
-def features(F_pad_hat, delta, F_norm):
-    E = radial_energy(F_pad_hat)
+def features(F_pad_hat, delta, F_norm, s, smax=None):
+    """The 65 features of data whose padded spectrum is F_pad_hat, for a
+    kernel with s = |k^|^2 on the same box (s_max its maximum by default)."""
+    if smax is None:
+        smax = float(np.max(s))
+    E = level_energy(F_pad_hat, s, smax)
     x = np.empty(NBINS + 1)
     x[:NBINS] = np.log10(E / E.mean() + 1e-30)
     x[NBINS] = math.log10(delta / F_norm)

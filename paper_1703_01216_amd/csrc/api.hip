@@ -211,6 +211,29 @@ __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long lon
 }
 
 // Per-block maxima of |k^|^2 over the octant (it covers every value of |k^|).
+// Kernel-spectrum levels of the predictor features: for octant entry
+// (kx, mz, my) (octant layout [kx][mz][my]) the number of thresholds thr[j]
+// (increasing) with |k^|^2 >= thr[j], written to level[kx][my][mz].
+struct LevelThr {
+  double t[63];
+};
+__global__ void k_level_table(const double2* __restrict__ oct, int kxn, int oz, int oy, LevelThr thr,
+                              uint8_t* __restrict__ level) {
+  const long long n = (long long)kxn * oz * oy;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const int my = (int)(i % oy), mz = (int)((i / oy) % oz), kx = (int)(i / ((long long)oy * oz));
+    const double2 k = oct[i];
+    const double s = k.x * k.x + k.y * k.y;
+    int lo = 0, hi = 63;  // count of thresholds <= s, by bisection
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (thr.t[mid] <= s) lo = mid + 1;
+      else hi = mid;
+    }
+    level[((size_t)kx * oy + my) * oz + mz] = (uint8_t)lo;
+  }
+}
+
 // The octant rounded to FP32 (each component to nearest).
 __global__ void k_round_octant(const double2* __restrict__ oct, long long n, float2* __restrict__ o32) {
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
@@ -340,7 +363,8 @@ struct fr3d_ctx {
   size_t esz = 4;
   double smax = 0;
   double2* oct = nullptr;
-  float2* oct32 = nullptr;  // FP32 contexts: the octant rounded to FP32 once (the FP32 filter's operand)
+  float2* oct32 = nullptr;
+  uint8_t* level = nullptr;  // kernel-spectrum level of every octant point, [kx][my][mz]  // FP32 contexts: the octant rounded to FP32 once (the FP32 filter's operand)
   // per-frequency z-systems (Algorithm 1 as in Sec. 5) instead of the 3D embedding
   bool layered = false;
   double *lay_kt = nullptr, *lay_V = nullptr, *lay_lam = nullptr;
@@ -491,6 +515,7 @@ fr3d_status alloc_lane_geometry(fr3d_ctx* c, Lane& L) {
 void free_geometry(fr3d_ctx* c) {
   dfree(c->oct);
   dfree(c->oct32);
+  dfree(c->level);
   dfree(c->lay_kt);
   dfree(c->lay_V);
   dfree(c->lay_lam);
@@ -588,11 +613,6 @@ int gap_default(int nz, int q) {
 BinGeom bin_geom(int px, int py, int pz) {
   BinGeom b;
   b.px = px; b.py = py; b.pz = pz;
-  long long l = std::lcm((long long)px, std::lcm((long long)py, (long long)pz));
-  b.fx = (l / px) * (l / px);
-  b.fy = (l / py) * (l / py);
-  b.fz = (l / pz) * (l / pz);
-  b.L3 = 3 * l * l;
   return b;
 }
 
@@ -629,6 +649,7 @@ FwdArgs fwd_args(fr3d_ctx* c, Lane& L, bool kernel) {
   a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
   a.kind = c->g.kind;
   a.bg = bin_geom(c->px, c->py, c->pz);
+  a.level = c->level;
   a.bins_part = L.bins_part;
   a.bins_out = L.energy;
   a.feat_out = L.feat;
@@ -1282,6 +1303,17 @@ fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc
   if (le != hipSuccess) return fail(c, FR3D_E_DEVICE, "kernel spectrum: %s", hipGetErrorString(le));
   c->smax = L0.scal_host[0];
   if (!(c->smax > 0) || !std::isfinite(c->smax)) return fail(c, FR3D_E_DEVICE, "kernel spectrum has no energy");
+  {
+    // levels of the kernel spectrum for the predictor features: thresholds
+    // s_max 10^((j - 64)/4), j = 1..63
+    LevelThr thr;
+    for (int j = 1; j < 64; ++j) thr.t[j - 1] = c->smax * std::pow(10.0, (j - 64) / 4.0);
+    HIPCHK(c, hipMalloc(&c->level, noct));
+    const unsigned nr = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 4096);
+    hipLaunchKernelGGL(k_level_table, dim3(nr), dim3(NT), 0, L0.stream, (const double2*)c->oct, c->kxn,
+                       c->pz / 2 + 1, c->py / 2 + 1, thr, c->level);
+    LCHK(c, hipGetLastError());
+  }
   if (c->esz == 4) {
     HIPCHK(c, hipMalloc(&c->oct32, noct * sizeof(float2)));
     const unsigned nr = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 4096);

@@ -3,8 +3,9 @@
 // (16x16x16 MFMA tiles, one wavefront per 16 batch rows or per 16x16 output
 // tile) and FP32 master weights updated by Adam.
 //
-// Inputs are the 65 spectral features of a data set (64 radial log-energy
-// bins and log10(delta/||F||)); they are standardised with stored mean and
+// Inputs are the 65 spectral features of a data set (64 log-energies of
+// the data per quarter-decade level of the kernel spectrum |k^|^2 / s_max,
+// and log10(delta/||F||)); they are standardised with stored mean and
 // deviation.  The output y is the standardised log10 alpha:
 // log10 alpha = t_mu + t_sigma * y.
 //

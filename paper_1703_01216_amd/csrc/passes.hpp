@@ -34,25 +34,11 @@ template <typename T, int P, int SH> struct TileC {
   static constexpr int C = (Tile<T, P>::C >> SH) > 0 ? (Tile<T, P>::C >> SH) : 1;
 };
 
-// Spectral-energy bin of a point (exact integer rule; see the feature oracle):
-// b = largest b <= 63 with 3 b^2 L <= 4096 U, U = sum 4 m_i^2 (l/P_i)^2, L = l^2.
+// Padded box of the predictor features' energies (Parseval normalisation,
+// half-spectrum weights).
 struct BinGeom {
   int px, py, pz;
-  long long fx, fy, fz;  // (l / P_i)^2
-  long long L3;          // 3 L
 };
-
-__device__ __forceinline__ int energy_bin(const BinGeom& g, int kx, int ky, int kz) {
-  const long long mx = kx <= g.px / 2 ? kx : kx - g.px;
-  const long long my = ky <= g.py / 2 ? ky : ky - g.py;
-  const long long mz = kz <= g.pz / 2 ? kz : kz - g.pz;
-  const long long U = 4 * (mx * mx * g.fx + my * my * g.fy + mz * mz * g.fz);
-  const long long U4 = 4096 * U;
-  int b = (int)(64.0f * sqrtf((float)U / (float)g.L3));  // estimate, corrected exactly below
-  if ((long long)(b + 1) * (b + 1) * g.L3 <= U4) b += 1;
-  if ((long long)b * b * g.L3 > U4) b -= 1;
-  return b < 63 ? b : 63;
-}
 
 struct FwdArgs {
   int nz_in, ny_in;   // rows of the x pass: nz_in planes of ny_in rows
@@ -66,6 +52,10 @@ struct FwdArgs {
   const double* ksrc; // generator mode: read the wrapped samples [Pz][Py][Px] from here instead
   // energy epilogue
   BinGeom bg;
+  // level of the kernel spectrum of every octant point, [kx][my][mz]
+  // (mz fastest): the number of thresholds s_max 10^((j - 64)/4), j = 1..63,
+  // that |k^|^2 reaches; a data point's energy goes to its level's bin
+  const uint8_t* level;
   double* bins_part;  // [64][z-pass workgroups]
   double* bins_out;   // [64] energies
   float* feat_out;    // [65] features

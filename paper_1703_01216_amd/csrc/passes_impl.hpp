@@ -156,8 +156,8 @@ __global__ __launch_bounds__(NT) void k_fy(const c2<T>* __restrict__ A, c2<T>* _
 
 // ============================================================ forward z pass
 // Complex transform along z of C consecutive ky-columns of one kx plane.
-// MODE 0 (data): n inputs, P outputs, fused radial-energy epilogue writing
-// per-workgroup bin partials.  MODE 1 (kernel spectrum): P inputs, only
+// MODE 0 (data): n inputs, P outputs, fused energy epilogue writing
+// per-workgroup partials of the energy per kernel-spectrum level.  MODE 1 (kernel spectrum): P inputs, only
 // kz <= P/2 and ky <= Py/2 stored (the octant).
 // Slot of a forward z workgroup's bin partials (the grid is a multiple of
 // 8 workgroups): workgroups of one XCD (w mod 8) fill adjacent slots, so each
@@ -221,6 +221,10 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   if constexpr (MODE == 0) {
     c2<T>* dst = S + (size_t)kx * P * py;
     const double w = (kx == 0 || 2 * kx == a.bg.px) ? 1.0 : 2.0;
+    constexpr int oz = P / 2 + 1;
+    const int oy = py / 2 + 1;
+    // the kernel-spectrum level of (kx, ky, kz): the octant entry (kx, |ky|, |kz|)
+    const uint8_t* lev = a.level + (size_t)kx * oy * oz;
     int cur = -1;
     double acc = 0.0;
     auto visit = [&](int kz, int col) {
@@ -228,7 +232,8 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       if (ky >= py) return;
       const c2<T> u = lds[kz * LD + col];
       dst[(size_t)kz * py + ky] = u;
-      const int b = energy_bin(a.bg, kx, ky, kz);
+      const int my = ky <= py / 2 ? ky : py - ky, mz = kz <= P / 2 ? kz : P - kz;
+      const int b = lev[(size_t)my * oz + mz];
       if (b != cur) {
         if (cur >= 0) atomicAdd(&bins[cur], acc);
         cur = b;
@@ -237,38 +242,25 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       acc += w * ((double)u.x * u.x + (double)u.y * u.y);
     };
     if constexpr (C <= NT && NT % C == 0) {
-      // each thread walks a run of consecutive kz in one column, so its bin
-      // changes rarely and few LDS atomics are needed.  A point's bin is
-      // floor(sqrt(4096 U / 3L)) capped at 63 (the rule of energy_bin),
-      // taken from an FP32 estimate: q = 4096 U / 3L <= 4096 and a few
-      // roundings of 6e-8 relative keep sqrt(q) within 2e-5 of its value,
-      // so the floor is exact unless sqrt(q) lies within 1e-4 of an
-      // integer; there the rule is applied exactly in FP64 (4096 U and
-      // b^2 3L are integers below 2^36).  No branch on the common path and
-      // no table in LDS.
+      // each thread walks a run of consecutive kz in one column (one row of
+      // the level table, read as consecutive bytes), so its bin changes
+      // rarely and few LDS atomics are needed
       constexpr int RPC = C * P / NT;
       const int col = tid % C, k0 = (tid / C) * RPC;
       const int ky = ky0 + col;
       if (ky < py) {
-        const long long mx = kx <= a.bg.px / 2 ? kx : kx - a.bg.px;
-        const long long my = ky <= a.bg.py / 2 ? ky : ky - a.bg.py;
-        const double cxy16 = 16384.0 * (double)(mx * mx * a.bg.fx + my * my * a.bg.fy);
-        const double fz16 = 16384.0 * (double)a.bg.fz, L3 = (double)a.bg.L3;
-        const float cxy16f = (float)cxy16, fz16f = (float)fz16, invL3f = (float)(1.0 / L3);
+        const uint8_t* lrow = lev + (size_t)(ky <= py / 2 ? ky : py - ky) * oz;
+        uint8_t lv[RPC];
+#pragma unroll
+        for (int j = 0; j < RPC; ++j) {
+          const int kz = k0 + j;
+          lv[j] = lrow[kz <= P / 2 ? kz : P - kz];
+        }
         for (int j = 0; j < RPC; ++j) {
           const int kz = k0 + j;
           const c2<T> u = lds[kz * LD + col];
           dst[(size_t)kz * py + ky] = u;
-          const int mz = kz <= a.bg.pz / 2 ? kz : kz - a.bg.pz;
-          const float sq = __builtin_amdgcn_sqrtf(fmaf((float)(mz * mz), fz16f, cxy16f) * invL3f);
-          int b = (int)sq;
-          const float fr = sq - (float)b;
-          if (fr < 1e-4f || fr > 0.9999f) {
-            const double U4 = fma((double)(mz * mz), fz16, cxy16);
-            b += (double)((b + 1) * (b + 1)) * L3 <= U4 ? 1 : 0;
-            b -= (double)(b * b) * L3 > U4 ? 1 : 0;
-          }
-          b = b < 63 ? b : 63;
+          const int b = lv[j];
           if (b != cur) {
             if (cur >= 0) atomicAdd(&bins[cur], acc);
             cur = b;
@@ -795,7 +787,7 @@ static __global__ __launch_bounds__(NT) void k_norm_final_k(InvArgs a, int nblk)
   if (threadIdx.x == 0) ctrl_advance_k(a.ctrl, r2, z2);
 }
 
-// Radial energies and predictor features from the z pass's per-workgroup bin
+// Level energies and predictor features from the z pass's per-workgroup bin
 // partials: workgroup b sums bin b over all partials in a fixed order; the
 // last workgroup forms x_b = log10(E_b / mean E + 1e-30) and
 // x_64 = log10(delta / ||F||) with ||F||^2 = sum E / (Px Py Pz) (Parseval).

@@ -42,3 +42,22 @@ def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_features(g: Geom, F, delta, margin=1e-9):
+    """The oracle's predictor features of data F on the geometry's sampled
+    kernel, and the number of spectral points whose |k^|^2 lies within
+    `margin` (relative) of a level threshold: those are the only points whose
+    level two FP64 spectra of the kernel may decide differently."""
+    from oracle import features
+    from oracle.geometry import sample_kernel
+    from oracle.operator import pad
+    khat = np.fft.fftn(sample_kernel(g))
+    s = (khat * khat.conj()).real
+    smax = float(s.max())
+    x, E = features.features(np.fft.fftn(pad(g, np.asarray(F, dtype=np.float64))), delta,
+                             float(np.linalg.norm(F)), s, smax)
+    thr = features.thresholds(smax)
+    idx = np.clip(np.searchsorted(thr, s.ravel()), 1, len(thr) - 1)
+    near = np.minimum(np.abs(s.ravel() / thr[idx - 1] - 1.0), np.abs(s.ravel() / thr[idx] - 1.0)) < margin
+    return x, E, int(near.sum())

@@ -12,11 +12,10 @@ import math
 import numpy as np
 import pytest
 
-from oracle import discrepancy, features, mlp, tikhonov
+from oracle import discrepancy, mlp, tikhonov
 from oracle.geometry import sample_kernel
-from oracle.operator import pad
 
-from gpu_helpers import geom, instance, rel_l2
+from gpu_helpers import geom, instance, oracle_features, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -140,7 +139,8 @@ def test_seed_matches_oracle_network(fr3d):
     wide = dict(accept_lo=0.0, accept_hi=1e300, log10_alpha_lo=-60.0, log10_alpha_hi=60.0)
     rep = c.solve_discrepancy(z, use_predictor=1, **wide)
     assert rep["n_evals"] == 1 and rep["flags"] == 0
-    x, _ = features.features(np.fft.fftn(pad(g, d["F"])), d["delta"], np.linalg.norm(d["F"]))
+    x, _, near = oracle_features(g, d["F"], d["delta"])
+    assert near == 0
     x = np.asarray(x, dtype=np.float64)
     yo, _ = mlp.forward(p32, x[None, :], bf16=True)
     assert math.log10(rep["alpha"]) == pytest.approx(-4.0 + 1.5 * float(yo[0]), abs=2e-3)
@@ -302,3 +302,33 @@ def test_seeded_search_matches_rule_fp64(fr3d, bias, snap):
     assert rep["flags"] == ref["flags"]
     assert rep["n_evals"] == ref["n_evals"]
     assert rep["alpha"] == pytest.approx(ref["alpha"], rel=1e-12)
+
+
+@pytest.mark.parametrize("bias,ratio", [(-3.0, 0.25), (-6.5, 0.3), (-1.0, 1.0)])
+def test_seeded_secant_slope_ratio_fp32(fr3d, bias, ratio):
+    # FP32 transforms: the whole-box slope comes from the FP32 filter's
+    # residual factors, so the steps need not match the FP64 rule point for
+    # point; the answer must meet the rule (r/delta inside the window by the
+    # oracle's FP64 residual at the device's alpha) and zeta must agree with
+    # the oracle there
+    g = geom(16, 16, 16)
+    d = instance(g, 72, 0.02)
+    c = fr3d.Context()
+    c.load_kernel(16, 16, 16, precision=32)
+    p = mlp.init_params(14)
+    for k in ("W1", "W2", "w3"):
+        p[k] = p[k] * 0.0
+    p["b3"][:] = bias
+    c.predictor_set(flat_params(p), identity_norm())
+    F = torch.tensor(d["F"], dtype=torch.float32, device="cuda")
+    c.set_data(F, d["delta"])
+    z = torch.empty_like(F)
+    tol = 1e-4
+    rep = c.solve_discrepancy(z, use_predictor=1, seed_slope=5.0, seed_slope_ratio=ratio, tol=tol,
+                              accept_lo=1.0, accept_hi=1.0, max_steps=20)
+    print("fp32 secant", bias, ratio, "evals", rep["n_evals"], "flags", rep["flags"], flush=True)
+    assert rep["flags"] & 7 == 0
+    khat = np.fft.fftn(sample_kernel(g))
+    o = tikhonov.solve_spectral(g, khat, d["F"], rep["alpha"])
+    assert abs(o["r_norm"] / d["delta"] - 1.0) <= 2 * tol
+    assert rel_l2(host(z), o["zeta"]) < 1e-5

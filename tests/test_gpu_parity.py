@@ -9,11 +9,11 @@ import math
 import numpy as np
 import pytest
 
-from oracle import discrepancy, features, recovery, tikhonov
+from oracle import discrepancy, recovery, tikhonov
 from oracle.geometry import sample_kernel, v0
 from oracle.operator import forward_circulant, forward_direct, pad
 
-from gpu_helpers import geom, half_spectrum, instance, octant_from_full, rel_l2
+from gpu_helpers import geom, half_spectrum, instance, octant_from_full, oracle_features, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -90,16 +90,17 @@ def test_features(fr3d, shape, precision):
     delta = 0.03 * np.linalg.norm(Fh)
     c.set_data(Fd, delta)
     feat, en = c.get_features()
-    x, E = features.features(np.fft.fftn(pad(g, Fh)), delta, np.linalg.norm(Fh))
+    x, E, near = oracle_features(g, Fh, delta)
+    assert near == 0  # every point's level is decided the same way on both sides
     tol = 1e-12 if precision == 64 else 2e-6
     assert np.abs(host(en) - E).max() < tol * E.max()
     assert np.abs(host(feat) - x).max() < 1e-4
 
 
 def test_features_bench_geometry(fr3d):
-    # the radial-energy epilogue of the forward z pass at 128^3 -> 256^3
-    # (FP32, the tile variant the bench runs): every bin's energy and the
-    # features against the oracle's binning of the FP64 spectrum
+    # the energy epilogue of the forward z pass at 128^3 -> 256^3 (FP32, the
+    # tile variant the bench runs): every level's energy and the features
+    # against the oracle's levels of the FP64 spectrum
     g = geom(128, 128, 128)
     c = ctx_for(fr3d, g, 32)
     c.apply_tuning()
@@ -109,7 +110,8 @@ def test_features_bench_geometry(fr3d):
     delta = 0.03 * np.linalg.norm(Fh)
     c.set_data(Fd, delta)
     feat, en = c.get_features()
-    x, E = features.features(np.fft.fftn(pad(g, Fh)), delta, np.linalg.norm(Fh))
+    x, E, near = oracle_features(g, Fh, delta)
+    assert near == 0
     assert np.abs(host(en) - E).max() < 2e-6 * E.max()
     assert np.abs(host(feat) - x).max() < 1e-4
 

@@ -730,49 +730,66 @@ def test_synth_noise_level_exact():
 
 # ---------------------------------------------------------------- features
 
-def test_bin_index_exact_against_integer_sqrt():
-    for pshape in ((16, 16, 16), (12, 8, 24)):
-        b = features.bin_index(pshape)
-        lc = math.lcm(*pshape)
-        L = lc * lc
-        for kz in range(pshape[0]):
-            for ky in range(pshape[1]):
-                for kx in range(pshape[2]):
-                    m = [k if k <= p // 2 else k - p for k, p in zip((kz, ky, kx), pshape)]
-                    U = sum(4 * mi * mi * (lc // p) ** 2 for mi, p in zip(m, pshape))
-                    # largest bb with 3 bb^2 L <= 4096 U  <=>  bb = isqrt(4096 U / (3 L))
-                    bb = math.isqrt((4096 * U) // (3 * L))
-                    assert b[kz, ky, kx] == min(bb, 63)
-    # the corner (P/2, P/2, P/2) has rho = 1 and goes to the last bin
-    assert features.bin_index((16, 16, 16))[8, 8, 8] == 63
+def test_level_index_rule():
+    # level = floor(4 log10(s / s_max)) + 64 clipped to [0, 63], by comparison
+    # with the thresholds s_max 10^((j - 64)/4)
+    smax = 3.7
+    r = inputs.rng(21)
+    s = smax * 10.0 ** r.uniform(-18.0, 0.0, size=4000)
+    b = features.level_index(s, smax)
+    ref = np.clip(np.floor(4.0 * np.log10(s / smax)) + 64, 0, 63).astype(np.int64)
+    thr = features.thresholds(smax)
+    near = np.min(np.abs(s[:, None] / thr[None, :] - 1.0), axis=1) < 1e-9
+    assert np.array_equal(b[~near], ref[~near]) and (~near).sum() > 3900
+    # exact thresholds open their level; s_max and above go to 63, zero to 0
+    assert list(features.level_index(thr, smax)) == list(range(1, 64))
+    assert list(features.level_index(np.nextafter(thr, 0.0), smax)) == list(range(0, 63))
+    assert features.level_index(np.array([smax, 2 * smax, 0.0, 1e-300]), smax).tolist() == [63, 63, 0, 0]
+    assert len(thr) == 63 and np.all(np.diff(thr) > 0)
+    assert thr[-1] == pytest.approx(smax * 10 ** -0.25, rel=1e-15) and thr[0] == pytest.approx(smax * 10 ** -15.75, rel=1e-15)
+    # only s / s_max matters
+    assert np.array_equal(features.level_index(7.0 * s, 7.0 * smax), b)
 
 
-def test_radial_energy_parseval():
+def test_level_energy_parseval():
     g = Geom(8, 6, 4)
     F = inputs.rng(13).standard_normal(g.shape)
     fh = np.fft.fftn(pad(g, F))
-    E = features.radial_energy(fh)
+    khat = np.fft.fftn(sample_kernel(g))
+    s = (khat * khat.conj()).real
+    E = features.level_energy(fh, s, s.max())
     assert E.sum() == pytest.approx(np.prod(g.pshape) * np.sum(F * F), rel=1e-12)
+    # the sampled kernel spreads its spectrum over many levels
+    assert (features.level_index(s, s.max()) == 63).any() and len(np.unique(features.level_index(s, s.max()))) > 10
 
 
 def test_features_values_on_a_hand_built_spectrum():
-    # 8^3 spectrum with |f^|^2 = 4 at k = 0 (bin 0), 9 at k = (0,0,1) and at its mirror
-    # (0,0,7): radius sqrt(u/3) with u = (2/8)^2, 64 sqrt(1/48) = 9.24 -> bin 9, and 1 at
-    # the corner (4,4,4) (radius 1 -> bin 63).  Mean bin energy (4 + 18 + 1)/64;
-    # empty bins give log10(1e-30) = -30; x_64 = log10(delta/||F||).
+    # 8^3 spectrum with |f^|^2 = 4 at k = 0 where s = s_max = 1 (level 63),
+    # 9 at k = (0,0,1) and at (0,0,7) where s = 0.0125 (log10 -1.90 -> level
+    # 56), 1 at the corner (4,4,4) where s = 2e-16 (log10 -15.70 -> level 1);
+    # s = 1e-20 elsewhere (level 0, no energy).  Mean level energy
+    # (4 + 18 + 1)/64; empty levels give log10(1e-30) = -30;
+    # x_64 = log10(delta/||F||).
     fh = np.zeros((8, 8, 8), complex)
     fh[0, 0, 0] = 2.0
     fh[0, 0, 1] = 3.0
     fh[0, 0, 7] = 3.0j
     fh[4, 4, 4] = -1.0
-    x, E = features.features(fh, 0.5, 20.0)
+    s = np.full((8, 8, 8), 1e-20)
+    s[0, 0, 0] = 1.0
+    s[0, 0, 1] = s[0, 0, 7] = 0.0125
+    s[4, 4, 4] = 2e-16
+    x, E = features.features(fh, 0.5, 20.0, s)
     ref = np.full(65, -30.0)
-    ref[0] = math.log10(4 * 64 / 23)
-    ref[9] = math.log10(18 * 64 / 23)
-    ref[63] = math.log10(64 / 23)
+    ref[63] = math.log10(4 * 64 / 23)
+    ref[56] = math.log10(18 * 64 / 23)
+    ref[1] = math.log10(64 / 23)
     ref[64] = math.log10(0.025)
     assert np.max(np.abs(x - ref)) < 1e-13
-    assert E[0] == 4 and E[9] == 18 and E[63] == 1 and E.sum() == 23
+    assert E[63] == 4 and E[56] == 18 and E[1] == 1 and E.sum() == 23
+    # the identity kernel (s = 1 everywhere): all energy in the top level
+    x1, E1 = features.features(fh, 0.5, 20.0, np.ones((8, 8, 8)))
+    assert E1[63] == 23 and E1[:63].sum() == 0 and x1[63] == pytest.approx(math.log10(64))
 
 
 # ---------------------------------------------------------------- MLP reference
