@@ -58,11 +58,11 @@ PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
 # sources with this digest; see profiles/passes_256cube_traffic.md and
 # profiles/passes_512cube_traffic.md.
-MEASURED_TRAFFIC = {"digest": "59cdc3fe6427ff8a", "n": 128,
-                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.3e6, "fwd_z": 103.7e6,
+MEASURED_TRAFFIC = {"digest": "6fca2eb2a356a936", "n": 128,
+                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 108.2e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
-MEASURED_TRAFFIC_512 = {"digest": "59cdc3fe6427ff8a", "n": 256,
-                        "bytes": {"inv_z": 1230.0e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 817.2e6,
+MEASURED_TRAFFIC_512 = {"digest": "6fca2eb2a356a936", "n": 256,
+                        "bytes": {"inv_z": 1229.8e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 853.8e6,
                                   "fwd_y": 404.4e6, "fwd_x": 202.0e6}}
 
 
@@ -79,17 +79,19 @@ def pass_bytes(n, esz=4, shape=None):
     padded to P = 2n per axis: reads of the nonzero inputs plus writes of the
     kept outputs (complex = 2 esz; the Tikhonov filter reads the kernel
     spectrum's octant as complex of the same precision: the FP32 path its
-    FP32 rounding, the FP64 path the FP64 octant)."""
+    FP32 rounding, the FP64 path the FP64 octant; the forward z pass reads
+    the octant's byte table of kernel-spectrum levels for the features)."""
     nz, ny, nx = shape or (n, n, n)
     Pz, Py = 2 * nz, 2 * ny
     kx = nx + 1
     c = 2 * esz
     cells = nx * ny * nz
-    octant = kx * (Pz // 2 + 1) * (Py // 2 + 1) * c
+    noct = kx * (Pz // 2 + 1) * (Py // 2 + 1)
+    octant = noct * c
     return {
         "fwd_x": cells * esz + kx * nz * ny * c,
         "fwd_y": kx * nz * ny * c + kx * nz * Py * c,
-        "fwd_z": kx * nz * Py * c + kx * Pz * Py * c,
+        "fwd_z": kx * nz * Py * c + kx * Pz * Py * c + noct,
         "inv_z": kx * Pz * Py * c + octant + kx * nz * Py * 2 * c,
         "inv_y": kx * nz * Py * 2 * c + kx * nz * ny * 2 * c,
         "inv_x": kx * nz * ny * 2 * c + cells * esz,
