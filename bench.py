@@ -86,12 +86,12 @@ def pass_bytes(n, esz=4, shape=None):
     kx = nx + 1
     c = 2 * esz
     cells = nx * ny * nz
-    noct = kx * (Pz // 2 + 1) * (Py // 2 + 1)
-    octant = noct * c
+    octant = kx * (Pz // 2 + 1) * (Py // 2 + 1) * c
+    levels = kx * (Py // 2 + 1) * Pz  # byte table of kernel-spectrum levels, rows over all kz
     return {
         "fwd_x": cells * esz + kx * nz * ny * c,
         "fwd_y": kx * nz * ny * c + kx * nz * Py * c,
-        "fwd_z": kx * nz * Py * c + kx * Pz * Py * c + noct,
+        "fwd_z": kx * nz * Py * c + kx * Pz * Py * c + levels,
         "inv_z": kx * Pz * Py * c + octant + kx * nz * Py * 2 * c,
         "inv_y": kx * nz * Py * 2 * c + kx * nz * ny * 2 * c,
         "inv_x": kx * nz * ny * 2 * c + cells * esz,

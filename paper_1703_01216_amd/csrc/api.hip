@@ -213,11 +213,13 @@ __global__ void k_add_noise(T* __restrict__ F, const T* __restrict__ e, long lon
 // Per-block maxima of |k^|^2 over the octant (it covers every value of |k^|).
 // Kernel-spectrum levels of the predictor features: for octant entry
 // (kx, mz, my) (octant layout [kx][mz][my]) the number of thresholds thr[j]
-// (increasing) with |k^|^2 >= thr[j], written to level[kx][my][mz].
+// (increasing) with |k^|^2 >= thr[j], written to level[kx][my][kz] for
+// kz = mz and kz = pz - mz (rows over the whole kz range, so that a run of
+// consecutive kz is a run of consecutive bytes).
 struct LevelThr {
   double t[63];
 };
-__global__ void k_level_table(const double2* __restrict__ oct, int kxn, int oz, int oy, LevelThr thr,
+__global__ void k_level_table(const double2* __restrict__ oct, int kxn, int oz, int oy, int pz, LevelThr thr,
                               uint8_t* __restrict__ level) {
   const long long n = (long long)kxn * oz * oy;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
@@ -230,7 +232,9 @@ __global__ void k_level_table(const double2* __restrict__ oct, int kxn, int oz, 
       if (thr.t[mid] <= s) lo = mid + 1;
       else hi = mid;
     }
-    level[((size_t)kx * oy + my) * oz + mz] = (uint8_t)lo;
+    uint8_t* row = level + ((size_t)kx * oy + my) * pz;
+    row[mz] = (uint8_t)lo;
+    if (mz > 0 && mz < pz - mz) row[pz - mz] = (uint8_t)lo;
   }
 }
 
@@ -364,7 +368,7 @@ struct fr3d_ctx {
   double smax = 0;
   double2* oct = nullptr;
   float2* oct32 = nullptr;
-  uint8_t* level = nullptr;  // kernel-spectrum level of every octant point, [kx][my][mz]  // FP32 contexts: the octant rounded to FP32 once (the FP32 filter's operand)
+  uint8_t* level = nullptr;  // kernel-spectrum level per (kx, |ky|, kz), [kx][my][kz]  // FP32 contexts: the octant rounded to FP32 once (the FP32 filter's operand)
   // per-frequency z-systems (Algorithm 1 as in Sec. 5) instead of the 3D embedding
   bool layered = false;
   double *lay_kt = nullptr, *lay_V = nullptr, *lay_lam = nullptr;
@@ -1308,10 +1312,10 @@ fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc
     // s_max 10^((j - 64)/4), j = 1..63
     LevelThr thr;
     for (int j = 1; j < 64; ++j) thr.t[j - 1] = c->smax * std::pow(10.0, (j - 64) / 4.0);
-    HIPCHK(c, hipMalloc(&c->level, noct));
+    HIPCHK(c, hipMalloc(&c->level, (size_t)kxn * (c->py / 2 + 1) * c->pz));
     const unsigned nr = (unsigned)std::min<long long>(((long long)noct + NT - 1) / NT, 4096);
     hipLaunchKernelGGL(k_level_table, dim3(nr), dim3(NT), 0, L0.stream, (const double2*)c->oct, c->kxn,
-                       c->pz / 2 + 1, c->py / 2 + 1, thr, c->level);
+                       c->pz / 2 + 1, c->py / 2 + 1, c->pz, thr, c->level);
     LCHK(c, hipGetLastError());
   }
   if (c->esz == 4) {

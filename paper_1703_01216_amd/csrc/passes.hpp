@@ -52,8 +52,8 @@ struct FwdArgs {
   const double* ksrc; // generator mode: read the wrapped samples [Pz][Py][Px] from here instead
   // energy epilogue
   BinGeom bg;
-  // level of the kernel spectrum of every octant point, [kx][my][mz]
-  // (mz fastest): the number of thresholds s_max 10^((j - 64)/4), j = 1..63,
+  // level of the kernel spectrum per (kx, |ky|, kz), [kx][Py/2+1][Pz] (kz
+  // fastest): the number of thresholds s_max 10^((j - 64)/4), j = 1..63,
   // that |k^|^2 reaches; a data point's energy goes to its level's bin
   const uint8_t* level;
   double* bins_part;  // [64][z-pass workgroups]

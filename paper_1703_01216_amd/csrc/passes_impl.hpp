@@ -206,6 +206,22 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     const int ky = ky0 + e % C;
     v[i] = (PE::ok(e) && ky < py) ? src[(size_t)(e / C) * py + ky] : mk<T>(0, 0);
   }
+  // data mode, run layout (each thread one column's run of RPC consecutive
+  // kz): the feature levels of the run, loaded with the data so that their
+  // latency hides behind the transform, four per word
+  constexpr bool RUN = C <= NT && NT % C == 0 && (C * P / NT) % 4 == 0;
+  constexpr int RPC = RUN ? C * P / NT : 4;
+  uint32_t lvw[RPC / 4] = {};
+  if constexpr (MODE == 0 && RUN) {
+    const int ky = ky0 + tid % C, k0 = (tid / C) * RPC;
+    if (ky < py) {
+      // the table row of (kx, |ky|) over all kz: RPC consecutive bytes from k0
+      const uint32_t* lrow = reinterpret_cast<const uint32_t*>(
+          a.level + ((size_t)kx * (py / 2 + 1) + (ky <= py / 2 ? ky : py - ky)) * P + k0);
+#pragma unroll
+      for (int j = 0; j < RPC / 4; ++j) lvw[j] = lrow[j];
+    }
+  }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
   if (MODE == 0 && tid < 64) bins[tid] = 0.0;
 #pragma unroll
@@ -221,10 +237,8 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   if constexpr (MODE == 0) {
     c2<T>* dst = S + (size_t)kx * P * py;
     const double w = (kx == 0 || 2 * kx == a.bg.px) ? 1.0 : 2.0;
-    constexpr int oz = P / 2 + 1;
-    const int oy = py / 2 + 1;
-    // the kernel-spectrum level of (kx, ky, kz): the octant entry (kx, |ky|, |kz|)
-    const uint8_t* lev = a.level + (size_t)kx * oy * oz;
+    // the kernel-spectrum level of (kx, ky, kz): table row (kx, |ky|), entry kz
+    const uint8_t* lev = a.level + (size_t)kx * (py / 2 + 1) * P;
     int cur = -1;
     double acc = 0.0;
     auto visit = [&](int kz, int col) {
@@ -232,8 +246,8 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       if (ky >= py) return;
       const c2<T> u = lds[kz * LD + col];
       dst[(size_t)kz * py + ky] = u;
-      const int my = ky <= py / 2 ? ky : py - ky, mz = kz <= P / 2 ? kz : P - kz;
-      const int b = lev[(size_t)my * oz + mz];
+      const int my = ky <= py / 2 ? ky : py - ky;
+      const int b = lev[(size_t)my * P + kz];
       if (b != cur) {
         if (cur >= 0) atomicAdd(&bins[cur], acc);
         cur = b;
@@ -241,26 +255,18 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       }
       acc += w * ((double)u.x * u.x + (double)u.y * u.y);
     };
-    if constexpr (C <= NT && NT % C == 0) {
-      // each thread walks a run of consecutive kz in one column (one row of
-      // the level table, read as consecutive bytes), so its bin changes
-      // rarely and few LDS atomics are needed
-      constexpr int RPC = C * P / NT;
+    if constexpr (RUN) {
+      // each thread walks a run of consecutive kz in one column, so its bin
+      // changes rarely and few LDS atomics are needed
       const int col = tid % C, k0 = (tid / C) * RPC;
       const int ky = ky0 + col;
       if (ky < py) {
-        const uint8_t* lrow = lev + (size_t)(ky <= py / 2 ? ky : py - ky) * oz;
-        uint8_t lv[RPC];
 #pragma unroll
-        for (int j = 0; j < RPC; ++j) {
-          const int kz = k0 + j;
-          lv[j] = lrow[kz <= P / 2 ? kz : P - kz];
-        }
         for (int j = 0; j < RPC; ++j) {
           const int kz = k0 + j;
           const c2<T> u = lds[kz * LD + col];
           dst[(size_t)kz * py + ky] = u;
-          const int b = lv[j];
+          const int b = (int)((lvw[j >> 2] >> (8 * (j & 3))) & 255u);
           if (b != cur) {
             if (cur >= 0) atomicAdd(&bins[cur], acc);
             cur = b;
