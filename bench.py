@@ -13,12 +13,13 @@ recovery of c.
 Searches run on the same batch (config.modes):
   learned      -- the predictor fine-tuned on the GPU for this geometry on
                   untimed instances (calibrate.fine_tune), its seed refined by
-                  secant steps on ln(r/T), the first with the slope of the
+                  secant steps on ln(r/T) whose first step assumes the
+                  calibrated median slope (a seed next to the lower range end
+                  starts there); every point accepted when |r/delta - 1| <=
+                  1e-3 (the headline value)
+  learned_ratio -- the same with the first step's slope taken from the
                   whole-box residual at the seed (formed by the seed's own
-                  evaluation) times the calibrated ratio (a seed next to the
-                  lower range end starts there); every point accepted when
-                  |r/delta - 1| <= 1e-3 (the headline value)
-  learned_fixed -- the same with the calibrated median slope for the first step
+                  evaluation) times the calibrated ratio
   bisection    -- plain bisection over log10 alpha in [-8, 0] to |r/delta - 1| <= 1e-3
   learned_net  -- the shipped network alone (no fine-tuning), secant steps with
                   the median root slope of its training instances
@@ -58,11 +59,11 @@ PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
 # sources with this digest; see profiles/passes_256cube_traffic.md and
 # profiles/passes_512cube_traffic.md.
-MEASURED_TRAFFIC = {"digest": "6fca2eb2a356a936", "n": 128,
-                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 108.2e6,
+MEASURED_TRAFFIC = {"digest": "1aa1d63285639bc1", "n": 128,
+                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 112.3e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
-MEASURED_TRAFFIC_512 = {"digest": "6fca2eb2a356a936", "n": 256,
-                        "bytes": {"inv_z": 1229.8e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 853.8e6,
+MEASURED_TRAFFIC_512 = {"digest": "1aa1d63285639bc1", "n": 256,
+                        "bytes": {"inv_z": 1228.2e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 886.5e6,
                                   "fwd_y": 404.4e6, "fwd_x": 202.0e6}}
 
 
@@ -641,7 +642,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16, help="oracle processes of the CPU baseline")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay each lane's evaluation as a HIP graph")
-    ap.add_argument("--modes", default="learned,bisection,learned_fixed,learned_net,learned_w,bisection_w,kary16")
+    ap.add_argument("--modes", default="learned,bisection,learned_ratio,learned_net,learned_w,bisection_w,kary16")
     ap.add_argument("--calibrate", type=int, default=96,
                     help="instances (not timed) on which the network is fine-tuned for this geometry; 0: none")
     ap.add_argument("--fp64", type=int, default=1, help="solve the batch in FP64 too")
@@ -704,12 +705,16 @@ def main():
         net_tuned = ctx.predictor_get()
         sk = {k: cal[k] for k in ("seed_slope", "seed_snap_lo", "seed_slope_ratio")}
         print(f"[bench] fine-tuning for the geometry: {cal}", file=sys.stderr, flush=True)
-    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **sk, **tight),
+    # the headline: the fine-tuned seed, the first secant step with the fixed
+    # median slope.  With the level features the seed is accepted at once for
+    # most instances, and the whole-box slope (learned_ratio) would cost every
+    # seed evaluation its reduction for the few that take a step.
+    fixed = {**sk, "seed_slope_ratio": 0.0}
+    mode_opts = {"learned": fr3d.default_opts(use_predictor=1, **fixed, **tight),
                  "learned_net": fr3d.default_opts(use_predictor=1, seed_slope=train_slope, **tight),
-                 # the fine-tuned seed with the fixed median slope for the first step
-                 "learned_fixed": fr3d.default_opts(use_predictor=1, **{**sk, "seed_slope_ratio": 0.0}, **tight),
+                 "learned_ratio": fr3d.default_opts(use_predictor=1, **sk, **tight),
                  "bisection": fr3d.default_opts(**tight),
-                 "learned_w": fr3d.default_opts(use_predictor=1, **sk, **wide),
+                 "learned_w": fr3d.default_opts(use_predictor=1, **fixed, **wide),
                  "bisection_w": fr3d.default_opts(**wide)}
     for m in modes:
         if m.startswith("kary"):  # kary<K>: the K-candidate search
@@ -810,7 +815,7 @@ def main():
         print(f"[bench] layered: {out['config']['layered']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         net = net_tuned or net_base
-        net_arg = (net[0].astype("float64"), net[1].astype("float64"), sk) if net is not None else None
+        net_arg = (net[0].astype("float64"), net[1].astype("float64"), fixed) if net is not None else None
         cb = cpu_baseline(Fh, deltas[:n_cpu], net_arg, checks, workers=args.cpu_workers)
         res = cb.pop("precision_checks")
         out["precision"] = [dict(precision=c["precision"], index=c["index"], alpha=c["alpha"], **r)

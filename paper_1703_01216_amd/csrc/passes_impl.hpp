@@ -176,7 +176,11 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   using PE = Per<TOT>;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
-  __shared__ double bins[64];
+  // two copies of the 64 feature bins, for even and odd lanes: neighbouring
+  // lanes (neighbouring ky columns) mostly hit the same level, and their
+  // LDS atomics on one address serialise
+  __shared__ double bins2[2 * 64];
+  double* bins = bins2 + 64 * (threadIdx.x & 1);
   const int tid = threadIdx.x;
   const int py = a.py;
   int kx, tile;
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     }
   }
   for (int m = tid; m < P; m += NT) tw[m] = twg[m];
-  if (MODE == 0 && tid < 64) bins[tid] = 0.0;
+  if (MODE == 0 && tid < 2 * 64) bins2[tid] = 0.0;
 #pragma unroll
   for (int i = 0; i < PE::n; ++i) {
     const int e = tid + i * NT;
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
     if (cur >= 0) atomicAdd(&bins[cur], acc);
     __syncthreads();
     const int bid = blockIdx.x, nblk = gridDim.x;
-    if (tid < 64) a.bins_part[(size_t)tid * nblk + bins_slot(bid, nblk)] = bins[tid];
+    if (tid < 64) a.bins_part[(size_t)tid * nblk + bins_slot(bid, nblk)] = bins2[tid] + bins2[64 + tid];
   } else {
     const int oy = py / 2 + 1;
     c2<T>* dst = S + (size_t)kx * NOUT * oy;
