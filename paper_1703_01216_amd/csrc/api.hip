@@ -724,7 +724,7 @@ template <typename T> fr3d_status inverse(fr3d_ctx* c, Lane& L, int mode, T* out
   // forward pass's features and the next data set
   if (slope && mode == 0 && !c->layered && c->filt == 0 && L.kmax == 0) {
     a.slope_part = (double2*)L.bins_part;
-    if (!iz_slope_map<T>(c->pz, c->tile_sh[3], a) || (size_t)a.slope_n * 2 > c->bins_part_n * 64)
+    if (!iz_slope_map<T>(c->pz, c->tile_sh[3], a) || (size_t)a.slope_n * (NT / 64) * 2 > c->bins_part_n * 64)
       return fail(c, FR3D_E_INVALID, "z pass of length %d: no slope partials", c->pz);
   }
   if (mode == 0 && L.kmax > 0) {

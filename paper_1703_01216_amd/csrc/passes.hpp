@@ -87,11 +87,12 @@ struct InvArgs {
   // full-box residual (Parseval over the half spectrum); null: not formed
   double* full_part;
   // the seed evaluation of a secant search with a slope ratio (Tikhonov
-  // filter): per z-pass workgroup (sum w e^2 |f^|^2, sum w e^2 (1 - e) |f^|^2)
-  // over its columns, e = a / (s + a) the residual factor and w the
-  // half-spectrum weight; the x pass's final kernel forms the full-box slope
-  // from the entries of the workgroups that hold a tile.  Set for the seed's
-  // launch only; null otherwise.
+  // filter): per wave of each z-pass workgroup, [workgroup][NT / 64],
+  // (sum w e^2 |f^|^2, sum w e^2 (1 - e) |f^|^2) over its points,
+  // e = a / (s + a) the residual factor and w the half-spectrum weight; the
+  // x pass's final kernel forms the full-box slope from the entries of the
+  // workgroups that hold a tile.  Set for the seed's launch only; null
+  // otherwise.
   double2* slope_part;
   int slope_n;              // z-pass workgroups
   int slope_ntile;          // column tiles per kx plane of the z pass

@@ -556,14 +556,13 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     }
     if constexpr (MODE == 0 && !KM) {
       // the seed of a secant search with a slope ratio (the host passes
-      // slope_part for that launch only): the workgroup's partials, with the
-      // half-spectrum weight w
+      // slope_part for that launch only): each wave's partials, with the
+      // half-spectrum weight w (no LDS)
       if (a.slope_part && a.filt == 0) {
-        __shared__ double red[NT / 64];
         const double w = (kx == 0 || kx == a.kx_n - 1) ? 1.0 : 2.0;
-        const double A = block_sum<NT>((double)sa, red);
-        const double B = block_sum<NT>((double)sb, red);
-        if (tid == 0) a.slope_part[blockIdx.x] = make_double2(w * A, w * B);
+        const double A = wave_sum<double>((double)sa);
+        const double B = wave_sum<double>((double)sb);
+        if ((tid & 63) == 0) a.slope_part[(size_t)blockIdx.x * (NT / 64) + (tid >> 6)] = make_double2(w * A, w * B);
       }
     }
     __syncthreads();
@@ -695,7 +694,9 @@ __global__ __launch_bounds__(NT) void k_ix(const c4<T>* __restrict__ W2, T* __re
   using PE = Per<TOT>;
   __shared__ c2<T> lds[P * LD];
   __shared__ c2<T> tw[P];
-  __shared__ double red[NT / 64];
+  // the norm reduction's scratch lives in the twiddle table, unused after
+  // the transform (at 512 points a separate array would cost a workgroup per CU)
+  double* red = reinterpret_cast<double*>(tw);
   if (inv_idle(a)) return;
   const int cand = a.kmode ? (int)blockIdx.z : 0;  // candidate of a K-candidate step
   if (a.kmode) {
@@ -760,16 +761,20 @@ static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
   const double tz = block_sum<NT>(p.y, red);
   double sfull = -1.0;
   if (a.slope_part && a.filt == 0 && ctrl_wants_slope(a.ctrl)) {
-    // the entries of workgroups with a tile, each thread over a fixed stride
+    // the wave entries of workgroups with a tile, each thread over a fixed
+    // stride of workgroups
     double2 q = make_double2(0.0, 0.0);
     for (int w = threadIdx.x; w < a.slope_n; w += NT) {
       int kx, tile;
       const bool mine = a.slope_quad ? xcd_quad_map(w, a.kx_n, a.slope_ntile, kx, tile)
                                      : xcd_pair_map(w, a.kx_n, a.slope_ntile, kx, tile);
       if (mine) {
-        const double2 v = a.slope_part[w];
-        q.x += v.x;
-        q.y += v.y;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+          const double2 v = a.slope_part[(size_t)w * (NT / 64) + i];
+          q.x += v.x;
+          q.y += v.y;
+        }
       }
     }
     const double A = block_sum<NT>(q.x, red);
