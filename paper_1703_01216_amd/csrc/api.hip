@@ -58,16 +58,35 @@ __global__ void k_report(const Ctrl* c, fr3d_report* r) {
 
 // Recovery (Algorithm 1, step 4): xi = zeta / V0 and c = (1/c0^2 - xi)^(-1/2)
 // with the argument clamped at 1e-6/c0^2; per-block counts of clamped cells.
+// Grid-stride over the cells, the loads of U strides issued together (one
+// memory round trip per U cells of a thread; cells visited in the same order).
 template <typename T>
 __global__ void k_recover(const T* __restrict__ zeta, const T* __restrict__ V0, double inv_c02, double floor_,
                           T* __restrict__ c, long long n, double* part) {
+  constexpr int U = 4;
   __shared__ double red[NT / 64];
   double cl = 0.0;
-  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-    const double xi = (double)zeta[i] / (double)V0[i];
-    double arg = inv_c02 - xi;
-    if (arg < floor_) { arg = floor_; cl += 1.0; }
-    c[i] = (T)(1.0 / sqrt(arg));
+  const long long st = (long long)gridDim.x * NT;
+  for (long long i0 = (long long)blockIdx.x * NT + threadIdx.x; i0 < n; i0 += U * st) {
+    T zv[U], vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * st;
+      if (i < n) {
+        zv[u] = zeta[i];
+        vv[u] = V0[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * st;
+      if (i < n) {
+        const double xi = (double)zv[u] / (double)vv[u];
+        double arg = inv_c02 - xi;
+        if (arg < floor_) { arg = floor_; cl += 1.0; }
+        c[i] = (T)(1.0 / sqrt(arg));
+      }
+    }
   }
   cl = block_sum<NT>(cl, red);
   if (threadIdx.x == 0) part[blockIdx.x] = cl;

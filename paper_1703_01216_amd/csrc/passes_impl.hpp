@@ -811,7 +811,7 @@ static __global__ __launch_bounds__(NT) void k_bins_final(FwdArgs a, int nblk) {
   __shared__ int last;
   const int b = blockIdx.x;
   const double* row = a.bins_part + (size_t)b * nblk;
-  double s = strided_sum<double>(row, threadIdx.x, nblk, NT);
+  double s = strided_sum<double, 16>(row, threadIdx.x, nblk, NT);
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) {
     a.bins_out[b] = s;
