@@ -292,10 +292,14 @@ __global__ void k_full_part(const c2<T>* __restrict__ S, InvArgs a) {
   if (inv_idle(a)) return;
   const double aa = a.ctrl->alpha_abs;
   const int py = a.py, pz = a.pz, oy = py / 2 + 1, oz = pz / 2 + 1;
-  const long long n = (long long)a.kx_n * pz * py;
+  const int lg = spec_lg(sizeof(T), pz, py), ng = spec_ng(py, lg);
+  const long long n = (long long)a.kx_n * spec_plane(pz, py, lg);  // S in storage order
   double acc = 0.0;
   for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += (long long)gridDim.x * NT) {
-    const int ky = (int)(e % py), kz = (int)((e / py) % pz), kx = (int)(e / ((long long)py * pz));
+    const long long row = e >> lg;  // (kx, granule, kz)
+    const int ky = (int)(((row / pz) % ng) << lg) + (int)(e & ((1 << lg) - 1));
+    const int kz = (int)(row % pz), kx = (int)(row / ((long long)pz * ng));
+    if (ky >= py) continue;  // a partial last granule's unused columns
     const int mz = kz <= pz / 2 ? kz : pz - kz, my = ky <= py / 2 ? ky : py - ky;
     const double2 kk = a.oct[((size_t)kx * oz + mz) * oy + my];
     const double s = kk.x * kk.x + kk.y * kk.y;
@@ -323,6 +327,19 @@ __global__ void k_full_final(InvArgs a, int nblk) {
   double s = strided_sum<double>(a.full_part, threadIdx.x, nblk, NT);
   s = block_sum<NT>(s, red);
   if (threadIdx.x == 0) a.ctrl->r2_full = s * a.scale;
+}
+
+// The data spectrum in the standard layout [Kx][Pz][Py] from its column
+// granules (inspection only).
+template <typename T>
+__global__ void k_spec_untile(const c2<T>* __restrict__ S, c2<T>* __restrict__ out, int kxn, int pz, int py) {
+  const int lg = spec_lg(sizeof(T), pz, py);
+  const size_t plane = spec_plane(pz, py, lg);
+  const long long n = (long long)kxn * pz * py;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += (long long)gridDim.x * NT) {
+    const int ky = (int)(e % py), kz = (int)((e / py) % pz), kx = (int)(e / ((long long)py * pz));
+    out[e] = S[(size_t)kx * plane + spec_off(kz, ky, pz, lg)];
+  }
 }
 
 __global__ void k_max_parts(const double* __restrict__ part, int n, double* out) {
@@ -1257,7 +1274,7 @@ fr3d_status load_kernel_impl(fr3d_ctx* c, const fr3d_geom* g, const double* ksrc
   c->kxn = c->px / 2 + 1;
   c->esz = g->precision == 64 ? 8 : 4;
   const size_t kxn = c->kxn;
-  const size_t nS = kxn * c->pz * c->py;
+  const size_t nS = kxn * spec_plane(c->pz, c->py, spec_lg(c->esz, c->pz, c->py));  // column-granule layout
   const size_t nA = kxn * g->nz * g->ny, nB = kxn * g->nz * c->py;
   c->spec_bytes = nS * 2 * c->esz;
   c->work_bytes = (nA + nB) * 4 * c->esz;  // W1 + W2 (pairs) cover A + B
@@ -2195,8 +2212,24 @@ fr3d_status fr3d_get_singular_values(fr3d_ctx* c, double* out, int64_t bytes) {
 fr3d_status fr3d_get_data_spectrum(fr3d_ctx* c, void* out, int64_t bytes) {
   if (!c) return FR3D_E_INVALID;
   if (!need(c, true, false)) return FR3D_E_STATE;
-  if (!out || bytes < (int64_t)c->spec_bytes) return fail(c, FR3D_E_INVALID, "need %zu bytes", c->spec_bytes);
-  HIPCHK(c, hipMemcpyAsync(out, c->lanes[0].spec, c->spec_bytes, hipMemcpyDeviceToDevice, c->lanes[0].stream));
+  // the layered form's lateral spectrum as stored; the 3D spectrum in the
+  // standard layout [Kx][Pz][Py] (stored in column granules)
+  const size_t nb = c->layered ? c->spec_bytes : (size_t)c->kxn * c->pz * c->py * 2 * c->esz;
+  if (!out || bytes < (int64_t)nb) return fail(c, FR3D_E_INVALID, "need %zu bytes", nb);
+  Lane& L0 = c->lanes[0];
+  if (c->layered) {
+    HIPCHK(c, hipMemcpyAsync(out, L0.spec, nb, hipMemcpyDeviceToDevice, L0.stream));
+  } else {
+    const long long n = (long long)c->kxn * c->pz * c->py;
+    const unsigned g = (unsigned)std::min<long long>((n + NT - 1) / NT, 8192);
+    if (c->esz == 8)
+      hipLaunchKernelGGL(k_spec_untile<double>, dim3(g), dim3(NT), 0, L0.stream, (const double2*)L0.spec,
+                         (double2*)out, c->kxn, c->pz, c->py);
+    else
+      hipLaunchKernelGGL(k_spec_untile<float>, dim3(g), dim3(NT), 0, L0.stream, (const float2*)L0.spec,
+                         (float2*)out, c->kxn, c->pz, c->py);
+    LCHK(c, hipGetLastError());
+  }
   return FR3D_OK;
 }
 

@@ -6,7 +6,8 @@
 //   F, zeta      real  [nz][ny][nx]                 data on Y / estimate on R
 //   A  (x done)  c2    [Kx][nz][ny]     Kx = Px/2+1 real-to-complex along x
 //   B  (y done)  c2    [Kx][nz][Py]
-//   S  (spectrum)c2    [Kx][Pz][Py]     f^ for kx <= Px/2 (f is real)
+//   S  (spectrum)c2    [Kx][Py/G][Pz][G] f^ for kx <= Px/2 (f is real), in
+//                                       column granules (spec_lg below)
 //   O  (octant)  double2 [Kx][Pz/2+1][Py/2+1]   k^ (even in kx, ky; Hermitian in kz)
 //   W1 (z undone) c4   [Kx][nz][Py]     (u^, r^) pairs, z < nz only
 //   W2 (y undone) c4   [Kx][nz][ny]
@@ -33,6 +34,33 @@ template <typename T, int P> struct Tile {
 template <typename T, int P, int SH> struct TileC {
   static constexpr int C = (Tile<T, P>::C >> SH) > 0 ? (Tile<T, P>::C >> SH) : 1;
 };
+
+// Column granules of the spectrum S: the Py columns of a kx plane are cut
+// into granules of G = 2^lg consecutive ky, and a granule's rows kz = 0..Pz-1
+// are stored one after another, so f^(kx, kz, ky) sits at
+//   ((kx ng + ky / G) Pz + kz) G + ky mod G,   ng = ceil(Py / G).
+// G is the column count of the z passes' half tile (which divides every
+// z-pass tile width), at most the largest power of two <= Py: every z-pass
+// workgroup then reads or writes whole granules, i.e. contiguous blocks,
+// instead of short column segments at the row pitch.  Columns ky >= Py of a
+// last, partial granule are never written or read.
+__host__ __device__ inline int spec_lg(int esz, int pz, int py) {
+  int p2 = 1;
+  while (p2 < pz) p2 <<= 1;
+  int c1 = (esz == 4 ? 4096 : 2048) / p2;  // Tile<T, Pz>::C
+  c1 = c1 > 0 ? c1 : 1;
+  c1 = (c1 >> 1) > 0 ? (c1 >> 1) : 1;  // TileC<T, Pz, 1>::C
+  int lg = 0;
+  while ((2 << lg) <= py && (2 << lg) <= c1) ++lg;
+  return lg;
+}
+__host__ __device__ inline int spec_ng(int py, int lg) { return (py + (1 << lg) - 1) >> lg; }
+// Offset of (kz, ky) within a kx plane of S.
+__host__ __device__ inline size_t spec_off(int kz, int ky, int pz, int lg) {
+  return ((((size_t)(ky >> lg) * pz) + kz) << lg) + (ky & ((1 << lg) - 1));
+}
+// Elements of one kx plane of S (padding columns included).
+__host__ __device__ inline size_t spec_plane(int pz, int py, int lg) { return ((size_t)spec_ng(py, lg) * pz) << lg; }
 
 // Padded box of the predictor features' energies (Parseval normalisation,
 // half-spectrum weights).

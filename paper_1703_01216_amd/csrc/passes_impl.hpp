@@ -239,17 +239,30 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
   __syncthreads();
   tile_fft<T, P, C, LD, NT, true, -1, PV>(lds, tw, tid);
   if constexpr (MODE == 0) {
-    c2<T>* dst = S + (size_t)kx * P * py;
+    const int lg = spec_lg(sizeof(T), P, py);
+    c2<T>* dst = S + (size_t)kx * spec_plane(P, py, lg);
     const double w = (kx == 0 || 2 * kx == a.bg.px) ? 1.0 : 2.0;
     // the kernel-spectrum level of (kx, ky, kz): table row (kx, |ky|), entry kz
     const uint8_t* lev = a.level + (size_t)kx * (py / 2 + 1) * P;
+    // the tile's C columns are C / G whole granules, consecutive in S: one
+    // contiguous range, written in storage order (columns past Py skipped)
+    {
+      c2<T>* out = dst + (((size_t)(ky0 >> lg) * P) << lg);
+      const int gm = (1 << lg) - 1;
+#pragma unroll
+      for (int i = 0; i < (C * P + NT - 1) / NT; ++i) {
+        const int e = tid + i * NT;
+        if ((C * P) % NT != 0 && e >= C * P) break;
+        const int r = e >> lg, kz = r % P, col = ((r / P) << lg) + (e & gm);
+        if (ky0 + col < py) out[e] = lds[kz * LD + col];
+      }
+    }
     int cur = -1;
     double acc = 0.0;
     auto visit = [&](int kz, int col) {
       const int ky = ky0 + col;
       if (ky >= py) return;
       const c2<T> u = lds[kz * LD + col];
-      dst[(size_t)kz * py + ky] = u;
       const int my = ky <= py / 2 ? ky : py - ky;
       const int b = lev[(size_t)my * P + kz];
       if (b != cur) {
@@ -259,6 +272,7 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
       }
       acc += w * ((double)u.x * u.x + (double)u.y * u.y);
     };
+    // energies: a second read of the tile
     if constexpr (RUN) {
       // each thread walks a run of consecutive kz in one column, so its bin
       // changes rarely and few LDS atomics are needed
@@ -269,7 +283,6 @@ __global__ __launch_bounds__(NT) void k_fz(const c2<T>* __restrict__ B, c2<T>* _
         for (int j = 0; j < RPC; ++j) {
           const int kz = k0 + j;
           const c2<T> u = lds[kz * LD + col];
-          dst[(size_t)kz * py + ky] = u;
           const int b = (int)((lvw[j >> 2] >> (8 * (j & 3))) & 255u);
           if (b != cur) {
             if (cur >= 0) atomicAdd(&bins[cur], acc);
@@ -402,7 +415,8 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
   const int oz = P / 2 + 1, oy = py / 2 + 1;
-  const c2<T>* src = S + (size_t)kx * P * py;
+  const int lg = spec_lg(sizeof(T), P, py);
+  const c2<T>* src = S + (size_t)kx * spec_plane(P, py, lg);
   const KT* oc;
   if constexpr (K32) oc = a.oct32 + (size_t)kx * oz * oy;
   else oc = a.oct + (size_t)kx * oz * oy;
@@ -496,8 +510,8 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
     for (int i = 0; i < UPT; ++i) {
       const int p = j + TPC * i;  // rows p and P-p (p = 0: rows 0 and P/2)
       const int r1 = p == 0 ? P / 2 : P - p;
-      f0[i] = okc ? src[(size_t)p * py + ky] : mk<T>(0, 0);
-      f1[i] = okc ? src[(size_t)r1 * py + ky] : mk<T>(0, 0);
+      f0[i] = okc ? src[spec_off(p, ky, P, lg)] : mk<T>(0, 0);
+      f1[i] = okc ? src[spec_off(r1, ky, P, lg)] : mk<T>(0, 0);
       k[i] = okc ? oc[(size_t)p * oy + my] : k0;
     }
     if (j == 0 && okc) kmid = oc[(size_t)(P / 2) * oy + my];
@@ -509,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
       const bool ok = PE::ok(e) && ky < py;
       const int mz = kz <= P / 2 ? kz : P - kz;
       const int my = ky <= py / 2 ? ky : py - ky;
-      f0[i] = ok ? src[(size_t)kz * py + ky] : mk<T>(0, 0);
+      f0[i] = ok ? src[spec_off(kz, ky, P, lg)] : mk<T>(0, 0);
       k[i] = ok ? oc[(size_t)mz * oy + my] : k0;
     }
   }
