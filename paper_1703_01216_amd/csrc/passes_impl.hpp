@@ -351,11 +351,11 @@ __device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& 
   return !(h && tile == t);
 }
 
-// Half tiles (C ky columns: half of each 128 B line of f^): tiles 2m and
-// 2m + 1 share the lines of f^, and the mirrored pair (line pair L - 1 - m)
-// shares octant columns with them; the four run as workgroups w, w + 8,
-// w + 16, w + 24, i.e. on one XCD, so the second read of a line or of an
-// octant column hits that XCD's L2.  Each XCD takes a contiguous range of
+// Tiles whose octant row segment is shorter than a line: tiles 2m and 2m + 1
+// share the lines of the octant's rows, and the mirrored pair (line pair
+// L - 1 - m) shares octant columns with them; the four run as workgroups w,
+// w + 8, w + 16, w + 24, i.e. on one XCD, so the second read of a line or of
+// an octant column hits that XCD's L2.  Each XCD takes a contiguous range of
 // these groups in order: the octant line at the edge between neighbouring
 // groups (the mirrored columns are offset by one) is then read by the same
 // XCD in consecutive groups.
@@ -374,6 +374,14 @@ __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& 
   tile = 2 * (sub < 2 ? gi : m2) + (sub & 1);
   return tile < ntile;
 }
+
+// Workgroup map of an inverse z launch: quads for half tiles, and for full
+// tiles whose octant row segment (C entries of at most 8 B in FP32, 16 B in
+// FP64) is shorter than a 128 B line, so that the neighbouring tiles sharing
+// its lines run on one XCD; pairs otherwise.
+template <typename T, int P, int SH> struct IzQuad {
+  static constexpr bool value = SH >= 1 || TileC<T, P, 0>::C * 2 * (int)sizeof(T) < 128;
+};
 
 // K32: the FP32 Tikhonov-family filter reads the kernel spectrum as FP32
 // (a.oct32, the FP64 octant rounded once), the values it rounds to anyway.
@@ -409,8 +417,8 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
   int kx, tile;
-  const bool mine = SH == 0 ? xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile)
-                            : xcd_quad_map(blockIdx.x, a.kx_n, ntile, kx, tile);
+  const bool mine = IzQuad<T, P, SH>::value ? xcd_quad_map(blockIdx.x, a.kx_n, ntile, kx, tile)
+                                            : xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile);
   if (!mine) return;
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
@@ -973,7 +981,7 @@ template <typename T, int p, int SH> static inline dim3 iz_grid(const InvArgs& a
   const long long ntile = cdiv(a.py, C);
   const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);
   const long long ngroups = (long long)a.kx_n * (((ntile + 1) / 2 + 1) / 2);
-  return dim3(SH >= 1 ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));
+  return dim3(IzQuad<T, p, SH>::value ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));
 }
 
 template <typename T>
@@ -1018,7 +1026,7 @@ template <typename T> bool iz_slope_map(int P, int sh, InvArgs& a) {
       constexpr int SV = decltype(v)::value;                                                                     \
       a.slope_n = (int)iz_grid<T, p, SV & 3>(a).x;                                                               \
       a.slope_ntile = (int)cdiv(a.py, TileC<T, p, (SV & 3) >= 1 ? 1 : 0>::C);                                    \
-      a.slope_quad = (SV & 3) >= 1 ? 1 : 0;                                                                      \
+      a.slope_quad = IzQuad<T, p, SV & 3>::value ? 1 : 0;                                                        \
       return hipSuccess;                                                                                         \
     });                                                                                                          \
     return true;
