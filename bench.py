@@ -252,7 +252,7 @@ def workload3_section(torch, fr3d, n_inst=64, steps=2, warmup=1, graphs=(False, 
             with torch.cuda.stream(st):
                 c = fr3d.Context(0, stream=st)
                 c.load_kernel(nx, ny, nz, q=q, precision=32)
-                c.apply_tuning()
+                c.apply_tuning(batched=True)
                 V = torch.empty(shape, dtype=torch.float32, device="cuda")
                 c.source_potential(V)
                 xi = inputs.xi_torch(shape, r["inclusions"])
@@ -612,7 +612,7 @@ def fp64_section(torch, fr3d, Fs, deltas, net, learned_opts, bisect_opts, lanes,
     n = Fs[0].shape[0]
     c = fr3d.Context(0)
     c.load_kernel(n, n, n, precision=64)
-    c.apply_tuning()
+    c.apply_tuning(batched=True)
     c.set_lanes(lanes)
     c.predictor_set(*net)
     V = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
@@ -672,7 +672,7 @@ def main():
     n = args.n
     ctx = fr3d.Context(0)
     ctx.load_kernel(n, n, n, precision=32)
-    tuning = ctx.apply_tuning()
+    tuning = ctx.apply_tuning(batched=True)  # the headline and its kernels' single-lane timing
     ctx.set_lanes(args.lanes)
     ctx.set_graphs(bool(args.graphs))
     modes = args.modes.split(",")

@@ -426,24 +426,27 @@ class Context:
         g = self.geom
         return f"{2 * g.nx}x{2 * g.ny}x{2 * g.nz}/fp{g.precision}"
 
-    def apply_tuning(self, path: str = TUNING_PATH):
+    def apply_tuning(self, path: str = TUNING_PATH, batched: bool = False):
         """Tile variants from an autotuner cache (JSON {key: {pass name: shift}});
         returns the applied entry or None when the cache has nothing for this
-        geometry.  Without an entry for this exact padded box, each pass takes
-        its variant from the cube whose side is that pass's transform length
-        (the pass kernels are compiled per length)."""
+        geometry.  batched: prefer the entry tuned for solves of several lanes
+        at once (key + "/batch", autotune --batched) when there is one.
+        Without an entry for this exact padded box, each pass takes its
+        variant from the cube whose side is that pass's transform length (the
+        pass kernels are compiled per length)."""
         import json
         if not os.path.exists(path):
             return None
         cache = json.load(open(path))
-        entry = cache.get(self.tuning_key())
+        entry = (cache.get(self.tuning_key() + "/batch") if batched else None) or cache.get(self.tuning_key())
         if not entry:
             g = self.geom
             axis = {"fwd_x": 2 * g.nx, "inv_x": 2 * g.nx, "fwd_y": 2 * g.ny, "inv_y": 2 * g.ny,
                     "fwd_z": 2 * g.nz, "inv_z": 2 * g.nz}
             entry = {}
             for name, P in axis.items():
-                cube = cache.get(f"{P}x{P}x{P}/fp{g.precision}")
+                cube = (cache.get(f"{P}x{P}x{P}/fp{g.precision}/batch") if batched else None) or \
+                    cache.get(f"{P}x{P}x{P}/fp{g.precision}")
                 if cube and name in cube:
                     entry[name] = cube[name]
         for k, v in entry.items():

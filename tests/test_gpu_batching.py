@@ -168,7 +168,7 @@ def test_workload3_full_size(fr3d):
         for q in r["q"]:
             c = fr3d.Context()
             c.load_kernel(nx, ny, nz, q=q, precision=32)
-            c.apply_tuning()
+            c.apply_tuning(batched=True)  # as the bench's batched workload
             V = torch.empty(shape, dtype=torch.float32, device="cuda")
             c.source_potential(V)
             xi = torch.tensor(r["xi"], dtype=torch.float32, device="cuda")

@@ -1,10 +1,10 @@
 """Oracle parity of the exact kernel instances the measurements time.
 
 * The headline workload (128^3 grids padded to 256^3, FP32) with the tile
-  variants the autotuner picked for it (`Context.apply_tuning`, the entry of
-  the tuning cache that the benchmark applies): data spectrum, estimate at a
-  fixed alpha and at the search's alpha, element by element against the FP64
-  oracle.
+  variants the autotuner picked for it (`Context.apply_tuning`: the entry
+  tuned for batched solves, which the benchmark applies, and the single-lane
+  entry): data spectrum, estimate at a fixed alpha and at the search's alpha,
+  element by element against the FP64 oracle.
 * Transform length 192 (n = 96, radix plan 16 x 4 x 3) on every axis, cubic
   and anisotropic, FP32 and FP64, default and tuned tiles; the alternative
   radix plans of lengths 192, 384 and 512 on every axis.
@@ -73,19 +73,22 @@ def check_estimate(c, g, khat, Fh, alpha, zeta, rep, precision):
     return err, o
 
 
+@pytest.mark.parametrize("batched", [True, False], ids=["batch-tiles", "single-lane-tiles"])
 @pytest.mark.parametrize("index", [0, 1])
-def test_headline_workload_with_bench_tiles(fr3d, index):
+def test_headline_workload_with_bench_tiles(fr3d, index, batched):
     from paper_1703_01216_amd import inputs
-    say(f"[bench-config] 128^3 -> 256^3 instance {index}, tuned tiles")
+    say(f"[bench-config] 128^3 -> 256^3 instance {index}, tuned tiles (batched {batched})")
     inst = inputs.workload_instance(2, index)
     g = geom(128, 128, 128)
     d = synth.make_data(g, inst["xi"], inst["noise"], inst["delta_rel"])
     c = fr3d.Context()
     c.load_kernel(128, 128, 128, precision=32)
-    applied = c.apply_tuning()
+    applied = c.apply_tuning(batched=batched)
     with open(fr3d.TUNING_PATH) as fh:
         cache = json.load(fh)
-    assert applied == cache["256x256x256/fp32"]
+    # the bench applies the batch entry (its headline runs 8 lanes at once)
+    want = cache.get("256x256x256/fp32/batch") if batched else None
+    assert applied == (want or cache["256x256x256/fp32"])
     Fd = dev(d["F"], 32)
     Fh = host(Fd)
     c.set_data(Fd, d["delta"])
@@ -177,7 +180,7 @@ def test_batched_workload_items_against_oracle(fr3d, index):
     for q in r["q"]:
         c = fr3d.Context()
         c.load_kernel(nx, ny, nz, q=q, precision=32)
-        c.apply_tuning()
+        c.apply_tuning(batched=True)  # as the bench's batched workload
         V = torch.empty(shape, dtype=torch.float32, device="cuda")
         c.source_potential(V)
         xi = inputs.xi_torch(shape, r["inclusions"])
