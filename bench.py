@@ -57,14 +57,16 @@ CAL_FIRST = 100000  # first instance index of the seed calibration set (disjoint
 PASS_NAMES = ["fwd_x", "fwd_y", "fwd_z", "inv_z", "inv_y", "inv_x"]
 # HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the
 # plain-copy calibration factors 2.000 and 1.000), valid only for the pass
-# sources with this digest; see profiles/passes_256cube_traffic.md and
-# profiles/passes_512cube_traffic.md.
-MEASURED_TRAFFIC = {"digest": "58c1af79f32544e5", "n": 128,
-                    "bytes": {"inv_z": 152.8e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 112.1e6,
+# sources with this digest and the tile codes they were taken with; see
+# profiles/passes_256cube_traffic.md and profiles/passes_512cube_traffic.md.
+MEASURED_TRAFFIC = {"digest": "05ee041c09fd10ab", "n": 128,
+                    "tiles": {"fwd_x": 0, "fwd_y": 1, "fwd_z": 0, "inv_x": 0, "inv_y": 1, "inv_z": 0},
+                    "bytes": {"inv_z": 152.9e6, "inv_y": 101.5e6, "inv_x": 42.4e6, "fwd_z": 111.1e6,
                               "fwd_y": 50.8e6, "fwd_x": 25.4e6}}
-MEASURED_TRAFFIC_512 = {"digest": "58c1af79f32544e5", "n": 256,
+MEASURED_TRAFFIC_512 = {"digest": "05ee041c09fd10ab", "n": 256,
+                        "tiles": {"fwd_x": 0, "fwd_y": 9, "fwd_z": 0, "inv_x": 8, "inv_y": 9, "inv_z": 0},
                         "bytes": {"inv_z": 1216.8e6, "inv_y": 808.6e6, "inv_x": 337.0e6, "fwd_z": 884.1e6,
-                                  "fwd_y": 404.3e6, "fwd_x": 202.0e6}}
+                                  "fwd_y": 404.4e6, "fwd_x": 202.0e6}}
 
 
 def pass_source_digest():
@@ -515,11 +517,13 @@ def pass_table(timing, pb):
     return passes
 
 
-def roofline_of(passes, pb, traffic_table, n):
+def roofline_of(passes, pb, traffic_table, n, tiles):
     dom = max(passes, key=lambda k: passes[k]["total_ms"])
     ach = passes[dom]["GB_s"]
     traffic = None
-    if traffic_table and pass_source_digest() == traffic_table["digest"] and n == traffic_table["n"]:
+    # the counters hold for the kernels they were taken on: same sources, size and tile codes
+    if (traffic_table and pass_source_digest() == traffic_table["digest"] and n == traffic_table["n"]
+            and (tiles or {}).get(dom) == traffic_table["tiles"].get(dom)):
         traffic = traffic_table["bytes"].get(dom)
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": pb[dom],
@@ -565,7 +569,7 @@ def section_512(torch, fr3d, reps=8, alpha=1e-6):
     torch.cuda.empty_cache()
     pb = pass_bytes(n)
     passes = pass_table(timing, pb)
-    roof = roofline_of(passes, pb, MEASURED_TRAFFIC_512, n)
+    roof = roofline_of(passes, pb, MEASURED_TRAFFIC_512, n, tuning)
     roof["measured"] = (f"HIP events at kernel start/end, one lane, {reps} forward transforms and {reps} "
                         f"evaluations at alpha = {alpha:g}")
     return {"grid": n, "padded": 2 * n, "tile_shifts": tuning, "roofline": roof, "passes": passes}
@@ -738,7 +742,7 @@ def main():
     print(f"[bench] kernel timing section: {kt_el * 1e3:.1f} ms", file=sys.stderr, flush=True)
     pb = pass_bytes(n)
     passes = pass_table(timing, pb)
-    roofline = roofline_of(passes, pb, MEASURED_TRAFFIC, n)
+    roofline = roofline_of(passes, pb, MEASURED_TRAFFIC, n, tuning)
     roofline["measured"] = "HIP events at kernel start/end, one lane, bisection to 1e-3 over the batch"
     s512 = None
     if args.n512:

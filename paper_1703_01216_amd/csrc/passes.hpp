@@ -124,7 +124,6 @@ struct InvArgs {
   double2* slope_part;
   int slope_n;              // z-pass workgroups
   int slope_ntile;          // column tiles per kx plane of the z pass
-  int slope_quad;           // 1: the z pass maps workgroups by quads (else pairs) of tiles
 };
 
 // Whether an inverse-pass kernel of this launch has nothing to do; alpha:
@@ -169,7 +168,7 @@ hipError_t launch_iz(int P, int mode, const c2<T>* S, c4<T>* W1, const InvArgs& 
 template <typename T>
 hipError_t launch_iy(int P, const c4<T>* W1, c4<T>* W2, const InvArgs& a, const c2<T>* tw, const Launch& L);
 // The workgroup map of launch_iz's single-evaluation Tikhonov launch for
-// tile code sh, into a.slope_n, a.slope_ntile and a.slope_quad; false for an
+// tile code sh, into a.slope_n and a.slope_ntile; false for an
 // unsupported length.
 template <typename T>
 bool iz_slope_map(int P, int sh, InvArgs& a);

@@ -335,30 +335,16 @@ __device__ __forceinline__ float recipf(float x) {
 }
 
 // Octant reuse: rows kz and P-kz need the same octant entry (conjugated), so
-// each thread loads f^ for such a pair of rows and the octant entry once;
-// tiles t and ntile-1-t of a plane need mirrored octant columns, so they are
-// dispatched as consecutive workgroups of the same XCD (workgroups go to
-// XCDs round robin) and share that XCD's L2.
-__device__ __forceinline__ bool xcd_pair_map(int w, int nplane, int ntile, int& plane, int& tile) {
-  const int npair = (ntile + 1) / 2;
-  const int x = w & 7, s = w >> 3;
-  const int h = s & 1;
-  const int pidx = (s >> 1) * 8 + x;
-  plane = pidx / npair;
-  const int t = pidx % npair;
-  if (plane >= nplane) return false;
-  tile = h ? ntile - 1 - t : t;
-  return !(h && tile == t);
-}
-
-// Tiles whose octant row segment is shorter than a line: tiles 2m and 2m + 1
-// share the lines of the octant's rows, and the mirrored pair (line pair
-// L - 1 - m) shares octant columns with them; the four run as workgroups w,
-// w + 8, w + 16, w + 24, i.e. on one XCD, so the second read of a line or of
-// an octant column hits that XCD's L2.  Each XCD takes a contiguous range of
-// these groups in order: the octant line at the edge between neighbouring
-// groups (the mirrored columns are offset by one) is then read by the same
-// XCD in consecutive groups.
+// each thread loads f^ for such a pair of rows and the octant entry once.
+// Tiles 2m and 2m + 1 of a plane read neighbouring columns of the octant's
+// rows (the same 128 B lines when a tile's row segment is shorter than a
+// line) and the mirrored pair (tiles of line pair L - 1 - m) the mirrored
+// columns ky -> Py - ky; the four run as workgroups w, w + 8, w + 16, w + 24,
+// i.e. on one XCD (workgroups go to the XCDs round robin), so the second
+// read of a line or of an octant column hits that XCD's L2.  Each XCD takes
+// a contiguous range of these groups in order: the octant line at the edge
+// between neighbouring groups (the mirrored columns are offset by one) is
+// then read by the same XCD in consecutive groups.
 __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& plane, int& tile) {
   const int L = (ntile + 1) / 2, G = (L + 1) / 2;  // line pairs, groups per plane
   const int ngroups = nplane * G, per = (ngroups + 7) / 8;  // groups per XCD
@@ -374,14 +360,6 @@ __device__ __forceinline__ bool xcd_quad_map(int w, int nplane, int ntile, int& 
   tile = 2 * (sub < 2 ? gi : m2) + (sub & 1);
   return tile < ntile;
 }
-
-// Workgroup map of an inverse z launch: quads for half tiles, and for full
-// tiles whose octant row segment (C entries of at most 8 B in FP32, 16 B in
-// FP64) is shorter than a 128 B line, so that the neighbouring tiles sharing
-// its lines run on one XCD; pairs otherwise.
-template <typename T, int P, int SH> struct IzQuad {
-  static constexpr bool value = SH >= 1 || TileC<T, P, 0>::C * 2 * (int)sizeof(T) < 128;
-};
 
 // K32: the FP32 Tikhonov-family filter reads the kernel spectrum as FP32
 // (a.oct32, the FP64 octant rounded once), the values it rounds to anyway.
@@ -417,8 +395,7 @@ __global__ __launch_bounds__(NT) void k_iz(const c2<T>* __restrict__ S, c4<T>* _
   const int py = a.py;
   const int ntile = (py + C - 1) / C;
   int kx, tile;
-  const bool mine = IzQuad<T, P, SH>::value ? xcd_quad_map(blockIdx.x, a.kx_n, ntile, kx, tile)
-                                            : xcd_pair_map(blockIdx.x, a.kx_n, ntile, kx, tile);
+  const bool mine = xcd_quad_map(blockIdx.x, a.kx_n, ntile, kx, tile);
   if (!mine) return;
   const int tid = threadIdx.x;
   const int ky0 = tile * C;
@@ -788,8 +765,7 @@ static __global__ __launch_bounds__(NT) void k_norm_final(InvArgs a, int nblk) {
     double2 q = make_double2(0.0, 0.0);
     for (int w = threadIdx.x; w < a.slope_n; w += NT) {
       int kx, tile;
-      const bool mine = a.slope_quad ? xcd_quad_map(w, a.kx_n, a.slope_ntile, kx, tile)
-                                     : xcd_pair_map(w, a.kx_n, a.slope_ntile, kx, tile);
+      const bool mine = xcd_quad_map(w, a.kx_n, a.slope_ntile, kx, tile);
       if (mine) {
 #pragma unroll
         for (int i = 0; i < NT / 64; ++i) {
@@ -975,13 +951,12 @@ hipError_t launch_fz(int P, int mode, const c2<T>* B, c2<T>* S, const FwdArgs& a
   }
 }
 
-// grid of the inverse z pass: pairs of full tiles, or groups of four half tiles
+// grid of the inverse z pass: groups of four tiles (xcd_quad_map)
 template <typename T, int p, int SH> static inline dim3 iz_grid(const InvArgs& a) {
   const int C = TileC<T, p, SH >= 1 ? 1 : 0>::C;
   const long long ntile = cdiv(a.py, C);
-  const long long npairs = (long long)a.kx_n * ((ntile + 1) / 2);
   const long long ngroups = (long long)a.kx_n * (((ntile + 1) / 2 + 1) / 2);
-  return dim3(IzQuad<T, p, SH>::value ? 32 * cdiv(ngroups, 8) : 16 * cdiv(npairs, 8));
+  return dim3(32 * cdiv(ngroups, 8));
 }
 
 template <typename T>
@@ -1026,7 +1001,6 @@ template <typename T> bool iz_slope_map(int P, int sh, InvArgs& a) {
       constexpr int SV = decltype(v)::value;                                                                     \
       a.slope_n = (int)iz_grid<T, p, SV & 3>(a).x;                                                               \
       a.slope_ntile = (int)cdiv(a.py, TileC<T, p, (SV & 3) >= 1 ? 1 : 0>::C);                                    \
-      a.slope_quad = IzQuad<T, p, SV & 3>::value ? 1 : 0;                                                        \
       return hipSuccess;                                                                                         \
     });                                                                                                          \
     return true;
