@@ -99,11 +99,12 @@ def test_features(fr3d, shape, precision):
 
 def test_features_bench_geometry(fr3d):
     # the energy epilogue of the forward z pass at 128^3 -> 256^3 (FP32, the
-    # tile variant the bench runs): every level's energy and the features
-    # against the oracle's levels of the FP64 spectrum
+    # tile variants the bench runs: the entry tuned for batched solves):
+    # every level's energy and the features against the oracle's levels of
+    # the FP64 spectrum
     g = geom(128, 128, 128)
     c = ctx_for(fr3d, g, 32)
-    c.apply_tuning()
+    c.apply_tuning(batched=True)
     F = np.random.default_rng(5).standard_normal(g.shape)
     Fd = dev(F, 32)
     Fh = host(Fd)
