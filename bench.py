@@ -527,7 +527,7 @@ def roofline_of(passes, pb, traffic_table, n, tiles):
         traffic = traffic_table["bytes"].get(dom)
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": pb[dom],
-            "avg_launch_us": passes[dom]["avg_us"]}
+            "avg_launch_us": passes[dom]["avg_us"], "tile_code": (tiles or {}).get(dom)}
 
 
 def section_512(torch, fr3d, reps=8, alpha=1e-6):
